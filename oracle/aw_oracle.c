@@ -1,0 +1,515 @@
+/*
+ * aw_oracle.c -- plain FP64 CPU oracle.  TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test suite, the package smoke check and the benchmark's CPU-baseline
+ * leg may load this library.  It shares no code, header, table or constant
+ * generator with the HIP library; the two agree only through the seeded
+ * counter-based generator below, which each side implements on its own from
+ * the published definition of SplitMix64 (Steele, Lea & Flood, OOPSLA 2014).
+ *
+ * What it computes (arXiv:1107.4107):
+ *   - Model, eqs. 1-2 (section "Model for Arnold Diffusion"):
+ *         H(P, X) = |P|^2 / 2 + eps * Hp(X),
+ *         Hp(x, y, z) = cos x * cos y * (1 + cos 2z),  M = 3.
+ *   - Propagation by a symplectic map (section "Computational method"): the
+ *     paper uses a 6th-order symplectic integrator whose reference is not
+ *     recoverable.  The reading taken here is the closed-form triple-jump
+ *     composition built on the second-order drift-kick-drift (Stormer-Verlet)
+ *     step:  S2(t) = D(t/2) K(t) D(t/2),  S4(t) = S2(g1 t) S2(g0 t) S2(g1 t),
+ *     S6(t) = S4(d1 t) S4(d0 t) S4(d1 t), g1 = 1/(2 - 2^(1/3)), g0 = 1 - 2 g1,
+ *     d1 = 1/(2 - 2^(1/5)), d0 = 1 - 2 d1.  The first-order member kick-then-
+ *     drift (STDMAP) is the coupled standard map the model section names.
+ *     The composition is applied literally (no merging of adjacent drifts).
+ *   - Per-orbit observables: the finite-time mean velocity
+ *     V = [X(t + dt) - X(t)] / dt on the unwrapped coordinates (section "Main
+ *     results"), the momentum drift |P(t) - P(0)|^2 (model section), and a
+ *     tangent-vector growth L = ln |w_T| / |w_0| (the finite-time Lyapunov
+ *     exponent the conclusions name), renormalised after every step.
+ *   - Forward-mode derivatives of the step-averaged momentum drift
+ *     J = (1/T) sum_k |P_k - P_0|^2 with respect to the six initial
+ *     coordinates and eps (seven tangent columns).
+ *   - Histograms of per-orbit values over two key coordinates, and the
+ *     equal-area histogram of the direction of V on the momentum sphere (the
+ *     density F of the "Main results" section and Figs. 2-4).
+ *
+ * Everything is IEEE binary64, built with -ffp-contract=off; sin and cos are
+ * libm's, applied to the unwrapped coordinates.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_STDMAP 1
+#define OR_S2 2
+#define OR_S4 4
+#define OR_S6 6
+
+/* Number of doubles in a resumable per-orbit record:
+ * X[3] P[3] w[6] X0[3] P0[3] L Jsum steps. */
+#define OR_REC 21
+
+/* Rows of the per-orbit output. */
+#define OR_L 0
+#define OR_LAMBDA 1
+#define OR_CHI 2
+#define OR_VX 3
+#define OR_VY 4
+#define OR_VZ 5
+#define OR_DP2 6
+#define OR_J 7
+#define OR_DE 8
+#define OR_NOUT 9
+
+/* ------------------------------------------------------------------------ */
+/* Eq. 2 and its first and second derivatives, written from the formula.    */
+/* ------------------------------------------------------------------------ */
+
+static double hp_value(const double X[3])
+{
+    return cos(X[0]) * cos(X[1]) * (1.0 + cos(2.0 * X[2]));
+}
+
+/* g = grad Hp(X). */
+static void hp_gradient(const double X[3], double g[3])
+{
+    double cx = cos(X[0]), sx = sin(X[0]);
+    double cy = cos(X[1]), sy = sin(X[1]);
+    double c2z = cos(2.0 * X[2]), s2z = sin(2.0 * X[2]);
+    g[0] = -sx * cy * (1.0 + c2z);
+    g[1] = -cx * sy * (1.0 + c2z);
+    g[2] = -2.0 * cx * cy * s2z;
+}
+
+/* Hs = Hessian of Hp at X, as a full symmetric 3x3 matrix. */
+static void hp_hessian(const double X[3], double Hs[3][3])
+{
+    double cx = cos(X[0]), sx = sin(X[0]);
+    double cy = cos(X[1]), sy = sin(X[1]);
+    double c2z = cos(2.0 * X[2]), s2z = sin(2.0 * X[2]);
+    Hs[0][0] = -cx * cy * (1.0 + c2z);
+    Hs[1][1] = -cx * cy * (1.0 + c2z);
+    Hs[2][2] = -4.0 * cx * cy * c2z;
+    Hs[0][1] = sx * sy * (1.0 + c2z);
+    Hs[0][2] = 2.0 * sx * cy * s2z;
+    Hs[1][2] = 2.0 * cx * sy * s2z;
+    Hs[1][0] = Hs[0][1];
+    Hs[2][0] = Hs[0][2];
+    Hs[2][1] = Hs[1][2];
+}
+
+/* Eq. 1: total energy of s = (x, y, z, px, py, pz). */
+static double energy(const double s[6], double eps)
+{
+    double p2 = s[3] * s[3] + s[4] * s[4] + s[5] * s[5];
+    return 0.5 * p2 + eps * hp_value(s);
+}
+
+/* ------------------------------------------------------------------------ */
+/* One orbit with an optional set of tangent columns.                       */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double s[6];      /* x y z (unwrapped) px py pz */
+    int ncol;         /* number of tangent columns */
+    int eps_col;      /* index of the column that carries d/d eps, or -1 */
+    double w[7][6];   /* tangent columns (dX, dP) */
+    double eps;
+} orbit;
+
+/* Drift D(tau): X <- X + tau P, dX <- dX + tau dP. */
+static void drift(orbit *o, double tau)
+{
+    for (int a = 0; a < 3; a++)
+        o->s[a] = o->s[a] + tau * o->s[3 + a];
+    for (int c = 0; c < o->ncol; c++)
+        for (int a = 0; a < 3; a++)
+            o->w[c][a] = o->w[c][a] + tau * o->w[c][3 + a];
+}
+
+/* Kick K(tau): P <- P - tau eps grad Hp(X);
+ * dP <- dP - tau eps Hess(X) dX (- tau grad Hp(X) on the eps column). */
+static void kick(orbit *o, double tau)
+{
+    double g[3];
+    hp_gradient(o->s, g);
+    if (o->ncol > 0) {
+        double Hs[3][3];
+        hp_hessian(o->s, Hs);
+        for (int c = 0; c < o->ncol; c++) {
+            double hv[3];
+            for (int a = 0; a < 3; a++)
+                hv[a] = Hs[a][0] * o->w[c][0] + Hs[a][1] * o->w[c][1] + Hs[a][2] * o->w[c][2];
+            for (int a = 0; a < 3; a++) {
+                double d = tau * o->eps * hv[a];
+                if (c == o->eps_col)
+                    d = d + tau * g[a];
+                o->w[c][3 + a] = o->w[c][3 + a] - d;
+            }
+        }
+    }
+    for (int a = 0; a < 3; a++)
+        o->s[3 + a] = o->s[3 + a] - tau * o->eps * g[a];
+}
+
+static double tj_g1(void) { return 1.0 / (2.0 - cbrt(2.0)); }
+static double tj_d1(void) { return 1.0 / (2.0 - pow(2.0, 1.0 / 5.0)); }
+
+static void map_s2(orbit *o, double t)
+{
+    drift(o, t / 2.0);
+    kick(o, t);
+    drift(o, t / 2.0);
+}
+
+static void map_s4(orbit *o, double t)
+{
+    double g1 = tj_g1(), g0 = 1.0 - 2.0 * g1;
+    map_s2(o, g1 * t);
+    map_s2(o, g0 * t);
+    map_s2(o, g1 * t);
+}
+
+static void map_s6(orbit *o, double t)
+{
+    double d1 = tj_d1(), d0 = 1.0 - 2.0 * d1;
+    map_s4(o, d1 * t);
+    map_s4(o, d0 * t);
+    map_s4(o, d1 * t);
+}
+
+/* One application of the map of the chosen form with step h. */
+static int map_step(orbit *o, int form, double h)
+{
+    switch (form) {
+    case OR_STDMAP: kick(o, h); drift(o, h); return 0;
+    case OR_S2: map_s2(o, h); return 0;
+    case OR_S4: map_s4(o, h); return 0;
+    case OR_S6: map_s6(o, h); return 0;
+    default: return -1;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Resumable per-orbit record with one renormalised tangent vector.         */
+/* ------------------------------------------------------------------------ */
+
+void oracle_rec_init(const double s0[6], const double w0[6], double rec[OR_REC])
+{
+    for (int a = 0; a < 6; a++) rec[a] = s0[a];        /* X, P */
+    for (int a = 0; a < 6; a++) rec[6 + a] = w0[a];    /* w */
+    for (int a = 0; a < 6; a++) rec[12 + a] = s0[a];   /* X0, P0 */
+    rec[18] = 0.0;                                     /* L */
+    rec[19] = 0.0;                                     /* Jsum */
+    rec[20] = 0.0;                                     /* steps done */
+}
+
+/* Advance a record by nsteps map steps.  After each full step:
+ * nu = |w|, L += ln nu, w /= nu, Jsum += |P_k - P_0|^2. */
+int oracle_rec_advance(int form, double eps, double h, long nsteps, double rec[OR_REC])
+{
+    orbit o;
+    o.ncol = 1;
+    o.eps_col = -1;
+    o.eps = eps;
+    for (int a = 0; a < 6; a++) o.s[a] = rec[a];
+    for (int a = 0; a < 6; a++) o.w[0][a] = rec[6 + a];
+    double L = rec[18], Jsum = rec[19];
+    for (long k = 0; k < nsteps; k++) {
+        if (map_step(&o, form, h)) return -1;
+        double n2 = 0.0;
+        for (int a = 0; a < 6; a++) n2 = n2 + o.w[0][a] * o.w[0][a];
+        double nu = sqrt(n2);
+        L = L + log(nu);
+        for (int a = 0; a < 6; a++) o.w[0][a] = o.w[0][a] / nu;
+        double d2 = 0.0;
+        for (int a = 0; a < 3; a++) {
+            double d = o.s[3 + a] - rec[15 + a];
+            d2 = d2 + d * d;
+        }
+        Jsum = Jsum + d2;
+    }
+    for (int a = 0; a < 6; a++) rec[a] = o.s[a];
+    for (int a = 0; a < 6; a++) rec[6 + a] = o.w[0][a];
+    rec[18] = L;
+    rec[19] = Jsum;
+    rec[20] = rec[20] + (double)nsteps;
+    return 0;
+}
+
+/* End-of-run observables of a record (T = steps done):
+ * L, lambda = L/(T h), chi = L/ln(1 + T h), V = (X_T - X_0)/(T h),
+ * dP2 = |P_T - P_0|^2, J = Jsum/T, dE = H(s_T) - H(s_0). */
+void oracle_rec_finish(const double rec[OR_REC], double eps, double h, double out[OR_NOUT])
+{
+    double T = rec[20];
+    double th = T * h;
+    double L = rec[18];
+    out[OR_L] = L;
+    out[OR_LAMBDA] = L / th;
+    out[OR_CHI] = L / log(1.0 + th);
+    for (int a = 0; a < 3; a++) out[OR_VX + a] = (rec[a] - rec[12 + a]) / th;
+    double d2 = 0.0;
+    for (int a = 0; a < 3; a++) {
+        double d = rec[3 + a] - rec[15 + a];
+        d2 = d2 + d * d;
+    }
+    out[OR_DP2] = d2;
+    out[OR_J] = rec[19] / T;
+    double s0[6];
+    for (int a = 0; a < 6; a++) s0[a] = rec[12 + a];
+    out[OR_DE] = energy(rec, eps) - energy(s0, eps);
+}
+
+/* Ensemble run over SoA initial conditions ic[6][N] and tangent starts
+ * w0[6][N]; writes out[9][N] and, if state is non-NULL, the final
+ * X, P and unit tangent w into state[12][N].  OpenMP over orbits. */
+int oracle_ensemble(int form, double eps, double h, long T, long N,
+                    const double *ic, const double *w0, double *out, double *state,
+                    int nthreads)
+{
+    if (form != OR_STDMAP && form != OR_S2 && form != OR_S4 && form != OR_S6) return -1;
+    if (T < 1 || N < 0) return -1;
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads)
+#endif
+    for (long n = 0; n < N; n++) {
+        double s0[6], u[6], rec[OR_REC], o[OR_NOUT];
+        for (int a = 0; a < 6; a++) {
+            s0[a] = ic[a * N + n];
+            u[a] = w0[a * N + n];
+        }
+        oracle_rec_init(s0, u, rec);
+        oracle_rec_advance(form, eps, h, T, rec);
+        oracle_rec_finish(rec, eps, h, o);
+        for (int r = 0; r < OR_NOUT; r++) out[r * N + n] = o[r];
+        if (state)
+            for (int a = 0; a < 12; a++) state[a * N + n] = rec[a];
+    }
+    return 0;
+}
+
+/* Apply T map steps to a single state s[6] in place (no tangent). */
+int oracle_map(int form, double eps, double h, long T, double s[6])
+{
+    orbit o;
+    o.ncol = 0;
+    o.eps_col = -1;
+    o.eps = eps;
+    for (int a = 0; a < 6; a++) o.s[a] = s[a];
+    for (long k = 0; k < T; k++)
+        if (map_step(&o, form, h)) return -1;
+    for (int a = 0; a < 6; a++) s[a] = o.s[a];
+    return 0;
+}
+
+/* Jacobian of T map steps at s0: M[i*6 + j] = d s_T[i] / d s0[j];
+ * also returns the final state in sT. */
+int oracle_jacobian(int form, double eps, double h, long T, const double s0[6],
+                    double sT[6], double M[36])
+{
+    orbit o;
+    o.ncol = 6;
+    o.eps_col = -1;
+    o.eps = eps;
+    for (int a = 0; a < 6; a++) o.s[a] = s0[a];
+    for (int c = 0; c < 6; c++)
+        for (int a = 0; a < 6; a++) o.w[c][a] = (a == c) ? 1.0 : 0.0;
+    for (long k = 0; k < T; k++)
+        if (map_step(&o, form, h)) return -1;
+    for (int a = 0; a < 6; a++) sT[a] = o.s[a];
+    for (int i = 0; i < 6; i++)
+        for (int j = 0; j < 6; j++) M[i * 6 + j] = o.w[j][i];
+    return 0;
+}
+
+/* J = (1/T) sum_{k=1..T} |P_k - P_0|^2 and its exact first derivatives by
+ * forward mode: dJ[0..5] w.r.t. the initial (x, y, z, px, py, pz), dJ[6]
+ * w.r.t. eps.  dJ_c = (2/T) sum_k (P_k - P_0) . (dP_k,c - dP_0,c). */
+int oracle_J_grad(int form, double eps, double h, long T, const double s0[6],
+                  double *J, double dJ[7])
+{
+    orbit o;
+    o.ncol = 7;
+    o.eps_col = 6;
+    o.eps = eps;
+    for (int a = 0; a < 6; a++) o.s[a] = s0[a];
+    for (int c = 0; c < 7; c++)
+        for (int a = 0; a < 6; a++) o.w[c][a] = (a == c) ? 1.0 : 0.0;
+    double P0[3] = {s0[3], s0[4], s0[5]};
+    double dP0[7][3];
+    for (int c = 0; c < 7; c++)
+        for (int a = 0; a < 3; a++) dP0[c][a] = o.w[c][3 + a];
+    double Jsum = 0.0, dsum[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (long k = 0; k < T; k++) {
+        if (map_step(&o, form, h)) return -1;
+        for (int a = 0; a < 3; a++) {
+            double d = o.s[3 + a] - P0[a];
+            Jsum = Jsum + d * d;
+            for (int c = 0; c < 7; c++)
+                dsum[c] = dsum[c] + d * (o.w[c][3 + a] - dP0[c][a]);
+        }
+    }
+    *J = Jsum / (double)T;
+    for (int c = 0; c < 7; c++) dJ[c] = 2.0 * dsum[c] / (double)T;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Counter-based SplitMix64 (Steele, Lea & Flood 2014).                     */
+/* The sequential generator advances state += 0x9E3779B97F4A7C15 and        */
+/* returns mix(state); output number c (from 0) is therefore                */
+/* mix(seed + (c + 1) * gamma).                                             */
+/* ------------------------------------------------------------------------ */
+
+uint64_t oracle_splitmix64(uint64_t seed, uint64_t counter)
+{
+    uint64_t z = seed + (counter + 1u) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* Uniform double in [0, 1): the top 53 bits times 2^-53. */
+double oracle_u01(uint64_t seed, uint64_t counter)
+{
+    return (double)(oracle_splitmix64(seed, counter) >> 11) * 0x1.0p-53;
+}
+
+/* Orbit index list: idx[m] if idx is non-NULL, else m. */
+static long pick(const long *idx, long m) { return idx ? idx[m] : m; }
+
+/* GRID2 slice: s = base; s[a0] = lo0 + i * ((hi0 - lo0) / nx);
+ * s[a1] = lo1 + j * ((hi1 - lo1) / ny); orbit n = j * nx + i. */
+int oracle_ic_grid2(int a0, int a1, double lo0, double hi0, double lo1, double hi1,
+                    long nx, long ny, const double base[6], const long *idx, long M,
+                    double *ic)
+{
+    if (a0 < 0 || a0 > 5 || a1 < 0 || a1 > 5 || a0 == a1 || nx < 1 || ny < 1) return -1;
+    double d0 = (hi0 - lo0) / (double)nx;
+    double d1 = (hi1 - lo1) / (double)ny;
+    for (long m = 0; m < M; m++) {
+        long n = pick(idx, m);
+        long i = n % nx, j = n / nx;
+        for (int a = 0; a < 6; a++) ic[a * M + m] = base[a];
+        ic[a0 * M + m] = lo0 + (double)i * d0;
+        ic[a1 * M + m] = lo1 + (double)j * d1;
+    }
+    return 0;
+}
+
+/* Uniform box: s_k = lo_k + (hi_k - lo_k) * U(seed, 16 n + k). */
+void oracle_ic_box(const double lo[6], const double hi[6], uint64_t seed,
+                   const long *idx, long M, double *ic)
+{
+    for (long m = 0; m < M; m++) {
+        long n = pick(idx, m);
+        for (int k = 0; k < 6; k++)
+            ic[k * M + m] = lo[k] + (hi[k] - lo[k]) * oracle_u01(seed, 16u * (uint64_t)n + (uint64_t)k);
+    }
+}
+
+/* Tangent start: u_k = 2 U(seed, 16 n + k) - 1, w0 = u / |u|. */
+void oracle_w0(uint64_t seed, const long *idx, long M, double *w0)
+{
+    for (long m = 0; m < M; m++) {
+        long n = pick(idx, m);
+        double u[6], n2 = 0.0;
+        for (int k = 0; k < 6; k++) {
+            u[k] = 2.0 * oracle_u01(seed, 16u * (uint64_t)n + (uint64_t)k) - 1.0;
+            n2 = n2 + u[k] * u[k];
+        }
+        double nu = sqrt(n2);
+        for (int k = 0; k < 6; k++) w0[k * M + m] = u[k] / nu;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Images.                                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Serial histogram in orbit order.  Bin of item n along an axis:
+ * floor((a - lo) / (hi - lo) * W).  With closed_upper = 0 the range is
+ * half-open and items outside [0, W) are dropped; with closed_upper = 1 an
+ * item exactly at hi goes to the last bin.  Non-finite keys are dropped.
+ * counts[j*W + i] += 1 and sums[j*W + i] += v[n].  Returns the number of
+ * dropped items. */
+long oracle_hist2d(long N, const double *a, const double *b, const double *v,
+                   double lo0, double hi0, double lo1, double hi1, int W, int H,
+                   int closed_upper, uint32_t *counts, double *sums)
+{
+    long dropped = 0;
+    memset(counts, 0, sizeof(uint32_t) * (size_t)W * (size_t)H);
+    memset(sums, 0, sizeof(double) * (size_t)W * (size_t)H);
+    for (long n = 0; n < N; n++) {
+        if (!isfinite(a[n]) || !isfinite(b[n])) { dropped++; continue; }
+        double fi = floor((a[n] - lo0) / (hi0 - lo0) * (double)W);
+        double fj = floor((b[n] - lo1) / (hi1 - lo1) * (double)H);
+        if (closed_upper) {
+            if (fi == (double)W && a[n] == hi0) fi = W - 1;
+            if (fj == (double)H && b[n] == hi1) fj = H - 1;
+        }
+        if (fi < 0.0 || fi >= (double)W || fj < 0.0 || fj >= (double)H) { dropped++; continue; }
+        long i = (long)fi, j = (long)fj;
+        counts[j * W + i] += 1u;
+        sums[j * W + i] = sums[j * W + i] + v[n];
+    }
+    return dropped;
+}
+
+/* Direction of V on the sphere as equal-area coordinates:
+ * phi = atan2(Vy, Vx) in [-pi, pi], mu = Vz / |V| in [-1, 1].
+ * A zero V gets NaN keys (dropped by the histogram). */
+void oracle_vdir_keys(long N, const double *V, double *phi, double *mu)
+{
+    for (long n = 0; n < N; n++) {
+        double vx = V[n], vy = V[N + n], vz = V[2 * N + n];
+        double r = sqrt(vx * vx + vy * vy + vz * vz);
+        if (r == 0.0) { phi[n] = NAN; mu[n] = NAN; continue; }
+        phi[n] = atan2(vy, vx);
+        mu[n] = vz / r;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Small accessors used by the tests.                                        */
+/* ------------------------------------------------------------------------ */
+
+double oracle_energy(const double s[6], double eps) { return energy(s, eps); }
+
+/* hp, gradient g[3], Hessian entries H6 = (xx, yy, zz, xy, xz, yz). */
+void oracle_hp_derivs(const double X[3], double *hp, double g[3], double H6[6])
+{
+    double Hs[3][3];
+    *hp = hp_value(X);
+    hp_gradient(X, g);
+    hp_hessian(X, Hs);
+    H6[0] = Hs[0][0];
+    H6[1] = Hs[1][1];
+    H6[2] = Hs[2][2];
+    H6[3] = Hs[0][1];
+    H6[4] = Hs[0][2];
+    H6[5] = Hs[1][2];
+}
+
+/* Triple-jump constants as evaluated here: g1, g0, d1, d0. */
+void oracle_tj_constants(double c[4])
+{
+    c[0] = tj_g1();
+    c[1] = 1.0 - 2.0 * c[0];
+    c[2] = tj_d1();
+    c[3] = 1.0 - 2.0 * c[2];
+}
+
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

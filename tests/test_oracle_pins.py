@@ -1,0 +1,397 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Every test here runs on the CPU.  Each pin is chosen so that a plausible slip
+in the oracle (a dropped term or sign in the force or the Hessian, a wrong
+composition coefficient, a transposed tangent column, a wrong accumulator)
+makes at least one of them fail:
+
+* the integrable limit eps = 0 (model section, after eq. 1), in closed form;
+* the derivatives of eq. 2 against complex-step / mpmath differentiation of
+  the formula as printed;
+* the Hamiltonian flow of eqs. 1-2 integrated by SciPy's DOP853, and the
+  order of convergence of each map form towards it;
+* symplecticity (section "Computational method") and time reversibility;
+* the reduction of the invariant plane z = p_z = 0 to two textbook Chirikov
+  standard maps;
+* the finite-time Lyapunov exponent at the hyperbolic and elliptic fixed
+  points of eq. 2, in closed form;
+* forward-mode derivatives of J against central finite differences;
+* histogram counts against numpy's histogram2d, and the equal-area property
+  of the direction binning.
+"""
+import json
+import os
+
+import mpmath
+import numpy as np
+import pytest
+from scipy.integrate import solve_ivp
+
+H_PAPER = 0.01 * 2.0 * np.pi  # h = 10^-2 T with T = 2 pi (section "Computational method")
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")
+
+
+# ---------------------------------------------------------------- helpers
+def hp_literal(x, y, z):
+    """Eq. 2 exactly as printed; works for complex arguments."""
+    return np.cos(x) * np.cos(y) * (1 + np.cos(2 * z))
+
+
+def grad_complex_step(X):
+    """Gradient of eq. 2 by complex-step differentiation (exact to rounding)."""
+    d = 1e-30
+    g = np.empty(3)
+    for a in range(3):
+        Z = np.array(X, dtype=complex)
+        Z[a] += 1j * d
+        g[a] = hp_literal(*Z).imag / d
+    return g
+
+
+def flow_rhs(eps):
+    def f(t, s):
+        g = grad_complex_step(s[:3])
+        return np.concatenate([s[3:], -eps * g])
+    return f
+
+
+def exact_flow(s0, eps, t):
+    sol = solve_ivp(flow_rhs(eps), (0.0, t), s0, method="DOP853", rtol=1e-13, atol=1e-13)
+    assert sol.success
+    return sol.y[:, -1]
+
+
+# ---------------------------------------------------------------- composition constants
+def test_triple_jump_order_conditions(orc):
+    """Triple-jump weights satisfy the order conditions of the composition:
+    2 g1 + g0 = 1 with 2 g1^3 + g0^3 = 0 (4th order) and 2 d1 + d0 = 1 with
+    2 d1^5 + d0^5 = 0 (6th order)."""
+    g1, g0, d1, d0 = orc.tj_constants()
+    assert abs(2 * g1 + g0 - 1) < 1e-15
+    assert abs(2 * g1 ** 3 + g0 ** 3) < 1e-14
+    assert abs(2 * d1 + d0 - 1) < 1e-15
+    assert abs(2 * d1 ** 5 + d0 ** 5) < 1e-14
+
+
+# ---------------------------------------------------------------- eq. 2 derivatives
+def test_hp_derivatives_against_mpmath(orc):
+    rng = np.random.default_rng(11)
+    mpmath.mp.dps = 30
+
+    def f(x, y, z):
+        return mpmath.cos(x) * mpmath.cos(y) * (1 + mpmath.cos(2 * z))
+
+    for _ in range(8):
+        X = rng.uniform(-7, 7, 3)
+        hp, g, H6 = orc.hp_derivs(X)
+        x, y, z = (mpmath.mpf(float(v)) for v in X)
+        assert abs(hp - float(f(x, y, z))) < 1e-15
+        for a, order in enumerate([(1, 0, 0), (0, 1, 0), (0, 0, 1)]):
+            assert abs(g[a] - float(mpmath.diff(f, (x, y, z), order))) < 1e-14
+        orders = [(2, 0, 0), (0, 2, 0), (0, 0, 2), (1, 1, 0), (1, 0, 1), (0, 1, 1)]
+        for a, order in enumerate(orders):
+            assert abs(H6[a] - float(mpmath.diff(f, (x, y, z), order))) < 1e-13
+
+
+def test_hp_fourier_form_and_bound(orc):
+    """Product-to-sum form of eq. 2: its Fourier modes are the primary
+    resonances (1, +-1, 0) and (1, +-1, +-2); and |Hp| <= 2 (model section)."""
+    gold = json.load(open(GOLDEN))
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        x, y, z = rng.uniform(-10, 10, 3)
+        four = 0.5 * (np.cos(x + y) + np.cos(x - y)) + 0.25 * (
+            np.cos(x + y + 2 * z) + np.cos(x + y - 2 * z) + np.cos(x - y + 2 * z) + np.cos(x - y - 2 * z))
+        s = np.array([x, y, z, 0, 0, 0])
+        assert abs(orc.energy(s, 1.0) - four) < 1e-14
+        assert abs(orc.energy(s, 1.0)) <= gold["Hp_bound"]["value"]
+    assert orc.energy(np.zeros(6), 1.0) == gold["Hp_bound"]["value"]
+
+
+# ---------------------------------------------------------------- eps = 0
+@pytest.mark.parametrize("form", ["stdmap", "s2", "s4", "s6"])
+def test_integrable_limit(orc, form):
+    """eps = 0: P constant, X(t) = X(0) + P t, and the tangent grows by the
+    linear shear: L_T = 1/2 ln(|dX0 + T h dP0|^2 + |dP0|^2)."""
+    rng = np.random.default_rng(1)
+    N, T = 16, 300
+    ic = rng.uniform(0, 2 * np.pi, (6, N))
+    w0 = orc.w0(7, N)
+    out, st = orc.ensemble(form, 0.0, H_PAPER, T, ic, w0, want_state=True)
+    th = T * H_PAPER
+    np.testing.assert_array_equal(st[3:6], ic[3:6])
+    np.testing.assert_allclose(st[0:3], ic[0:3] + th * ic[3:6], rtol=1e-12, atol=1e-12)
+    L = 0.5 * np.log(np.sum((w0[0:3] + th * w0[3:6]) ** 2, axis=0) + np.sum(w0[3:6] ** 2, axis=0))
+    np.testing.assert_allclose(out[0], L, rtol=1e-11)
+    np.testing.assert_allclose(out[3:6], ic[3:6], rtol=1e-12, atol=1e-13)
+    assert np.all(out[6] == 0) and np.all(out[7] == 0) and np.all(out[8] == 0)
+
+
+# ---------------------------------------------------------------- the flow of eqs. 1-2
+def test_s6_tracks_hamiltonian_flow(orc):
+    """S6 at a small step reproduces the DOP853 solution of Hamilton's
+    equations of eqs. 1-2 (force from the printed eq. 2, not from the oracle)."""
+    rng = np.random.default_rng(2)
+    for eps in (1.0, 0.1):
+        s0 = np.concatenate([rng.uniform(0, 2 * np.pi, 3), rng.uniform(-1.5, 1.5, 3)])
+        h, T = 0.02, 100
+        ref = exact_flow(s0, eps, h * T)
+        got = orc.map_state("s6", eps, h, T, s0)
+        assert np.max(np.abs(got - ref)) < 1e-10
+
+
+@pytest.mark.parametrize("form,order,h", [("stdmap", 1, 0.02), ("s2", 2, 0.05), ("s4", 4, 0.1), ("s6", 6, 0.2)])
+def test_convergence_order(orc, form, order, h):
+    """Error against the exact flow falls by 2^order per halving of h."""
+    s0 = np.array([0.3, 1.1, 0.7, 0.9, -0.4, 0.6])
+    t, eps = 2.0, 1.0
+    ref = exact_flow(s0, eps, t)
+    errs = []
+    for hh in (h, h / 2):
+        T = int(round(t / hh))
+        errs.append(np.max(np.abs(orc.map_state(form, eps, hh, T, s0) - ref)))
+    ratio = errs[0] / errs[1]
+    assert 0.75 * 2 ** order < ratio < 1.3 * 2 ** order, (errs, ratio)
+
+
+# ---------------------------------------------------------------- symplecticity, reversibility
+@pytest.mark.parametrize("form", ["stdmap", "s6"])
+def test_symplectic_jacobian(orc, form):
+    Om = np.block([[np.zeros((3, 3)), np.eye(3)], [-np.eye(3), np.zeros((3, 3))]])
+    s0 = np.array([0.4, 2.0, 1.3, 0.7, 0.2, -0.5])
+    _, M = orc.jacobian(form, 0.3, H_PAPER, 50, s0)
+    assert np.max(np.abs(M.T @ Om @ M - Om)) < 1e-11
+    assert abs(np.linalg.det(M) - 1.0) < 1e-10
+
+
+@pytest.mark.parametrize("form", ["stdmap", "s6"])
+def test_jacobian_against_finite_differences(orc, form):
+    s0 = np.array([0.4, 2.0, 1.3, 0.7, 0.2, -0.5])
+    eps, T, d = 0.05, 20, 1e-6
+    _, M = orc.jacobian(form, eps, H_PAPER, T, s0)
+    fd = np.empty((6, 6))
+    for j in range(6):
+        e = np.zeros(6)
+        e[j] = d
+        fd[:, j] = (orc.map_state(form, eps, H_PAPER, T, s0 + e) - orc.map_state(form, eps, H_PAPER, T, s0 - e)) / (2 * d)
+    assert np.max(np.abs(M - fd)) < 1e-7
+
+
+@pytest.mark.parametrize("form", ["s2", "s4", "s6"])
+def test_time_reversibility(orc, form):
+    """Symmetric compositions: S(-h) S(h) = id and R S R S = id, R(X, P) = (X, -P)."""
+    s0 = np.array([0.4, 2.0, 1.3, 0.7, 0.2, -0.5])
+    fwd = orc.map_state(form, 0.5, H_PAPER, 40, s0)
+    back = orc.map_state(form, 0.5, -H_PAPER, 40, fwd)
+    assert np.max(np.abs(back - s0)) < 1e-12
+    r = fwd.copy()
+    r[3:] *= -1
+    rr = orc.map_state(form, 0.5, H_PAPER, 40, r)
+    rr[3:] *= -1
+    assert np.max(np.abs(rr - s0)) < 1e-12
+
+
+# ---------------------------------------------------------------- invariant plane
+def test_invariant_plane_is_two_chirikov_maps(orc):
+    """On z = p_z = 0, eq. 2 reduces to eps (cos u + cos v) with u = x + y,
+    v = x - y, and the kick-then-drift map becomes, for each of u and v, the
+    Chirikov standard map I' = I + K sin u, u' = u + I', I = 2 h p_u, K = 2 eps h^2."""
+    eps, h, T = 0.2, 0.3, 60
+    s = np.array([0.9, -0.35, 0.0, 0.4, 1.3, 0.0])
+    u, v = s[0] + s[1], s[0] - s[1]
+    Iu, Iv = 2 * h * (s[3] + s[4]) / 2, 2 * h * (s[3] - s[4]) / 2
+    K = 2 * eps * h * h
+    for _ in range(T):
+        s = orc.map_state("stdmap", eps, h, 1, s)
+        Iu = Iu + K * np.sin(u)
+        u = u + Iu
+        Iv = Iv + K * np.sin(v)
+        v = v + Iv
+        assert s[2] == 0.0 and s[5] == 0.0
+    assert abs((s[0] + s[1]) - u) < 1e-11 and abs((s[0] - s[1]) - v) < 1e-11
+    assert abs(2 * h * (s[3] + s[4]) / 2 - Iu) < 1e-12
+    assert abs(2 * h * (s[3] - s[4]) / 2 - Iv) < 1e-12
+    # The 6th-order map keeps the plane invariant too (exact zeros).
+    s6 = orc.map_state("s6", 0.01, H_PAPER, 500, np.array([0.0, 0.0, 0.0, 2.0, 1.0, 0.0]))
+    assert s6[2] == 0.0 and s6[5] == 0.0
+
+
+# ---------------------------------------------------------------- energy
+def test_energy_bounded_and_in_layer(orc):
+    """No secular energy growth under the symplectic map, and P^2 stays in the
+    layer 2(E - 2 eps) <= P^2 <= 2(E + 2 eps) implied by |Hp| <= 2."""
+    eps = 1.0
+    s = np.array([0.3, 1.0, 2.0, 4.0, 3.0, 2.5])
+    E0 = orc.energy(s, eps)
+    dE = []
+    for _ in range(200):
+        s = orc.map_state("s6", eps, H_PAPER, 50, s)
+        dE.append(abs(orc.energy(s, eps) - E0))
+        p2 = np.sum(s[3:] ** 2)
+        assert 2 * (E0 - 2 * eps) - 1e-8 <= p2 <= 2 * (E0 + 2 * eps) + 1e-8
+    dE = np.array(dE)
+    assert dE.max() < 1e-6
+    assert dE[100:].max() < 3 * dE[:100].max() + 1e-12
+
+
+# ---------------------------------------------------------------- Lyapunov indicator
+def test_ftle_at_hyperbolic_point(orc):
+    """X = 0, P = 0 is the maximum of eq. 2 (Hp = 2 - x^2 - y^2 - 2 z^2 + ...),
+    a fixed point whose linearisation has growth rates sqrt(2 eps) (x, y) and
+    sqrt(4 eps) (z); the FTLE tends to the largest."""
+    eps, T = 0.1, 20000
+    out = orc.ensemble("s6", eps, H_PAPER, T, np.zeros((6, 1)), orc.w0(0, 1))
+    assert abs(out[1, 0] - np.sqrt(4 * eps)) < 0.01
+    assert out[2, 0] > 2.0
+
+
+def test_ftle_at_elliptic_point(orc):
+    """X = (pi, 0, 0), P = 0 is the minimum of eq. 2: the tangent only rotates,
+    L stays bounded and the indicator reads regular."""
+    ic = np.array([[np.pi], [0], [0], [0], [0], [0]], dtype=float)
+    out = orc.ensemble("s6", 0.1, H_PAPER, 20000, ic, orc.w0(0, 1))
+    assert abs(out[0, 0]) < 3.0
+    assert out[2, 0] < 0.5
+
+
+def test_regular_orbits_keep_velocity_near_initial_momentum(orc):
+    """Regular orbits keep V close to P(0) (section Main results): at small eps
+    |V - P0| is O(eps)."""
+    ic = orc.ic_grid2((3, 4), (0.5, 0.5), (2 * np.pi, 2 * np.pi), 8, 8, [0, 0, 0, 0, 0, 1.0])
+    for eps in (1e-4, 1e-3):
+        out = orc.ensemble("s6", eps, H_PAPER, 2000, ic, orc.w0(0, 64))
+        reg = out[2] < 1.5
+        assert reg.mean() > 0.8
+        dv = np.max(np.abs(out[3:6, reg] - ic[3:6, reg]))
+        assert dv < 40 * eps
+
+
+# ---------------------------------------------------------------- J derivatives
+def test_J_forward_mode_against_finite_differences(orc):
+    s0 = np.array([0.4, 2.0, 0.3, 0.9, 0.5, 0.2])
+    eps, T, d = 1e-2, 300, 1e-6
+    J, dJ = orc.J_grad("s6", eps, H_PAPER, T, s0)
+    assert J > 0
+    for c in range(7):
+        if c < 6:
+            e = np.zeros(6)
+            e[c] = d
+            Jp, _ = orc.J_grad("s6", eps, H_PAPER, T, s0 + e)
+            Jm, _ = orc.J_grad("s6", eps, H_PAPER, T, s0 - e)
+        else:
+            Jp, _ = orc.J_grad("s6", eps + d, H_PAPER, T, s0)
+            Jm, _ = orc.J_grad("s6", eps - d, H_PAPER, T, s0)
+        fd = (Jp - Jm) / (2 * d)
+        assert abs(dJ[c] - fd) <= 1e-6 * max(abs(fd), 1e-3), (c, dJ[c], fd)
+    # J also equals the accumulator of the one-tangent run.
+    out = orc.ensemble("s6", eps, H_PAPER, T, s0.reshape(6, 1), orc.w0(0, 1))
+    assert abs(out[7, 0] - J) <= 1e-14 * J
+
+
+def test_J_gradient_symmetry_on_invariant_plane(orc):
+    """z -> -z, p_z -> -p_z is a symmetry of eq. 2, so dJ/dz0 = dJ/dpz0 = 0
+    exactly on the plane z = p_z = 0."""
+    _, dJ = orc.J_grad("s6", 1e-2, H_PAPER, 200, np.array([0.0, 0.0, 0.0, 1.3, 2.1, 0.0]))
+    assert dJ[2] == 0.0 and dJ[5] == 0.0
+
+
+# ---------------------------------------------------------------- resume
+def test_chunked_run_is_bitwise_equal(orc):
+    s0 = np.array([0.1, 0.2, 0.3, 1.0, 2.0, 0.5])
+    w = orc.w0(3, 1)[:, 0]
+    full = orc.rec_advance("s6", 0.02, H_PAPER, 500, orc.rec_init(s0, w))
+    part = orc.rec_init(s0, w)
+    for n in (123, 77, 300):
+        part = orc.rec_advance("s6", 0.02, H_PAPER, n, part)
+    np.testing.assert_array_equal(part, full)
+    np.testing.assert_array_equal(orc.rec_finish(part, 0.02, H_PAPER), orc.rec_finish(full, 0.02, H_PAPER))
+
+
+# ---------------------------------------------------------------- inputs
+def test_splitmix64_counter_form_matches_sequential_generator(orc):
+    """Output c of the sequential SplitMix64 generator (state += gamma; mix)."""
+    M = (1 << 64) - 1
+
+    def seq(seed, n):
+        st, out = seed, []
+        for _ in range(n):
+            st = (st + 0x9E3779B97F4A7C15) & M
+            z = st
+            z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+            z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+            out.append(z ^ (z >> 31))
+        return out
+
+    for seed in (0, 1, 2, 12345678901234567):
+        ref = seq(seed, 40)
+        assert [orc.splitmix64(seed, c) for c in range(40)] == ref
+        assert all(orc.u01(seed, c) == (ref[c] >> 11) * 2.0 ** -53 for c in range(40))
+
+
+def test_uniform_draws_are_uniform(orc):
+    from scipy.stats import kstest
+    ic = orc.ic_box([0] * 6, [1] * 6, 2, 20000)
+    for k in range(6):
+        assert kstest(ic[k], "uniform").pvalue > 1e-4
+    w = orc.w0(0, 1000)
+    np.testing.assert_allclose(np.sqrt(np.sum(w * w, axis=0)), 1.0, atol=2e-16)
+
+
+def test_grid_left_edges(orc):
+    ic = orc.ic_grid2((3, 4), (0, 0), (2 * np.pi, 2 * np.pi), 64, 32, [9, 8, 7, 6, 5, 4])
+    d0, d1 = 2 * np.pi / 64, 2 * np.pi / 32
+    n = np.arange(64 * 32)
+    np.testing.assert_array_equal(ic[3], (n % 64) * d0)
+    np.testing.assert_array_equal(ic[4], (n // 64) * d1)
+    assert ic[3].min() == 0 and ic[3].max() < 2 * np.pi
+    np.testing.assert_array_equal(ic[[0, 1, 2, 5]], np.array([[9], [8], [7], [4]]) * np.ones((1, n.size)))
+    sub = orc.ic_grid2((3, 4), (0, 0), (2 * np.pi, 2 * np.pi), 64, 32, [9, 8, 7, 6, 5, 4], idx=[5, 700])
+    np.testing.assert_array_equal(sub, ic[:, [5, 700]])
+
+
+# ---------------------------------------------------------------- images
+def test_hist2d_matches_numpy(orc):
+    rng = np.random.default_rng(9)
+    N, W, H = 50000, 37, 23
+    a = rng.uniform(-0.5, 7.0, N)
+    b = rng.uniform(-0.2, 6.5, N)
+    v = rng.normal(size=N)
+    counts, sums, dropped = orc.hist2d(a, b, v, (0, 0), (2 * np.pi, 2 * np.pi), W, H)
+    ref, _, _ = np.histogram2d(b, a, bins=[H, W], range=[[0, 2 * np.pi], [0, 2 * np.pi]])
+    np.testing.assert_array_equal(counts, ref.astype(np.uint32))
+    assert counts.sum() + dropped == N
+    i = np.floor(a / (2 * np.pi) * W).astype(int)
+    j = np.floor(b / (2 * np.pi) * H).astype(int)
+    ok = (i >= 0) & (i < W) & (j >= 0) & (j < H)
+    ref_s = np.zeros((H, W))
+    np.add.at(ref_s, (j[ok], i[ok]), v[ok])
+    np.testing.assert_allclose(sums, ref_s, rtol=1e-12, atol=1e-12)
+
+
+def test_direction_density_is_equal_area(orc):
+    """Isotropic directions give a flat density 1/(4 pi) in (phi, mu) bins."""
+    rng = np.random.default_rng(4)
+    N, W, H = 400000, 16, 8
+    V = rng.normal(size=(3, N)) * 3.0
+    dens, counts, dropped = orc.hist_vdir(V, W, H)
+    assert dropped == 0 and counts.sum() == N
+    expect = N / (W * H)
+    chi2 = np.sum((counts - expect) ** 2 / expect)
+    assert chi2 < W * H + 6 * np.sqrt(2 * W * H)
+    np.testing.assert_allclose(dens.mean(), 1 / (4 * np.pi), rtol=1e-12)
+
+
+# ---------------------------------------------------------------- paper constants
+def test_paper_constants(orc):
+    g = json.load(open(GOLDEN))
+    # eq. 3: eps_eff = max|Hp| / H = 2 / E, with eps = 1.
+    assert 2.0 / g["E_weak"]["value"] == pytest.approx(g["eps_eff_weak"]["value"], rel=1e-15)
+    a, b = g["eps_eff_moderate"]["value"]
+    assert 2.0 / g["E_moderate"]["value"] == pytest.approx(a / b, rel=1e-15)
+    # W = (sqrt E, sqrt E, 0) lies on the three resonance planes and on the sphere P^2 = 2E.
+    E = g["E_moderate"]["value"]
+    W = np.sqrt(E) * np.array(g["W_point_over_sqrtE"]["value"])
+    for m in g["W_resonances"]["value"]:
+        assert abs(np.dot(m, W)) < 1e-14
+    assert abs(W @ W - 2 * E) < 1e-12
+    assert H_PAPER == pytest.approx(g["step_over_T"]["value"] * 2 * np.pi)
