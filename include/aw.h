@@ -1,0 +1,249 @@
+/*
+ * aw.h -- C ABI of libaw, the MI355X (gfx950) ensemble mapper for the
+ * Arnold-web model of arXiv:1107.4107 ("Mapping the Arnold web with a
+ * GPU-supercomputer", Seibert, Denisov, Ponomarev, Hanggi).
+ *
+ * Model (eqs. 1-2): H(P, X) = |P|^2 / 2 + eps * Hp(X),
+ *                   Hp(x, y, z) = cos x cos y (1 + cos 2z),   M = 3.
+ * Propagation (section "Computational method"): a symplectic map with step h.
+ * The paper's 6th-order scheme is taken as the triple-jump composition
+ * S6(h) = S4(d1 h) S4(d0 h) S4(d1 h), S4(t) = S2(g1 t) S2(g0 t) S2(g1 t),
+ * S2(t) = D(t/2) K(t) D(t/2) with d1 = 1/(2 - 2^(1/5)), g1 = 1/(2 - 2^(1/3));
+ * its first-order member K(h) then D(h) is the coupled standard map that the
+ * model section names.  Drift D(t): X += t P.  Kick K(t): P -= t eps grad Hp(X).
+ *
+ * Conventions for every entry point:
+ *  - Pointers named *_dev are device memory of the current HIP device, owned
+ *    by the caller; the library never frees or reallocates them.  Pointers to
+ *    descriptors (aw_ensemble, aw_image_spec, aw_tuning) are host memory and
+ *    are read before the call returns.
+ *  - Arrays are structure-of-arrays, float64 unless stated: a "[R][N]" array
+ *    holds row r of orbit n at offset r*N + n.  Orbit n of a GRID2 slice is
+ *    n = j*nx + i (i along axis[0]).
+ *  - All work is enqueued on `stream` (a hipStream_t, NULL = default stream);
+ *    no entry point synchronises the host except where stated.
+ *  - Arguments are validated before anything is enqueued.  On a non-AW_OK
+ *    return nothing was enqueued (AW_EDEVICE: a launch failed) and
+ *    aw_last_error() gives a message.  No C++ exception crosses the ABI.
+ *  - Asynchronous device faults surface at the caller's next synchronisation.
+ *  - Internal scratch (histogram sort buffers, batch tables) is allocated by
+ *    the library on first use, grown when needed and kept per device until
+ *    aw_release() or process exit; calls that overlap on one device through
+ *    different streams must not share the library (they share that scratch).
+ */
+#ifndef AW_H
+#define AW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AW_OK = 0,
+  AW_EINVAL = 1,        /* an argument is out of range or inconsistent */
+  AW_EUNSUPPORTED = 2,  /* a well-formed request this build does not do (e.g. M != 3) */
+  AW_EDEVICE = 3,       /* a HIP call or kernel launch failed */
+  AW_ENOMEM = 4,        /* internal scratch could not be allocated */
+  AW_EWORKSPACE = 5     /* caller workspace too small */
+} aw_status;
+
+/* Text of the last non-AW_OK status returned on this host thread. */
+const char *aw_last_error(void);
+/* Library version string. */
+const char *aw_version(void);
+/* Frees the library's internal scratch on the current device (synchronises it). */
+aw_status aw_release(void);
+
+/* Map forms: the first-order coupled standard map and the symmetric
+ * compositions of order 2, 4 and 6 (section "Computational method"). */
+typedef enum { AW_MAP_STDMAP = 1, AW_MAP_S2 = 2, AW_MAP_S4 = 4, AW_MAP_S6 = 6 } aw_map_form;
+
+/* Initial conditions of an ensemble (sections "Main results", Figs. 2-4).
+ *  GRID2:    a 2-D slice: s = base; s[axis[0]] = lo[0] + i * ((hi[0]-lo[0])/nx),
+ *            s[axis[1]] = lo[1] + j * ((hi[1]-lo[1])/ny)  (left edges).
+ *  BOX:      s_k = box_lo[k] + (box_hi[k]-box_lo[k]) * U(seed_ic, 16 n + k).
+ *  EXPLICIT: the caller's ic_dev[6][N].
+ * U(seed, c) = (SplitMix64 output number c of the stream seeded with `seed`,
+ * i.e. mix(seed + (c+1)*0x9E3779B97F4A7C15)) >> 11, times 2^-53.
+ * The tangent start of orbit n is w0 = u/|u|, u_k = 2 U(seed_tangent, 16 n + k) - 1,
+ * for every ic_kind.  Coordinate order is (x, y, z, px, py, pz). */
+typedef enum { AW_IC_GRID2 = 0, AW_IC_BOX = 1, AW_IC_EXPLICIT = 2 } aw_ic_kind;
+
+/* flags */
+#define AW_F_TANGENT 1u  /* propagate the tangent vector (L, lambda, chi, class) */
+
+/* Rows of the per-orbit output orbit_out[AW_NOUT][N]:
+ *  L      = ln(|w_T| / |w_0|), the tangent-vector growth (FTLE numerator);
+ *  LAMBDA = L / (T h);         CHI = L / ln(1 + T h);
+ *  V      = (X_T - X_0) / (T h) on unwrapped X, the finite-time mean velocity
+ *           of section "Main results" with Delta t = T h;
+ *  DP2    = |P_T - P_0|^2, the momentum drift of the model section;
+ *  J      = (1/T) sum_{k=1..T} |P_k - P_0|^2;
+ *  DE     = H(s_T) - H(s_0).
+ * Without AW_F_TANGENT the rows L, LAMBDA, CHI hold NaN and class is 0. */
+enum {
+  AW_OUT_L = 0, AW_OUT_LAMBDA, AW_OUT_CHI, AW_OUT_VX, AW_OUT_VY, AW_OUT_VZ,
+  AW_OUT_DP2, AW_OUT_J, AW_OUT_DE, AW_NOUT
+};
+
+typedef struct {
+  int32_t M;              /* degrees of freedom; only 3 is defined (eq. 2) */
+  int32_t map_form;       /* aw_map_form */
+  double eps;             /* eps of eq. 1 (finite) */
+  double h;               /* step (finite, non-zero; the paper: 0.01 * 2 pi) */
+  int64_t n_steps;        /* T >= 1 */
+  int32_t ic_kind;        /* aw_ic_kind */
+  int32_t axis[2];        /* GRID2: the two varied coordinates, 0..5, distinct */
+  double lo[2], hi[2];    /* GRID2: ranges */
+  int64_t nx, ny;         /* GRID2: grid size (>= 1) */
+  double base[6];         /* GRID2: the fixed coordinates */
+  double box_lo[6], box_hi[6]; /* BOX */
+  int64_t n_orbits;       /* BOX and EXPLICIT: N (>= 0); GRID2: ignored (N = nx*ny) */
+  uint64_t seed_ic;       /* BOX */
+  uint64_t seed_tangent;  /* tangent start */
+  double chi_threshold;   /* class = chi > chi_threshold */
+  uint32_t flags;         /* AW_F_* */
+} aw_ensemble;
+
+/* Launch shape.  NULL = defaults (block 256, one orbit per lane, step loop not
+ * unrolled, renormalisation every 8 steps).  block in {64, 128, 256};
+ * orbits_per_lane in {1, 2}; unroll in {1, 2}; renorm_every in {1, 2, 4, 8, 16}.
+ * persistent_wgs: workgroups of the batched persistent launch (0 = auto). */
+typedef struct {
+  int32_t block;
+  int32_t orbits_per_lane;
+  int32_t unroll;
+  int32_t renorm_every;
+  int32_t persistent_wgs;
+} aw_tuning;
+
+/* Number of orbits of an ensemble (nx*ny for GRID2), or -1 if invalid. */
+int64_t aw_ensemble_size(const aw_ensemble *ens);
+
+/* Writes the initial state ic_dev[6][N] and the tangent start w0_dev[6][N]
+ * (either may be NULL) of an ensemble: the exact values the propagation
+ * starts from.  EXPLICIT ensembles copy ic_dev from ic_in_dev. */
+aw_status aw_generate_ic(const aw_ensemble *ens, const double *ic_in_dev,
+                         double *ic_dev, double *w0_dev, void *stream);
+
+/* Propagate ensembles for their n_steps and write per-orbit outputs.
+ * n_ens >= 1 descriptors; with n_ens > 1 every ensemble must share map_form
+ * and flags, and all of them run in ONE persistent launch whose workgroups
+ * take (ensemble, tile) items, longest first, from a device queue.
+ *   ic_dev[e]        EXPLICIT: [6][N_e], else ignored (the array may be NULL)
+ *   orbit_out_dev[e] [AW_NOUT][N_e] or NULL
+ *   state_out_dev[e] [12][N_e] (X, P, unit tangent) or NULL
+ *   cls_dev[e]       uint8 [N_e] (1 = chi > chi_threshold) or NULL
+ * Per-orbit results are bitwise independent of the tuning and of batching. */
+aw_status aw_map_ensemble(const aw_ensemble *ens, int32_t n_ens,
+                          const double *const *ic_dev, double *const *orbit_out_dev,
+                          double *const *state_out_dev, uint8_t *const *cls_dev,
+                          const aw_tuning *tuning, void *stream);
+
+/* Rows of the resumable carry[AW_NCARRY][N]. */
+#define AW_NCARRY 21
+
+/* Resumable form of aw_map_ensemble for one ensemble: runs global steps
+ * [k_begin, k_end) with 0 <= k_begin < k_end <= n_steps.  k_begin == 0 starts
+ * from the initial conditions; otherwise the state is read from carry_dev.
+ * If k_end < n_steps the state is written to carry_dev; if k_end == n_steps
+ * the outputs are written as by aw_map_ensemble.  A chain of calls covering
+ * [0, n_steps) gives results bitwise equal to one aw_map_ensemble call. */
+aw_status aw_map_ensemble_steps(const aw_ensemble *ens, const double *ic_dev,
+                                double *carry_dev, int64_t k_begin, int64_t k_end,
+                                double *orbit_out_dev, double *state_out_dev,
+                                uint8_t *cls_dev, const aw_tuning *tuning, void *stream);
+
+/* Images (section "Main results"; Figs. 2-4).
+ *  IC_GRID:   GRID2 ensembles only; image[j][i] = orbit_out row `field` of
+ *             orbit j*nx + i (W = nx, H = ny).  counts, if non-NULL, is one
+ *             uint32: the number of orbits with class 1 (needs AW_F_TANGENT).
+ *  HIST_P0:   key = initial coordinates (key_axis[0], key_axis[1]); bin
+ *             floor((a - lo)/(hi - lo) * W) per axis, half-open ranges, items
+ *             outside dropped; image = per-bin mean of row `field` (0 where
+ *             empty), counts = per-bin count.
+ *  HIST_VDIR: the density F of the direction of V on the momentum sphere:
+ *             phi = atan2(Vy, Vx) over [-pi, pi] (W bins), mu = Vz/|V| over
+ *             [-1, 1] (H bins), closed at the top; image = count / (N dphi dmu),
+ *             counts = per-bin count.  A zero V is dropped.
+ * Histograms are built by a counting sort of items by image tile followed by
+ * per-tile LDS accumulation; counts are exact and deterministic, float sums
+ * may differ in the last bits between runs. */
+typedef enum { AW_IMG_IC_GRID = 0, AW_IMG_HIST_P0 = 1, AW_IMG_HIST_VDIR = 2 } aw_image_kind;
+
+typedef struct {
+  int32_t kind;        /* aw_image_kind */
+  int32_t field;       /* AW_OUT_* row imaged (IC_GRID) or averaged (HIST_P0) */
+  int32_t W, H;        /* image size; IC_GRID requires W = nx, H = ny */
+  int32_t key_axis[2]; /* HIST_P0: key coordinates, 0..5 */
+  double lo[2], hi[2]; /* HIST_P0: key ranges (lo < hi) */
+} aw_image_spec;
+
+/* Propagate and reduce to an image, per ensemble:
+ *   image_dev[e]  [H][W] float64;  counts_dev[e] [H][W] uint32 (or NULL; see above)
+ *   cls_dev[e]    uint8 [N_e] or NULL.
+ * n_ens > 1 runs the propagation as one persistent launch (as aw_map_ensemble). */
+aw_status aw_indicator_image(const aw_ensemble *ens, int32_t n_ens, const aw_image_spec *spec,
+                             double *const *image_dev, uint32_t *const *counts_dev,
+                             uint8_t *const *cls_dev, const aw_tuning *tuning, void *stream);
+
+/* The histogram reduction on its own, over caller keys a_dev[N], b_dev[N] and
+ * values v_dev[N] (v_dev may be NULL: sums are then not formed): bin along
+ * each axis floor((key - lo)/(hi - lo) * W); closed_upper = 0: half-open
+ * ranges, out-of-range and non-finite keys dropped; closed_upper = 1: a key
+ * equal to hi goes to the last bin.  counts_dev [H][W] uint32, sums_dev
+ * [H][W] float64 (NULL allowed), dropped_dev one uint64 (NULL allowed). */
+aw_status aw_histogram2d(int64_t N, const double *a_dev, const double *b_dev, const double *v_dev,
+                         double lo0, double hi0, double lo1, double hi1, int32_t W, int32_t H,
+                         int32_t closed_upper, uint32_t *counts_dev, double *sums_dev,
+                         uint64_t *dropped_dev, void *stream);
+
+/* Equal-area keys of the direction of V[3][N]: phi = atan2(Vy, Vx),
+ * mu = Vz / |V|; NaN for a zero V. */
+aw_status aw_vdir_keys(int64_t N, const double *V_dev, double *phi_dev, double *mu_dev, void *stream);
+
+/* Gradient of J = (1/T) sum_{k=1..T} |P_k - P_0|^2 (the step-averaged momentum
+ * drift of the model section) by a hand-written adjoint: one forward pass that
+ * stores a state checkpoint every ckpt_every steps, then, segment by segment
+ * from the end, a recompute of the segment's step states and a reverse sweep
+ * that inverts each stage.  ens->ic_kind must be EXPLICIT (ic_dev[6][N]).
+ *   grad_J_dev [N]: upstream dL/dJ_n (NULL = all ones)
+ *   J_out_dev [N] or NULL; grad_ic_dev [6][N]: dL/d(initial x..pz);
+ *   grad_eps_dev [N]: per-orbit dL/deps contributions (sum them for the scalar).
+ * Requires a caller workspace of aw_indicator_grad_workspace() bytes. */
+aw_status aw_indicator_grad_workspace(const aw_ensemble *ens, int64_t ckpt_every, size_t *bytes);
+aw_status aw_indicator_grad(const aw_ensemble *ens, const double *ic_dev, const double *grad_J_dev,
+                            int64_t ckpt_every, double *J_out_dev, double *grad_ic_dev,
+                            double *grad_eps_dev, void *workspace_dev, size_t ws_bytes,
+                            const aw_tuning *tuning, void *stream);
+
+/* A captured HIP graph of aw_indicator_image over n_ens ensembles (one
+ * persistent launch plus the reductions).  Buffers are bound at creation;
+ * the descriptors are copied.  Launching replays the whole batch. */
+typedef struct aw_graph aw_graph;
+aw_status aw_graph_create(const aw_ensemble *ens, int32_t n_ens, const aw_image_spec *spec,
+                          double *const *image_dev, uint32_t *const *counts_dev,
+                          uint8_t *const *cls_dev, const aw_tuning *tuning, aw_graph **out);
+aw_status aw_graph_launch(aw_graph *g, void *stream);
+void aw_graph_destroy(aw_graph *g);
+
+/* Kernel timing for measurement: when enabled, HIP events are recorded on the
+ * launch stream around every propagation kernel.  aw_timing_read() waits for
+ * the recorded events, returns the summed kernel milliseconds and the number
+ * of launches since the last read, and clears the record. */
+aw_status aw_timing_enable(int32_t on);
+aw_status aw_timing_read(double *ms, int64_t *launches);
+
+/* FP64 operations per map step of the propagation kernel as built, for the
+ * roofline: counts of fma, mul and add/sub instructions (per orbit-step,
+ * excluding the per-orbit prologue/epilogue); flops = 2 fma + mul + add. */
+aw_status aw_step_op_counts(int32_t map_form, int32_t tangent, int64_t *fma, int64_t *mul,
+                            int64_t *add);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AW_H */

@@ -61,6 +61,7 @@ def _load():
         "oracle_map": (i, [i, d, d, l, _dp]),
         "oracle_jacobian": (i, [i, d, d, l, _dp, _dp, _dp]),
         "oracle_J_grad": (i, [i, d, d, l, _dp, _dp, _dp]),
+        "oracle_J_grad_ensemble": (i, [i, d, d, l, l, _dp, _dp, _dp, i]),
         "oracle_splitmix64": (u64, [u64, u64]),
         "oracle_u01": (d, [u64, u64]),
         "oracle_ic_grid2": (i, [i, i, d, d, d, d, l, l, _dp, _lp, l, _dp]),
@@ -181,6 +182,17 @@ def J_grad(form, eps, h, T, s0):
     if _load().oracle_J_grad(_form(form), eps, h, int(T), _ptr(s0), ctypes.byref(J), _ptr(dJ)):
         raise ValueError("bad map form")
     return J.value, dJ
+
+
+def J_grad_ensemble(form, eps, h, T, ic, nthreads=0):
+    """Forward-mode J and dJ[7, N] (d/d x..pz, eps) for every orbit of ic[6, N]."""
+    ic = _f64(ic)
+    N = ic.shape[1]
+    J = np.empty(N)
+    dJ = np.empty((7, N))
+    if _load().oracle_J_grad_ensemble(_form(form), eps, h, int(T), N, _ptr(ic), _ptr(J), _ptr(dJ), int(nthreads)):
+        raise ValueError("bad map form")
+    return J, dJ
 
 
 def rec_init(s0, w0_):

@@ -275,7 +275,7 @@ int oracle_ensemble(int form, double eps, double h, long T, long N,
     if (T < 1 || N < 0) return -1;
 #ifdef _OPENMP
     if (nthreads <= 0) nthreads = omp_get_max_threads();
-#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads)
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
 #endif
     for (long n = 0; n < N; n++) {
         double s0[6], u[6], rec[OR_REC], o[OR_NOUT];
@@ -357,6 +357,24 @@ int oracle_J_grad(int form, double eps, double h, long T, const double s0[6],
     *J = Jsum / (double)T;
     for (int c = 0; c < 7; c++) dJ[c] = 2.0 * dsum[c] / (double)T;
     return 0;
+}
+
+/* oracle_J_grad over orbits ic[6][N]: J[N], dJ[7][N].  OpenMP over orbits. */
+int oracle_J_grad_ensemble(int form, double eps, double h, long T, long N, const double *ic,
+                           double *J, double *dJ, int nthreads)
+{
+    int bad = 0;
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads) reduction(|:bad)
+#endif
+    for (long n = 0; n < N; n++) {
+        double s0[6], d[7];
+        for (int a = 0; a < 6; a++) s0[a] = ic[a * N + n];
+        bad |= oracle_J_grad(form, eps, h, T, s0, &J[n], d);
+        for (int c = 0; c < 7; c++) dJ[c * N + n] = d[c];
+    }
+    return bad ? -1 : 0;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -1,0 +1,208 @@
+// aw_adj.hip -- reverse-mode (adjoint) gradient of the step-averaged momentum
+// drift J = (1/T) sum_{k=1..T} |P_k - P_0|^2 with respect to the initial
+// state and eps, for the maps of aw_fwd.hip.
+//
+// Forward kernel: one lane per orbit runs the map (no tangent), accumulates J
+// and stores the state at the start of every segment of `ckpt` steps.
+// Backward kernel: one lane per orbit walks the segments from the last one;
+// for each it recomputes the segment from its checkpoint, storing the end
+// state of every step, then sweeps the steps backwards.  Inside a step the
+// stages are undone in reverse order by inverting them exactly in exact
+// arithmetic (drift: X -= t P; kick: P += t eps grad Hp(X)), starting from the
+// stored end state, while the adjoint is propagated:
+//   drift  D(t):  Pbar += t Xbar
+//   kick   K(t):  Xbar -= t eps Hess(X) Pbar,  epsbar -= t grad Hp(X) . Pbar
+// and the source of J, (2 gJ / T)(P_k - P_0), enters Pbar at every step
+// boundary k >= 1.  The explicit P_0 dependence of J adds
+// -(2 gJ / T) sum_k (P_k - P_0) to the initial-momentum gradient.
+// Each lane only reads back what it wrote itself, so no synchronisation
+// between lanes is needed.
+#include <hip/hip_runtime.h>
+
+#include "aw_device.hpp"
+#include "aw_internal.hpp"
+#include "aw_launch.hpp"
+
+namespace aw {
+
+template <int FORM>
+__device__ __forceinline__ void adj_step_fwd(Orbit &o, const AdjDesc &d) {
+  using F = FormPattern<FORM>;
+  constexpr int NK = F::NK;
+  if constexpr (F::LEAD) {
+#pragma unroll
+    for (int i = 0; i < NK; ++i) {
+      drift<false>(o, d.drift[F::drift_idx[i]]);
+      kick<false>(o, d.ka2[F::kick_idx[i]], d.ka4[F::kick_idx[i]]);
+    }
+    drift<false>(o, d.drift[F::drift_idx[NK]]);
+  } else {
+    kick<false>(o, d.ka2[0], d.ka4[0]);
+    drift<false>(o, d.drift[0]);
+  }
+}
+
+struct Adjoint {
+  double xb, yb, zb, pxb, pyb, pzb, eb;
+};
+
+// Undo D(t) on the state and apply its transpose to the adjoint.
+__device__ __forceinline__ void rev_drift(Orbit &o, Adjoint &a, double t) {
+  o.x = __builtin_fma(-t, o.px, o.x);
+  o.y = __builtin_fma(-t, o.py, o.y);
+  o.z = __builtin_fma(-t, o.pz, o.z);
+  a.pxb = __builtin_fma(t, a.xb, a.pxb);
+  a.pyb = __builtin_fma(t, a.yb, a.pyb);
+  a.pzb = __builtin_fma(t, a.zb, a.pzb);
+}
+
+// Undo K(t) on the state and apply its transpose to the adjoint.
+// a2 = 2 t eps, a4 = 4 t eps, w2 = 2 t, w4 = 4 t.
+__device__ __forceinline__ void rev_kick(Orbit &o, Adjoint &a, double a2, double a4, double w2,
+                                         double w4) {
+  const SinCos X = sincos_red(o.x), Y = sincos_red(o.y), Z = sincos_red(o.z);
+  const uint32_t sg = (X.par ^ Y.par) << 31;
+  const double cx = flip(X.c, sg), sx = flip(X.s, sg);
+  const double cy = Y.c, sy = Y.s;
+  const double cz2 = Z.c * Z.c;
+  const double czsz = Z.c * Z.s;
+  const double c2z = __builtin_fma(-Z.s, Z.s, cz2);
+  const double psc = sx * cy, pcs = cx * sy, pcc = cx * cy, pss = sx * sy;
+  const double e1 = a2 * cz2, e2 = a4 * czsz, e3 = a4 * c2z;
+  const double f1 = w2 * cz2, f2 = w4 * czsz;
+  // d(P after kick)/d eps = -t grad Hp = (f1 psc, f1 pcs, f2 pcc).
+  a.eb = __builtin_fma(f1, __builtin_fma(psc, a.pxb, pcs * a.pyb), a.eb);
+  a.eb = __builtin_fma(f2 * pcc, a.pzb, a.eb);
+  // Xbar += (-t eps Hess) Pbar, the same symmetric matrix as the tangent kick.
+  const double mxx = e1 * pcc, nxy = e1 * pss, nxz = e2 * psc, nyz = e2 * pcs, mzz = e3 * pcc;
+  const double pxb = a.pxb, pyb = a.pyb, pzb = a.pzb;
+  a.xb = __builtin_fma(mxx, pxb, a.xb);
+  a.xb = __builtin_fma(-nxy, pyb, a.xb);
+  a.xb = __builtin_fma(-nxz, pzb, a.xb);
+  a.yb = __builtin_fma(-nxy, pxb, a.yb);
+  a.yb = __builtin_fma(mxx, pyb, a.yb);
+  a.yb = __builtin_fma(-nyz, pzb, a.yb);
+  a.zb = __builtin_fma(-nxz, pxb, a.zb);
+  a.zb = __builtin_fma(-nyz, pyb, a.zb);
+  a.zb = __builtin_fma(mzz, pzb, a.zb);
+  // P before the kick.
+  o.px = __builtin_fma(-e1, psc, o.px);
+  o.py = __builtin_fma(-e1, pcs, o.py);
+  o.pz = __builtin_fma(-e2, pcc, o.pz);
+}
+
+template <int FORM>
+__device__ __forceinline__ void adj_step_rev(Orbit &o, Adjoint &a, const AdjDesc &d) {
+  using F = FormPattern<FORM>;
+  constexpr int NK = F::NK;
+  if constexpr (F::LEAD) {
+    rev_drift(o, a, d.drift[F::drift_idx[NK]]);
+#pragma unroll
+    for (int i = NK - 1; i >= 0; --i) {
+      const int u = F::kick_idx[i];
+      rev_kick(o, a, d.ka2[u], d.ka4[u], d.kw2[u], d.kw4[u]);
+      rev_drift(o, a, d.drift[F::drift_idx[i]]);
+    }
+  } else {
+    rev_drift(o, a, d.drift[0]);
+    rev_kick(o, a, d.ka2[0], d.ka4[0], d.kw2[0], d.kw4[0]);
+  }
+}
+
+__device__ __forceinline__ void load6(const double *p, int64_t N, int64_t n, Orbit &o) {
+  o.x = p[0 * N + n]; o.y = p[1 * N + n]; o.z = p[2 * N + n];
+  o.px = p[3 * N + n]; o.py = p[4 * N + n]; o.pz = p[5 * N + n];
+}
+
+__device__ __forceinline__ void store6(double *p, int64_t N, int64_t n, const Orbit &o) {
+  p[0 * N + n] = o.x; p[1 * N + n] = o.y; p[2 * N + n] = o.z;
+  p[3 * N + n] = o.px; p[4 * N + n] = o.py; p[5 * N + n] = o.pz;
+}
+
+template <int FORM>
+__global__ __launch_bounds__(256) void k_adj_fwd(AdjDesc d) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= d.N) return;
+  Orbit o;
+  load6(d.ic, d.N, n, o);
+  o.p0x = o.px; o.p0y = o.py; o.p0z = o.pz;
+  o.jsum = 0.0;
+  for (int64_t s = 0; s < d.n_seg; ++s) {
+    store6(d.ckpts + s * 6 * d.N, d.N, n, o);
+    const int64_t g0 = s * d.ckpt;
+    const int64_t g1 = g0 + d.ckpt < d.T ? g0 + d.ckpt : d.T;
+    for (int64_t g = g0; g < g1; ++g) {
+      adj_step_fwd<FORM>(o, d);
+      accum_j(o);
+    }
+  }
+  if (d.J) d.J[n] = o.jsum / (double)d.T;
+}
+
+template <int FORM>
+__global__ __launch_bounds__(256) void k_adj_bwd(AdjDesc d) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= d.N) return;
+  const int64_t N = d.N;
+  const double p0x = d.ic[3 * N + n], p0y = d.ic[4 * N + n], p0z = d.ic[5 * N + n];
+  const double c = 2.0 * (d.gJ ? d.gJ[n] : 1.0) / (double)d.T;
+  Adjoint a{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double sx = 0.0, sy = 0.0, sz = 0.0;  // sum_k (P_k - P_0)
+  Orbit o;
+  o.p0x = p0x; o.p0y = p0y; o.p0z = p0z;
+  o.jsum = 0.0;
+  o.kexp = 0;
+  for (int64_t s = d.n_seg - 1; s >= 0; --s) {
+    const int64_t g0 = s * d.ckpt;
+    const int64_t g1 = g0 + d.ckpt < d.T ? g0 + d.ckpt : d.T;
+    load6(d.ckpts + s * 6 * N, N, n, o);
+    for (int64_t g = g0; g < g1; ++g) {
+      adj_step_fwd<FORM>(o, d);
+      store6(d.steps + (g - g0) * 6 * N, N, n, o);
+    }
+    for (int64_t g = g1 - 1; g >= g0; --g) {
+      load6(d.steps + (g - g0) * 6 * N, N, n, o);   // state after step g
+      const double ex = o.px - p0x, ey = o.py - p0y, ez = o.pz - p0z;
+      a.pxb = __builtin_fma(c, ex, a.pxb);
+      a.pyb = __builtin_fma(c, ey, a.pyb);
+      a.pzb = __builtin_fma(c, ez, a.pzb);
+      sx += ex; sy += ey; sz += ez;
+      adj_step_rev<FORM>(o, a, d);
+    }
+  }
+  d.gic[0 * N + n] = a.xb;
+  d.gic[1 * N + n] = a.yb;
+  d.gic[2 * N + n] = a.zb;
+  d.gic[3 * N + n] = __builtin_fma(-c, sx, a.pxb);
+  d.gic[4 * N + n] = __builtin_fma(-c, sy, a.pyb);
+  d.gic[5 * N + n] = __builtin_fma(-c, sz, a.pzb);
+  d.geps[n] = a.eb;
+}
+
+hipError_t launch_adj_forward(const AdjDesc &d, int form, const Tuning &t, hipStream_t s) {
+  if (d.N <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((d.N + t.block - 1) / t.block);
+  switch (form) {
+  case 1: hipLaunchKernelGGL(k_adj_fwd<1>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  case 2: hipLaunchKernelGGL(k_adj_fwd<2>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  case 4: hipLaunchKernelGGL(k_adj_fwd<4>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  case 6: hipLaunchKernelGGL(k_adj_fwd<6>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_backward(const AdjDesc &d, int form, const Tuning &t, hipStream_t s) {
+  if (d.N <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((d.N + t.block - 1) / t.block);
+  switch (form) {
+  case 1: hipLaunchKernelGGL(k_adj_bwd<1>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  case 2: hipLaunchKernelGGL(k_adj_bwd<2>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  case 4: hipLaunchKernelGGL(k_adj_bwd<4>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  case 6: hipLaunchKernelGGL(k_adj_bwd<6>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace aw

@@ -1,0 +1,837 @@
+// aw_api.hip -- the C ABI of libaw (declared in include/aw.h): argument
+// validation, stage-weight set-up, library scratch, batching, HIP graphs and
+// kernel timing.  Every numerical step runs in the kernels of aw_fwd.hip,
+// aw_hist.hip and aw_adj.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "aw.h"
+#include "aw_internal.hpp"
+#include "aw_launch.hpp"
+
+using namespace aw;
+
+namespace {
+
+thread_local std::string g_err;
+
+aw_status fail(aw_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+aw_status hip_fail(hipError_t e, const char *what) {
+  return fail(AW_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// Library scratch per device (grow-only).
+// ---------------------------------------------------------------------------
+struct Buf {
+  void *p = nullptr;
+  size_t n = 0;
+};
+
+struct DevScratch {
+  Buf bins, vals, block_counts, block_dropped, tile_start, sorted_local, sorted_val;
+  Buf descs, items, head;
+  void *stage = nullptr;  // pinned host staging of batch tables
+  size_t stage_n = 0;
+  hipEvent_t stage_done = nullptr;
+};
+
+std::mutex g_mu;
+std::map<int, DevScratch> g_scratch;
+
+hipError_t grow(Buf &b, size_t need) {
+  if (need == 0) need = 256;
+  if (b.n >= need) return hipSuccess;
+  if (b.p) {
+    hipError_t e = hipFree(b.p);
+    if (e != hipSuccess) return e;
+    b.p = nullptr;
+    b.n = 0;
+  }
+  size_t n = need + need / 4;
+  hipError_t e = hipMalloc(&b.p, n);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return e;
+  }
+  b.n = n;
+  return hipSuccess;
+}
+
+DevScratch &scratch() {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  return g_scratch[dev];
+}
+
+// ---------------------------------------------------------------------------
+// Kernel timing.
+// ---------------------------------------------------------------------------
+bool g_timing = false;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events;
+
+struct TimedLaunch {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipStream_t s;
+  explicit TimedLaunch(hipStream_t st) : s(st) {
+    if (!g_timing) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+      a = b = nullptr;
+      return;
+    }
+    (void)hipEventRecord(a, s);
+  }
+  ~TimedLaunch() {
+    if (!a) return;
+    (void)hipEventRecord(b, s);
+    g_events.emplace_back(a, b);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Stage weights of the map forms (merged adjacent drifts).
+// ---------------------------------------------------------------------------
+struct Stages {
+  int nk = 0, nd = 0;
+  double kick[MAX_KICKS];
+  double drift[MAX_DRIFTS];
+};
+
+Stages stages_of(int form) {
+  Stages s;
+  auto from_kicks = [&](const double *w, int nk) {
+    s.nk = nk;
+    s.nd = nk + 1;
+    for (int i = 0; i < nk; ++i) s.kick[i] = w[i];
+    s.drift[0] = 0.5 * w[0];
+    for (int i = 1; i < nk; ++i) s.drift[i] = 0.5 * (w[i - 1] + w[i]);
+    s.drift[nk] = 0.5 * w[nk - 1];
+  };
+  const double g1 = 1.0 / (2.0 - std::cbrt(2.0)), g0 = 1.0 - 2.0 * g1;
+  const double d1 = 1.0 / (2.0 - std::pow(2.0, 1.0 / 5.0)), d0 = 1.0 - 2.0 * d1;
+  if (form == AW_MAP_STDMAP) {
+    s.nk = 1;
+    s.nd = 1;
+    s.kick[0] = 1.0;
+    s.drift[0] = 1.0;
+  } else if (form == AW_MAP_S2) {
+    const double w[1] = {1.0};
+    from_kicks(w, 1);
+  } else if (form == AW_MAP_S4) {
+    const double w[3] = {g1, g0, g1};
+    from_kicks(w, 3);
+  } else if (form == AW_MAP_S6) {
+    const double w[9] = {g1 * d1, g0 * d1, g1 * d1, g1 * d0, g0 * d0, g1 * d0, g1 * d1, g0 * d1, g1 * d1};
+    from_kicks(w, 9);
+  }
+  return s;
+}
+
+// Compile-time stage pattern of a form (see FormPattern).
+struct Pattern {
+  int nk, nd;
+  const int *kidx, *didx;
+};
+
+Pattern pattern_of(int form) {
+  switch (form) {
+  case 1: return {FormPattern<1>::NK, FormPattern<1>::ND, FormPattern<1>::kick_idx, FormPattern<1>::drift_idx};
+  case 2: return {FormPattern<2>::NK, FormPattern<2>::ND, FormPattern<2>::kick_idx, FormPattern<2>::drift_idx};
+  case 4: return {FormPattern<4>::NK, FormPattern<4>::ND, FormPattern<4>::kick_idx, FormPattern<4>::drift_idx};
+  default: return {FormPattern<6>::NK, FormPattern<6>::ND, FormPattern<6>::kick_idx, FormPattern<6>::drift_idx};
+  }
+}
+
+// Distinct stage weights (times h) of a form.  Every stage that shares an
+// index must carry bitwise the same weight; false otherwise.
+bool unique_weights(int form, double h, double kick[MAX_UNIQUE], double drift[MAX_UNIQUE]) {
+  const Stages st = stages_of(form);
+  const Pattern pt = pattern_of(form);
+  if (pt.nk != st.nk || pt.nd != st.nd) return false;
+  bool kset[MAX_UNIQUE] = {false, false, false, false}, dset[MAX_UNIQUE] = {false, false, false, false};
+  for (int i = 0; i < MAX_UNIQUE; ++i) kick[i] = drift[i] = 0.0;
+  for (int i = 0; i < st.nk; ++i) {
+    const int u = pt.kidx[i];
+    const double v = st.kick[i] * h;
+    if (kset[u] && std::memcmp(&kick[u], &v, sizeof v) != 0) return false;
+    kick[u] = v;
+    kset[u] = true;
+  }
+  for (int i = 0; i < st.nd; ++i) {
+    const int u = pt.didx[i];
+    const double v = st.drift[i] * h;
+    if (dset[u] && std::memcmp(&drift[u], &v, sizeof v) != 0) return false;
+    drift[u] = v;
+    dset[u] = true;
+  }
+  return true;
+}
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+aw_status check_tuning(const aw_tuning *t, Tuning &out) {
+  out = Tuning{};
+  if (!t) return AW_OK;
+  out.block = t->block ? t->block : 256;
+  out.opl = t->orbits_per_lane ? t->orbits_per_lane : 1;
+  out.unroll = t->unroll ? t->unroll : 1;
+  out.renorm = t->renorm_every ? t->renorm_every : 8;
+  out.pwgs = t->persistent_wgs;
+  if (out.block != 64 && out.block != 128 && out.block != 256)
+    return fail(AW_EINVAL, "tuning.block must be 64, 128 or 256 (got %d)", out.block);
+  if (out.opl != 1 && out.opl != 2) return fail(AW_EINVAL, "tuning.orbits_per_lane must be 1 or 2");
+  if (out.unroll != 1 && out.unroll != 2) return fail(AW_EINVAL, "tuning.unroll must be 1 or 2");
+  if (out.renorm < 1 || out.renorm > 16 || (out.renorm & (out.renorm - 1)))
+    return fail(AW_EINVAL, "tuning.renorm_every must be 1, 2, 4, 8 or 16");
+  if (out.pwgs < 0) return fail(AW_EINVAL, "tuning.persistent_wgs must be >= 0");
+  return AW_OK;
+}
+
+int64_t ens_size(const aw_ensemble &e) {
+  if (e.ic_kind == AW_IC_GRID2) {
+    if (e.nx < 1 || e.ny < 1 || e.nx > (int64_t(1) << 31) || e.ny > (int64_t(1) << 31)) return -1;
+    return e.nx * e.ny;
+  }
+  return e.n_orbits >= 0 ? e.n_orbits : -1;
+}
+
+aw_status check_ensemble(const aw_ensemble *e, const double *ic, int idx) {
+  if (!e) return fail(AW_EINVAL, "ensemble %d: null descriptor", idx);
+  if (e->M != 3) return fail(AW_EUNSUPPORTED, "ensemble %d: only M = 3 is defined (got %d)", idx, e->M);
+  if (e->map_form != AW_MAP_STDMAP && e->map_form != AW_MAP_S2 && e->map_form != AW_MAP_S4 &&
+      e->map_form != AW_MAP_S6)
+    return fail(AW_EINVAL, "ensemble %d: unknown map_form %d", idx, e->map_form);
+  if (!is_fin(e->eps)) return fail(AW_EINVAL, "ensemble %d: eps must be finite", idx);
+  if (!is_fin(e->h) || e->h == 0.0) return fail(AW_EINVAL, "ensemble %d: h must be finite and non-zero", idx);
+  if (e->n_steps < 1) return fail(AW_EINVAL, "ensemble %d: n_steps must be >= 1", idx);
+  if (e->flags & ~AW_F_TANGENT) return fail(AW_EINVAL, "ensemble %d: unknown flags 0x%x", idx, e->flags);
+  {
+    double k[MAX_UNIQUE], dr[MAX_UNIQUE];
+    if (!unique_weights(e->map_form, e->h, k, dr))
+      return fail(AW_EUNSUPPORTED, "ensemble %d: stage weights do not follow the form's pattern", idx);
+  }
+  if (std::isnan(e->chi_threshold)) return fail(AW_EINVAL, "ensemble %d: chi_threshold is NaN", idx);
+  const int64_t N = ens_size(*e);
+  if (N < 0) return fail(AW_EINVAL, "ensemble %d: bad size (nx, ny or n_orbits)", idx);
+  if (N > (int64_t(1) << 31) - 1) return fail(AW_EINVAL, "ensemble %d: more than 2^31-1 orbits", idx);
+  switch (e->ic_kind) {
+  case AW_IC_GRID2:
+    if (e->axis[0] < 0 || e->axis[0] > 5 || e->axis[1] < 0 || e->axis[1] > 5 || e->axis[0] == e->axis[1])
+      return fail(AW_EINVAL, "ensemble %d: GRID2 axes must be distinct and in 0..5", idx);
+    for (int k = 0; k < 2; ++k)
+      if (!is_fin(e->lo[k]) || !is_fin(e->hi[k])) return fail(AW_EINVAL, "ensemble %d: GRID2 range not finite", idx);
+    for (int k = 0; k < 6; ++k)
+      if (!is_fin(e->base[k])) return fail(AW_EINVAL, "ensemble %d: GRID2 base not finite", idx);
+    break;
+  case AW_IC_BOX:
+    for (int k = 0; k < 6; ++k)
+      if (!is_fin(e->box_lo[k]) || !is_fin(e->box_hi[k]) || !is_fin(e->box_hi[k] - e->box_lo[k]))
+        return fail(AW_EINVAL, "ensemble %d: BOX range not finite", idx);
+    break;
+  case AW_IC_EXPLICIT:
+    if (N > 0 && !ic) return fail(AW_EINVAL, "ensemble %d: EXPLICIT needs ic_dev", idx);
+    break;
+  default:
+    return fail(AW_EINVAL, "ensemble %d: unknown ic_kind %d", idx, e->ic_kind);
+  }
+  return AW_OK;
+}
+
+FwdDesc make_desc(const aw_ensemble &e, const double *ic, const Tuning &t) {
+  FwdDesc d;
+  std::memset(&d, 0, sizeof d);
+  double tau[MAX_UNIQUE];
+  (void)unique_weights(e.map_form, e.h, tau, d.drift);  // checked by check_ensemble
+  for (int u = 0; u < MAX_UNIQUE; ++u) {
+    d.ka2[u] = 2.0 * tau[u] * e.eps;
+    d.ka4[u] = 4.0 * tau[u] * e.eps;
+  }
+  d.eps = e.eps;
+  d.th = (double)e.n_steps * e.h;
+  d.lth = std::log(1.0 + d.th);
+  d.chi_thr = e.chi_threshold;
+  d.T = e.n_steps;
+  d.k_begin = 0;
+  d.k_end = e.n_steps;
+  d.N = ens_size(e);
+  d.ic_kind = e.ic_kind;
+  d.ax0 = e.axis[0];
+  d.ax1 = e.axis[1];
+  d.renorm_mask = t.renorm - 1;
+  if (e.ic_kind == AW_IC_GRID2) {
+    d.nx = e.nx;
+    d.lo0 = e.lo[0];
+    d.lo1 = e.lo[1];
+    d.d0 = (e.hi[0] - e.lo[0]) / (double)e.nx;
+    d.d1 = (e.hi[1] - e.lo[1]) / (double)e.ny;
+    for (int k = 0; k < 6; ++k) d.base[k] = e.base[k];
+  } else {
+    d.nx = 1;
+  }
+  for (int k = 0; k < 6; ++k) {
+    d.box_lo[k] = e.box_lo[k];
+    d.box_span[k] = e.box_hi[k] - e.box_lo[k];
+  }
+  d.seed_ic = e.seed_ic;
+  d.seed_tan = e.seed_tangent;
+  d.ic = ic;
+  d.epi = EPI_NONE;
+  return d;
+}
+
+bool tangent_on(const aw_ensemble &e) { return (e.flags & AW_F_TANGENT) != 0; }
+
+aw_status launch_one(const FwdDesc &d, const Tuning &t, int form, bool tan, hipStream_t s) {
+  hipError_t err;
+  {
+    TimedLaunch tl(s);
+    err = launch_fwd(d, t, form, tan, s);
+  }
+  if (err != hipSuccess) return hip_fail(err, "propagation launch");
+  return AW_OK;
+}
+
+// Batched persistent launch of descs (host copies) over n ensembles.
+struct BatchTables {
+  std::vector<WorkItem> items;
+  int form = 6;
+  bool tan = true;
+};
+
+BatchTables make_items(const std::vector<FwdDesc> &descs, const Tuning &t) {
+  BatchTables b;
+  const int64_t per = (int64_t)t.block * t.opl;
+  for (size_t e = 0; e < descs.size(); ++e)
+    for (int64_t f = 0; f < descs[e].N; f += per) b.items.push_back(WorkItem{(int32_t)e, 0, f});
+  // Longest processing time first: a tile's cost is its step count.
+  std::stable_sort(b.items.begin(), b.items.end(), [&](const WorkItem &a, const WorkItem &c) {
+    return descs[a.ens].T > descs[c.ens].T;
+  });
+  return b;
+}
+
+int persistent_wgs(int form, bool tan, const Tuning &t) {
+  if (t.pwgs > 0) return t.pwgs;
+  int dev = 0, ncu = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+    ncu = 256;
+  return ncu * persistent_blocks_per_cu(form, tan, t);
+}
+
+aw_status upload_tables(DevScratch &sc, const std::vector<FwdDesc> &descs, const std::vector<WorkItem> &items,
+                        hipStream_t s) {
+  const size_t bd = descs.size() * sizeof(FwdDesc), bi = items.size() * sizeof(WorkItem);
+  hipError_t e;
+  if ((e = grow(sc.descs, bd)) != hipSuccess || (e = grow(sc.items, bi)) != hipSuccess ||
+      (e = grow(sc.head, 256)) != hipSuccess)
+    return fail(AW_ENOMEM, "batch tables: %s", hipGetErrorString(e));
+  if (!sc.stage_done && (e = hipEventCreateWithFlags(&sc.stage_done, hipEventDisableTiming)) != hipSuccess)
+    return hip_fail(e, "hipEventCreate");
+  // The pinned staging buffer may still feed the previous batch's copy.
+  if ((e = hipEventSynchronize(sc.stage_done)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  if (sc.stage_n < bd + bi) {
+    if (sc.stage) (void)hipHostFree(sc.stage);
+    sc.stage = nullptr;
+    sc.stage_n = 0;
+    if ((e = hipHostMalloc(&sc.stage, bd + bi, hipHostMallocDefault)) != hipSuccess)
+      return fail(AW_ENOMEM, "pinned staging: %s", hipGetErrorString(e));
+    sc.stage_n = bd + bi;
+  }
+  std::memcpy(sc.stage, descs.data(), bd);
+  std::memcpy((char *)sc.stage + bd, items.data(), bi);
+  if ((e = hipMemcpyAsync(sc.descs.p, sc.stage, bd, hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(sc.items.p, (char *)sc.stage + bd, bi, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_fail(e, "batch table upload");
+  if ((e = hipEventRecord(sc.stage_done, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  return AW_OK;
+}
+
+aw_status launch_batched_tables(const FwdDesc *descs_dev, const WorkItem *items_dev, int32_t n_items,
+                                uint32_t *head, const Tuning &t, int form, bool tan, hipStream_t s) {
+  const int nwg = std::max(1, std::min<int>(persistent_wgs(form, tan, t), n_items));
+  hipError_t err;
+  {
+    TimedLaunch tl(s);
+    err = launch_fwd_batched(descs_dev, items_dev, n_items, head, t, form, tan, nwg, s);
+  }
+  if (err != hipSuccess) return hip_fail(err, "persistent launch");
+  return AW_OK;
+}
+
+aw_status validate_batch(const aw_ensemble *ens, int32_t n_ens, const double *const *ic_dev) {
+  if (!ens || n_ens < 1) return fail(AW_EINVAL, "need n_ens >= 1 descriptors");
+  for (int e = 0; e < n_ens; ++e) {
+    aw_status st = check_ensemble(&ens[e], ic_dev ? ic_dev[e] : nullptr, e);
+    if (st != AW_OK) return st;
+    if (ens[e].map_form != ens[0].map_form || ens[e].flags != ens[0].flags)
+      return fail(AW_EINVAL, "batched ensembles must share map_form and flags (ensemble %d differs)", e);
+  }
+  return AW_OK;
+}
+
+// Image spec checks; fills the epilogue fields of d.
+aw_status apply_image(const aw_image_spec *sp, const aw_ensemble &e, int idx, FwdDesc &d, double *img,
+                      uint32_t *cnt) {
+  if (!sp) return fail(AW_EINVAL, "null image spec");
+  if (sp->W < 1 || sp->H < 1) return fail(AW_EINVAL, "image W, H must be >= 1");
+  if (!img) return fail(AW_EINVAL, "ensemble %d: null image buffer", idx);
+  d.W = sp->W;
+  d.H = sp->H;
+  d.field = sp->field;
+  switch (sp->kind) {
+  case AW_IMG_IC_GRID:
+    if (e.ic_kind != AW_IC_GRID2) return fail(AW_EINVAL, "ensemble %d: IC_GRID images need a GRID2 ensemble", idx);
+    if (sp->W != e.nx || sp->H != e.ny) return fail(AW_EINVAL, "ensemble %d: IC_GRID needs W = nx, H = ny", idx);
+    if (sp->field < 0 || sp->field >= AW_NOUT) return fail(AW_EINVAL, "image field out of range");
+    d.epi = EPI_IC_GRID;
+    d.img = img;
+    d.n_class = cnt;
+    break;
+  case AW_IMG_HIST_P0:
+    if (sp->field < 0 || sp->field >= AW_NOUT) return fail(AW_EINVAL, "image field out of range");
+    if (sp->key_axis[0] < 0 || sp->key_axis[0] > 5 || sp->key_axis[1] < 0 || sp->key_axis[1] > 5)
+      return fail(AW_EINVAL, "HIST_P0 key axes must be in 0..5");
+    if (!(sp->lo[0] < sp->hi[0]) || !(sp->lo[1] < sp->hi[1]) || !is_fin(sp->hi[0] - sp->lo[0]) ||
+        !is_fin(sp->hi[1] - sp->lo[1]))
+      return fail(AW_EINVAL, "HIST_P0 ranges must satisfy lo < hi");
+    d.epi = EPI_HIST_P0;
+    d.key0 = sp->key_axis[0];
+    d.key1 = sp->key_axis[1];
+    d.klo0 = sp->lo[0];
+    d.khi0 = sp->hi[0];
+    d.klo1 = sp->lo[1];
+    d.khi1 = sp->hi[1];
+    break;
+  case AW_IMG_HIST_VDIR:
+    d.epi = EPI_HIST_VDIR;
+    break;
+  default:
+    return fail(AW_EINVAL, "unknown image kind %d", sp->kind);
+  }
+  if (sp->kind != AW_IMG_IC_GRID) {
+    const HistPlan p = hist_plan(d.N, sp->W, sp->H);
+    if (p.n_tiles > MAX_TILES) return fail(AW_EINVAL, "image too large: %d tiles (max %d)", p.n_tiles, MAX_TILES);
+    if ((int64_t)p.n_tiles * p.G > (int64_t(1) << 30)) return fail(AW_EINVAL, "image x ensemble too large");
+  }
+  return AW_OK;
+}
+
+aw_status hist_scratch(DevScratch &sc, const HistPlan &p, int64_t n_items, bool want_vals, HistScratch &w) {
+  hipError_t e;
+  if ((e = grow(sc.block_counts, p.bytes_block_counts)) != hipSuccess ||
+      (e = grow(sc.block_dropped, p.bytes_block_dropped)) != hipSuccess ||
+      (e = grow(sc.tile_start, p.bytes_tile_start)) != hipSuccess ||
+      (e = grow(sc.sorted_local, sizeof(uint16_t) * (size_t)std::max<int64_t>(n_items, 1))) != hipSuccess ||
+      (want_vals && (e = grow(sc.sorted_val, sizeof(double) * (size_t)std::max<int64_t>(n_items, 1))) != hipSuccess))
+    return fail(AW_ENOMEM, "histogram scratch: %s", hipGetErrorString(e));
+  w.block_counts = (uint32_t *)sc.block_counts.p;
+  w.block_dropped = (uint32_t *)sc.block_dropped.p;
+  w.tile_start = (uint32_t *)sc.tile_start.p;
+  w.sorted_local = (uint16_t *)sc.sorted_local.p;
+  w.sorted_val = want_vals ? (double *)sc.sorted_val.p : nullptr;
+  return AW_OK;
+}
+
+// Propagate n ensembles with image epilogues and run the reductions.
+// bins/vals point into one scratch area, offset per ensemble.
+aw_status image_run(const aw_ensemble *ens, int32_t n_ens, const aw_image_spec *spec, double *const *image,
+                    uint32_t *const *counts, uint8_t *const *cls, const Tuning &t, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  DevScratch &sc = scratch();
+  std::vector<FwdDesc> descs(n_ens);
+  std::vector<int64_t> off(n_ens + 1, 0);
+  for (int e = 0; e < n_ens; ++e) {
+    descs[e] = make_desc(ens[e], nullptr, t);
+    off[e + 1] = off[e] + descs[e].N;
+  }
+  const bool hist = spec->kind != AW_IMG_IC_GRID;
+  hipError_t herr;
+  if (hist) {
+    if ((herr = grow(sc.bins, sizeof(uint32_t) * (size_t)off[n_ens])) != hipSuccess ||
+        (spec->kind == AW_IMG_HIST_P0 && (herr = grow(sc.vals, sizeof(double) * (size_t)off[n_ens])) != hipSuccess))
+      return fail(AW_ENOMEM, "image scratch: %s", hipGetErrorString(herr));
+  }
+  for (int e = 0; e < n_ens; ++e) {
+    aw_status st = apply_image(spec, ens[e], e, descs[e], image[e], counts ? counts[e] : nullptr);
+    if (st != AW_OK) return st;
+    descs[e].cls = cls ? cls[e] : nullptr;
+    if (hist) {
+      descs[e].bins = (uint32_t *)sc.bins.p + off[e];
+      descs[e].vals = spec->kind == AW_IMG_HIST_P0 ? (double *)sc.vals.p + off[e] : nullptr;
+    }
+    if (descs[e].epi == EPI_IC_GRID && descs[e].n_class) {
+      if ((herr = launch_zero_u32(descs[e].n_class, 1, s)) != hipSuccess) return hip_fail(herr, "zero counter");
+    }
+  }
+  const int form = ens[0].map_form;
+  const bool tan = tangent_on(ens[0]);
+  aw_status st;
+  if (n_ens == 1) {
+    st = launch_one(descs[0], t, form, tan, s);
+  } else {
+    BatchTables b = make_items(descs, t);
+    st = upload_tables(sc, descs, b.items, s);
+    if (st == AW_OK)
+      st = launch_batched_tables((const FwdDesc *)sc.descs.p, (const WorkItem *)sc.items.p, (int32_t)b.items.size(),
+                                 (uint32_t *)sc.head.p, t, form, tan, s);
+  }
+  if (st != AW_OK) return st;
+  if (!hist) return AW_OK;
+  for (int e = 0; e < n_ens; ++e) {
+    const HistPlan p = hist_plan(descs[e].N, spec->W, spec->H);
+    HistScratch w;
+    st = hist_scratch(sc, p, descs[e].N, spec->kind == AW_IMG_HIST_P0, w);
+    if (st != AW_OK) return st;
+    const int mode = spec->kind == AW_IMG_HIST_P0 ? 1 : 2;
+    const double norm = 1.0 / ((double)descs[e].N * (2.0 * M_PI / spec->W) * (2.0 / spec->H));
+    herr = launch_hist_reduce(descs[e].N, descs[e].bins, descs[e].vals, p, w, mode, norm,
+                              counts ? counts[e] : nullptr, image[e], nullptr, s);
+    if (herr != hipSuccess) return hip_fail(herr, "histogram reduction");
+  }
+  return AW_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *aw_last_error(void) { return g_err.c_str(); }
+
+const char *aw_version(void) { return "libaw 0.1 (gfx950, FP64)"; }
+
+aw_status aw_release(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  auto it = g_scratch.find(dev);
+  if (it == g_scratch.end()) return AW_OK;
+  (void)hipDeviceSynchronize();
+  DevScratch &sc = it->second;
+  Buf *bufs[] = {&sc.bins, &sc.vals, &sc.block_counts, &sc.block_dropped, &sc.tile_start,
+                 &sc.sorted_local, &sc.sorted_val, &sc.descs, &sc.items, &sc.head};
+  for (Buf *b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  if (sc.stage) (void)hipHostFree(sc.stage);
+  if (sc.stage_done) (void)hipEventDestroy(sc.stage_done);
+  g_scratch.erase(it);
+  return AW_OK;
+}
+
+int64_t aw_ensemble_size(const aw_ensemble *ens) {
+  if (!ens) return -1;
+  return ens_size(*ens);
+}
+
+aw_status aw_generate_ic(const aw_ensemble *ens, const double *ic_in_dev, double *ic_dev, double *w0_dev,
+                         void *stream) {
+  aw_status st = check_ensemble(ens, ic_in_dev, 0);
+  if (st != AW_OK) return st;
+  const FwdDesc d = make_desc(*ens, ic_in_dev, Tuning{});
+  hipError_t e = launch_gen_ic(d, ic_dev, w0_dev, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "initial-condition launch");
+  return AW_OK;
+}
+
+aw_status aw_map_ensemble(const aw_ensemble *ens, int32_t n_ens, const double *const *ic_dev,
+                          double *const *orbit_out_dev, double *const *state_out_dev, uint8_t *const *cls_dev,
+                          const aw_tuning *tuning, void *stream) {
+  aw_status st = validate_batch(ens, n_ens, ic_dev);
+  if (st != AW_OK) return st;
+  Tuning t;
+  if ((st = check_tuning(tuning, t)) != AW_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<FwdDesc> descs(n_ens);
+  for (int e = 0; e < n_ens; ++e) {
+    descs[e] = make_desc(ens[e], ic_dev ? ic_dev[e] : nullptr, t);
+    descs[e].out = orbit_out_dev ? orbit_out_dev[e] : nullptr;
+    descs[e].state = state_out_dev ? state_out_dev[e] : nullptr;
+    descs[e].cls = cls_dev ? cls_dev[e] : nullptr;
+  }
+  const int form = ens[0].map_form;
+  const bool tan = tangent_on(ens[0]);
+  if (n_ens == 1) return launch_one(descs[0], t, form, tan, s);
+  std::lock_guard<std::mutex> lk(g_mu);
+  DevScratch &sc = scratch();
+  BatchTables b = make_items(descs, t);
+  if (b.items.empty()) return AW_OK;
+  if ((st = upload_tables(sc, descs, b.items, s)) != AW_OK) return st;
+  return launch_batched_tables((const FwdDesc *)sc.descs.p, (const WorkItem *)sc.items.p, (int32_t)b.items.size(),
+                               (uint32_t *)sc.head.p, t, form, tan, s);
+}
+
+aw_status aw_map_ensemble_steps(const aw_ensemble *ens, const double *ic_dev, double *carry_dev, int64_t k_begin,
+                                int64_t k_end, double *orbit_out_dev, double *state_out_dev, uint8_t *cls_dev,
+                                const aw_tuning *tuning, void *stream) {
+  aw_status st = check_ensemble(ens, ic_dev, 0);
+  if (st != AW_OK) return st;
+  Tuning t;
+  if ((st = check_tuning(tuning, t)) != AW_OK) return st;
+  if (k_begin < 0 || k_end <= k_begin || k_end > ens->n_steps)
+    return fail(AW_EINVAL, "need 0 <= k_begin < k_end <= n_steps");
+  if (!carry_dev && (k_begin > 0 || k_end < ens->n_steps))
+    return fail(AW_EINVAL, "a partial range needs carry_dev");
+  FwdDesc d = make_desc(*ens, ic_dev, t);
+  d.k_begin = k_begin;
+  d.k_end = k_end;
+  d.carry = carry_dev;
+  d.out = orbit_out_dev;
+  d.state = state_out_dev;
+  d.cls = cls_dev;
+  return launch_one(d, t, ens->map_form, tangent_on(*ens), (hipStream_t)stream);
+}
+
+aw_status aw_indicator_image(const aw_ensemble *ens, int32_t n_ens, const aw_image_spec *spec,
+                             double *const *image_dev, uint32_t *const *counts_dev, uint8_t *const *cls_dev,
+                             const aw_tuning *tuning, void *stream) {
+  aw_status st = validate_batch(ens, n_ens, nullptr);
+  if (st != AW_OK) return st;
+  if (!spec) return fail(AW_EINVAL, "null image spec");
+  if (!image_dev) return fail(AW_EINVAL, "null image array");
+  for (int e = 0; e < n_ens; ++e)
+    if (ens[e].ic_kind == AW_IC_EXPLICIT)
+      return fail(AW_EINVAL, "aw_indicator_image generates its initial conditions (GRID2 or BOX)");
+  Tuning t;
+  if ((st = check_tuning(tuning, t)) != AW_OK) return st;
+  return image_run(ens, n_ens, spec, image_dev, counts_dev, cls_dev, t, (hipStream_t)stream);
+}
+
+aw_status aw_histogram2d(int64_t N, const double *a_dev, const double *b_dev, const double *v_dev, double lo0,
+                         double hi0, double lo1, double hi1, int32_t W, int32_t H, int32_t closed_upper,
+                         uint32_t *counts_dev, double *sums_dev, uint64_t *dropped_dev, void *stream) {
+  if (N < 0 || N > (int64_t(1) << 31) - 1) return fail(AW_EINVAL, "N out of range");
+  if (W < 1 || H < 1) return fail(AW_EINVAL, "W, H must be >= 1");
+  if (!(lo0 < hi0) || !(lo1 < hi1) || !is_fin(hi0 - lo0) || !is_fin(hi1 - lo1))
+    return fail(AW_EINVAL, "ranges must satisfy lo < hi");
+  if (N > 0 && (!a_dev || !b_dev)) return fail(AW_EINVAL, "null key arrays");
+  if (!counts_dev) return fail(AW_EINVAL, "null counts");
+  const HistPlan p = hist_plan(N, W, H);
+  if (p.n_tiles > MAX_TILES) return fail(AW_EINVAL, "image too large: %d tiles (max %d)", p.n_tiles, MAX_TILES);
+  std::lock_guard<std::mutex> lk(g_mu);
+  DevScratch &sc = scratch();
+  hipError_t e;
+  if ((e = grow(sc.bins, sizeof(uint32_t) * (size_t)std::max<int64_t>(N, 1))) != hipSuccess ||
+      (v_dev && (e = grow(sc.vals, sizeof(double) * (size_t)std::max<int64_t>(N, 1))) != hipSuccess))
+    return fail(AW_ENOMEM, "histogram scratch: %s", hipGetErrorString(e));
+  HistScratch w;
+  aw_status st = hist_scratch(sc, p, N, v_dev != nullptr, w);
+  if (st != AW_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  double *vals = v_dev ? (double *)sc.vals.p : nullptr;
+  if ((e = launch_hist_bins(N, a_dev, b_dev, v_dev, lo0, hi0, lo1, hi1, W, H, closed_upper, (uint32_t *)sc.bins.p,
+                            vals, s)) != hipSuccess)
+    return hip_fail(e, "histogram bins");
+  if ((e = launch_hist_reduce(N, (uint32_t *)sc.bins.p, vals, p, w, 0, 1.0, counts_dev, v_dev ? sums_dev : nullptr,
+                              dropped_dev, s)) != hipSuccess)
+    return hip_fail(e, "histogram reduction");
+  return AW_OK;
+}
+
+aw_status aw_vdir_keys(int64_t N, const double *V_dev, double *phi_dev, double *mu_dev, void *stream) {
+  if (N < 0) return fail(AW_EINVAL, "N < 0");
+  if (N > 0 && (!V_dev || !phi_dev || !mu_dev)) return fail(AW_EINVAL, "null array");
+  hipError_t e = launch_vdir_keys(N, V_dev, phi_dev, mu_dev, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "vdir launch");
+  return AW_OK;
+}
+
+aw_status aw_indicator_grad_workspace(const aw_ensemble *ens, int64_t ckpt_every, size_t *bytes) {
+  if (!bytes) return fail(AW_EINVAL, "null bytes");
+  if (!ens) return fail(AW_EINVAL, "null ensemble");
+  if (ckpt_every < 1) return fail(AW_EINVAL, "ckpt_every must be >= 1");
+  if (ens->n_steps < 1) return fail(AW_EINVAL, "n_steps must be >= 1");
+  const int64_t N = ens_size(*ens);
+  if (N < 0) return fail(AW_EINVAL, "bad ensemble size");
+  const int64_t ck = std::min(ckpt_every, ens->n_steps);
+  const int64_t n_seg = (ens->n_steps + ck - 1) / ck;
+  *bytes = sizeof(double) * 6 * (size_t)N * (size_t)(n_seg + ck);
+  return AW_OK;
+}
+
+aw_status aw_indicator_grad(const aw_ensemble *ens, const double *ic_dev, const double *grad_J_dev,
+                            int64_t ckpt_every, double *J_out_dev, double *grad_ic_dev, double *grad_eps_dev,
+                            void *workspace_dev, size_t ws_bytes, const aw_tuning *tuning, void *stream) {
+  aw_status st = check_ensemble(ens, ic_dev, 0);
+  if (st != AW_OK) return st;
+  if (ens->ic_kind != AW_IC_EXPLICIT) return fail(AW_EINVAL, "aw_indicator_grad needs an EXPLICIT ensemble");
+  Tuning t;
+  if ((st = check_tuning(tuning, t)) != AW_OK) return st;
+  size_t need = 0;
+  if ((st = aw_indicator_grad_workspace(ens, ckpt_every, &need)) != AW_OK) return st;
+  const int64_t N = ens_size(*ens);
+  if (N > 0 && (!grad_ic_dev || !grad_eps_dev)) return fail(AW_EINVAL, "null gradient outputs");
+  if (ws_bytes < need || (N > 0 && !workspace_dev))
+    return fail(AW_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  AdjDesc d;
+  std::memset(&d, 0, sizeof d);
+  double tau[MAX_UNIQUE];
+  (void)unique_weights(ens->map_form, ens->h, tau, d.drift);
+  for (int u = 0; u < MAX_UNIQUE; ++u) {
+    d.ka2[u] = 2.0 * tau[u] * ens->eps;
+    d.ka4[u] = 4.0 * tau[u] * ens->eps;
+    d.kw2[u] = 2.0 * tau[u];
+    d.kw4[u] = 4.0 * tau[u];
+  }
+  d.eps = ens->eps;
+  d.T = ens->n_steps;
+  d.N = N;
+  d.ckpt = std::min(ckpt_every, ens->n_steps);
+  d.n_seg = (d.T + d.ckpt - 1) / d.ckpt;
+  d.ic = ic_dev;
+  d.gJ = grad_J_dev;
+  d.J = J_out_dev;
+  d.gic = grad_ic_dev;
+  d.geps = grad_eps_dev;
+  d.ckpts = (double *)workspace_dev;
+  d.steps = d.ckpts + (size_t)d.n_seg * 6 * (size_t)N;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_adj_forward(d, ens->map_form, t, s);
+  if (e != hipSuccess) return hip_fail(e, "adjoint forward launch");
+  e = launch_adj_backward(d, ens->map_form, t, s);
+  if (e != hipSuccess) return hip_fail(e, "adjoint backward launch");
+  return AW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Graphs of the batched image path.
+// ---------------------------------------------------------------------------
+struct aw_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<void *> dev_allocs;
+};
+
+aw_status aw_graph_create(const aw_ensemble *ens, int32_t n_ens, const aw_image_spec *spec, double *const *image_dev,
+                          uint32_t *const *counts_dev, uint8_t *const *cls_dev, const aw_tuning *tuning,
+                          aw_graph **out) {
+  if (!out) return fail(AW_EINVAL, "null graph handle");
+  *out = nullptr;
+  aw_status st = validate_batch(ens, n_ens, nullptr);
+  if (st != AW_OK) return st;
+  if (!spec || !image_dev) return fail(AW_EINVAL, "null image spec or array");
+  if (spec->kind != AW_IMG_IC_GRID) return fail(AW_EUNSUPPORTED, "graphs are built for IC_GRID images");
+  for (int e = 0; e < n_ens; ++e)
+    if (ens[e].ic_kind == AW_IC_EXPLICIT) return fail(AW_EINVAL, "graph ensembles generate their initial conditions");
+  Tuning t;
+  if ((st = check_tuning(tuning, t)) != AW_OK) return st;
+  std::vector<FwdDesc> descs(n_ens);
+  for (int e = 0; e < n_ens; ++e) {
+    descs[e] = make_desc(ens[e], nullptr, t);
+    if ((st = apply_image(spec, ens[e], e, descs[e], image_dev[e], counts_dev ? counts_dev[e] : nullptr)) != AW_OK)
+      return st;
+    descs[e].cls = cls_dev ? cls_dev[e] : nullptr;
+  }
+  BatchTables b = make_items(descs, t);
+  aw_graph *g = new aw_graph();
+  auto cleanup = [&](aw_status s2) {
+    aw_graph_destroy(g);
+    return s2;
+  };
+  void *dd = nullptr, *di = nullptr, *dh = nullptr;
+  hipError_t e;
+  if ((e = hipMalloc(&dd, std::max<size_t>(1, descs.size() * sizeof(FwdDesc)))) != hipSuccess)
+    return cleanup(fail(AW_ENOMEM, "graph tables: %s", hipGetErrorString(e)));
+  g->dev_allocs.push_back(dd);
+  if ((e = hipMalloc(&di, std::max<size_t>(1, b.items.size() * sizeof(WorkItem)))) != hipSuccess)
+    return cleanup(fail(AW_ENOMEM, "graph tables: %s", hipGetErrorString(e)));
+  g->dev_allocs.push_back(di);
+  if ((e = hipMalloc(&dh, 256)) != hipSuccess) return cleanup(fail(AW_ENOMEM, "graph tables: %s", hipGetErrorString(e)));
+  g->dev_allocs.push_back(dh);
+  if ((e = hipMemcpy(dd, descs.data(), descs.size() * sizeof(FwdDesc), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(di, b.items.data(), b.items.size() * sizeof(WorkItem), hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(hip_fail(e, "graph table upload"));
+  hipStream_t cs;
+  if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) return cleanup(hip_fail(e, "stream"));
+  const int form = ens[0].map_form;
+  const bool tan = tangent_on(ens[0]);
+  const int nwg = std::max(1, std::min<int>(persistent_wgs(form, tan, t), (int)b.items.size()));
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    for (int k = 0; k < n_ens; ++k)
+      if (descs[k].n_class) (void)launch_zero_u32(descs[k].n_class, 1, cs);
+    if (!b.items.empty())
+      (void)launch_fwd_batched((const FwdDesc *)dd, (const WorkItem *)di, (int32_t)b.items.size(), (uint32_t *)dh, t,
+                               form, tan, nwg, cs);
+    e = hipStreamEndCapture(cs, &g->graph);
+  }
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "graph capture"));
+  if ((e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0)) != hipSuccess)
+    return cleanup(hip_fail(e, "graph instantiate"));
+  *out = g;
+  return AW_OK;
+}
+
+aw_status aw_graph_launch(aw_graph *g, void *stream) {
+  if (!g || !g->exec) return fail(AW_EINVAL, "null graph");
+  hipError_t e;
+  {
+    TimedLaunch tl((hipStream_t)stream);
+    e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+  }
+  if (e != hipSuccess) return hip_fail(e, "graph launch");
+  return AW_OK;
+}
+
+void aw_graph_destroy(aw_graph *g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (!g->dev_allocs.empty()) (void)hipDeviceSynchronize();
+  for (void *p : g->dev_allocs) (void)hipFree(p);
+  delete g;
+}
+
+aw_status aw_timing_enable(int32_t on) {
+  g_timing = on != 0;
+  return AW_OK;
+}
+
+aw_status aw_timing_read(double *ms, int64_t *launches) {
+  double total = 0.0;
+  int64_t n = 0;
+  for (auto &ev : g_events) {
+    hipError_t e = hipEventSynchronize(ev.second);
+    float t = 0.f;
+    if (e == hipSuccess && hipEventElapsedTime(&t, ev.first, ev.second) == hipSuccess) {
+      total += t;
+      ++n;
+    }
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  g_events.clear();
+  if (ms) *ms = total;
+  if (launches) *launches = n;
+  return AW_OK;
+}
+
+aw_status aw_step_op_counts(int32_t map_form, int32_t tangent, int64_t *fma, int64_t *mul, int64_t *add) {
+  if (!fma || !mul || !add) return fail(AW_EINVAL, "null output");
+  if (map_form != 1 && map_form != 2 && map_form != 4 && map_form != 6) return fail(AW_EINVAL, "unknown map_form");
+  step_op_counts(map_form, tangent != 0, fma, mul, add);
+  return AW_OK;
+}
+
+}  // extern "C"

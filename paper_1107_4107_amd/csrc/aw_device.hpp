@@ -1,0 +1,193 @@
+// aw_device.hpp -- device-side arithmetic of the ensemble mapper (gfx950, FP64).
+//
+// Model (arXiv:1107.4107, eqs. 1-2): H = |P|^2/2 + eps Hp(X),
+// Hp = cos x cos y (1 + cos 2z) = 2 cx cy cz^2.
+//   grad Hp = (-2 sx cy cz^2, -2 cx sy cz^2, -4 cx cy cz sz)
+//   Hess Hp: xx = yy = -2 cx cy cz^2, zz = -4 cx cy (cz^2 - sz^2),
+//            xy = 2 sx sy cz^2, xz = 4 sx cy cz sz, yz = 4 cx sy cz sz.
+// Kick K(t): P -= t eps grad Hp(X), dP -= t eps Hess(X) dX.
+// Drift D(t): X += t P, dX += t dP.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "aw_sincos_coef.h"
+
+namespace aw {
+
+// ---------------------------------------------------------------------------
+// sin and cos of an unwrapped angle.
+// x = q pi + r with q = nearest integer to x/pi (by adding 1.5*2^52, whose
+// low mantissa word then holds q), r reduced with a three-part pi; the first
+// fused step is exact for |x| < 2^20 pi.  sin x = (-1)^q sin r,
+// cos x = (-1)^q cos r.  The sign (-1)^q is NOT applied here: `par` returns
+// q's low bit in bit 0 so that callers can fold signs of products together.
+// ---------------------------------------------------------------------------
+struct SinCos {
+  double c, s;     // cos r, sin r
+  uint32_t par;    // low word of (q + 1.5*2^52): bit 0 = q mod 2
+};
+
+__device__ __forceinline__ SinCos sincos_red(double x) {
+  const double t = __builtin_fma(x, AW_INV_PI, AW_ROUND_MAGIC);
+  const double q = t - AW_ROUND_MAGIC;
+  double r = __builtin_fma(-q, AW_PI_A, x);
+  r = __builtin_fma(-q, AW_PI_B, r);
+  r = __builtin_fma(-q, AW_PI_C, r);
+  const double u = r * r;
+  double ps = AW_SIN_C[AW_SIN_NC - 1];
+#pragma unroll
+  for (int i = AW_SIN_NC - 2; i >= 0; --i) ps = __builtin_fma(ps, u, AW_SIN_C[i]);
+  double pc = AW_COS_C[AW_COS_NC - 1];
+#pragma unroll
+  for (int i = AW_COS_NC - 2; i >= 0; --i) pc = __builtin_fma(pc, u, AW_COS_C[i]);
+  SinCos o;
+  o.s = __builtin_fma(r * u, ps, r);
+  o.c = __builtin_fma(u, pc, 1.0);
+  o.par = (uint32_t)__double2loint(t);
+  return o;
+}
+
+// Flip the sign of v when bit 31 of `sgn` is set.
+__device__ __forceinline__ double flip(double v, uint32_t sgn) {
+  return __hiloint2double(__double2hiint(v) ^ (int)sgn, __double2loint(v));
+}
+
+// FP64 operation counts of one sincos_red (for the roofline accounting).
+constexpr int SC_FMA = 1 + 3 + (AW_SIN_NC - 1) + 1 + (AW_COS_NC - 1) + 1;
+constexpr int SC_MUL = 2;  // r*r, r*u
+constexpr int SC_ADD = 1;  // t - magic
+
+// True signed cos/sin (used outside the hot loop).
+__device__ __forceinline__ void sincos_full(double x, double &s, double &c) {
+  SinCos a = sincos_red(x);
+  uint32_t sg = a.par << 31;
+  s = flip(a.s, sg);
+  c = flip(a.c, sg);
+}
+
+// Hp(X) = 2 cx cy cz^2.
+__device__ __forceinline__ double hp_value(double x, double y, double z) {
+  SinCos X = sincos_red(x), Y = sincos_red(y), Z = sincos_red(z);
+  uint32_t sg = (X.par ^ Y.par) << 31;
+  return flip(2.0 * X.c * Y.c * (Z.c * Z.c), sg);
+}
+
+// ---------------------------------------------------------------------------
+// Per-orbit register state.
+// ---------------------------------------------------------------------------
+struct Orbit {
+  double x, y, z, px, py, pz;          // state (X unwrapped)
+  double dx, dy, dz, dpx, dpy, dpz;    // tangent vector, scaled by 2^-kexp
+  double p0x, p0y, p0z;                // initial momentum
+  double jsum;                         // sum_k |P_k - P_0|^2
+  int kexp;                            // tangent scale exponent (|w| true = |w| 2^kexp)
+};
+
+// Kick with weight a2 = 2 t eps, a4 = 4 t eps.  With sigma = (-1)^(qx+qy)
+// folded into the x factors, every force and Hessian term of eq. 2 carries
+// exactly one x factor and one y factor, and the z factors enter squared, so
+// the reduced-angle sines and cosines can be used directly.
+template <bool TAN>
+__device__ __forceinline__ void kick(Orbit &o, double a2, double a4) {
+  const SinCos X = sincos_red(o.x), Y = sincos_red(o.y), Z = sincos_red(o.z);
+  const uint32_t sg = (X.par ^ Y.par) << 31;
+  const double cx = flip(X.c, sg), sx = flip(X.s, sg);
+  const double cy = Y.c, sy = Y.s;
+  const double cz2 = Z.c * Z.c;
+  const double czsz = Z.c * Z.s;
+  const double e1 = a2 * cz2;      // 2 t eps cz^2
+  const double e2 = a4 * czsz;     // 4 t eps cz sz
+  const double psc = sx * cy, pcs = cx * sy, pcc = cx * cy;
+  if (TAN) {
+    const double c2z = __builtin_fma(-Z.s, Z.s, cz2);   // cz^2 - sz^2
+    const double e3 = a4 * c2z;
+    const double pss = sx * sy;
+    const double mxx = e1 * pcc;    // -t eps Hxx = -t eps Hyy
+    const double nxy = e1 * pss;    //  t eps Hxy
+    const double nxz = e2 * psc;    //  t eps Hxz
+    const double nyz = e2 * pcs;    //  t eps Hyz
+    const double mzz = e3 * pcc;    // -t eps Hzz
+    const double dx = o.dx, dy = o.dy, dz = o.dz;
+    o.dpx = __builtin_fma(mxx, dx, o.dpx);
+    o.dpx = __builtin_fma(-nxy, dy, o.dpx);
+    o.dpx = __builtin_fma(-nxz, dz, o.dpx);
+    o.dpy = __builtin_fma(-nxy, dx, o.dpy);
+    o.dpy = __builtin_fma(mxx, dy, o.dpy);
+    o.dpy = __builtin_fma(-nyz, dz, o.dpy);
+    o.dpz = __builtin_fma(-nxz, dx, o.dpz);
+    o.dpz = __builtin_fma(-nyz, dy, o.dpz);
+    o.dpz = __builtin_fma(mzz, dz, o.dpz);
+  }
+  o.px = __builtin_fma(e1, psc, o.px);   // -t eps dHp/dx
+  o.py = __builtin_fma(e1, pcs, o.py);   // -t eps dHp/dy
+  o.pz = __builtin_fma(e2, pcc, o.pz);   // -t eps dHp/dz
+}
+
+template <bool TAN>
+__device__ __forceinline__ void drift(Orbit &o, double t) {
+  o.x = __builtin_fma(t, o.px, o.x);
+  o.y = __builtin_fma(t, o.py, o.y);
+  o.z = __builtin_fma(t, o.pz, o.z);
+  if (TAN) {
+    o.dx = __builtin_fma(t, o.dpx, o.dx);
+    o.dy = __builtin_fma(t, o.dpy, o.dy);
+    o.dz = __builtin_fma(t, o.dpz, o.dz);
+  }
+}
+
+// Op counts of kick/drift (roofline accounting).
+template <bool TAN> struct KickOps {
+  static constexpr int fma = 3 * SC_FMA + 3 + (TAN ? 1 + 9 : 0);
+  static constexpr int mul = 3 * SC_MUL + 7 + (TAN ? 7 : 0);
+  static constexpr int add = 3 * SC_ADD;
+};
+template <bool TAN> struct DriftOps {
+  static constexpr int fma = TAN ? 6 : 3;
+};
+
+// Accumulate |P - P0|^2.
+__device__ __forceinline__ void accum_j(Orbit &o) {
+  const double ex = o.px - o.p0x, ey = o.py - o.p0y, ez = o.pz - o.p0z;
+  o.jsum = __builtin_fma(ex, ex, o.jsum);
+  o.jsum = __builtin_fma(ey, ey, o.jsum);
+  o.jsum = __builtin_fma(ez, ez, o.jsum);
+}
+
+// Rescale the tangent vector by an exact power of two so that |w|^2 lies in
+// [0.5, 2); the scale is accumulated in kexp.  Exact: it changes no mantissa.
+__device__ __forceinline__ void renorm(Orbit &o) {
+  double n2 = o.dx * o.dx;
+  n2 = __builtin_fma(o.dy, o.dy, n2);
+  n2 = __builtin_fma(o.dz, o.dz, n2);
+  n2 = __builtin_fma(o.dpx, o.dpx, n2);
+  n2 = __builtin_fma(o.dpy, o.dpy, n2);
+  n2 = __builtin_fma(o.dpz, o.dpz, n2);
+  const int e = __builtin_amdgcn_frexp_exp(n2);
+  const int s = e >> 1;
+  o.dx = __builtin_amdgcn_ldexp(o.dx, -s);
+  o.dy = __builtin_amdgcn_ldexp(o.dy, -s);
+  o.dz = __builtin_amdgcn_ldexp(o.dz, -s);
+  o.dpx = __builtin_amdgcn_ldexp(o.dpx, -s);
+  o.dpy = __builtin_amdgcn_ldexp(o.dpy, -s);
+  o.dpz = __builtin_amdgcn_ldexp(o.dpz, -s);
+  o.kexp += s;
+}
+
+// ---------------------------------------------------------------------------
+// Counter-based SplitMix64 (Steele, Lea & Flood 2014): output number c of the
+// stream seeded with `seed` is mix(seed + (c + 1) * 0x9E3779B97F4A7C15).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t c) {
+  uint64_t z = seed + (c + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ double u01(uint64_t seed, uint64_t c) {
+  return (double)(splitmix64(seed, c) >> 11) * 0x1.0p-53;
+}
+
+}  // namespace aw

@@ -1,0 +1,423 @@
+// aw_fwd.hip -- ensemble propagation kernels (gfx950, FP64).
+//
+// One orbit per lane (or two, interleaved, for instruction-level
+// parallelism); the state, the tangent vector and the accumulators stay in
+// VGPRs for the whole run; initial conditions are generated in registers from
+// the ensemble descriptor, so the only HBM traffic is the coalesced
+// structure-of-arrays store of the per-orbit results (and of the resumable
+// carry when a run is split into several launches).
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "aw_device.hpp"
+#include "aw_internal.hpp"
+#include "aw_launch.hpp"
+
+namespace aw {
+
+// ---------------------------------------------------------------------------
+// Initial conditions and tangent start (exact operations only, so the values
+// are bitwise those of any IEEE implementation of the same formulas).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void gen_ic(const FwdDesc &d, int64_t n, double s[6]) {
+#pragma clang fp contract(off)
+  if (d.ic_kind == 0) {
+    const int64_t i = n % d.nx, j = n / d.nx;
+    const double v0 = d.lo0 + (double)i * d.d0;
+    const double v1 = d.lo1 + (double)j * d.d1;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s[k] = (k == d.ax0) ? v0 : ((k == d.ax1) ? v1 : d.base[k]);
+  } else if (d.ic_kind == 1) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      s[k] = d.box_lo[k] + d.box_span[k] * u01(d.seed_ic, 16ull * (uint64_t)n + (uint64_t)k);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s[k] = d.ic[k * d.N + n];
+  }
+}
+
+__device__ __forceinline__ void gen_w0(uint64_t seed, int64_t n, double w[6]) {
+#pragma clang fp contract(off)
+  double u[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) u[k] = 2.0 * u01(seed, 16ull * (uint64_t)n + (uint64_t)k) - 1.0;
+  double n2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) n2 = n2 + u[k] * u[k];
+  const double nu = sqrt(n2);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) w[k] = u[k] / nu;
+}
+
+// ---------------------------------------------------------------------------
+// One map step: NK kicks, each preceded by a drift, and a closing drift
+// (symmetric compositions), or kick-then-drift (coupled standard map).
+// ---------------------------------------------------------------------------
+template <int FORM, bool TAN, int OPL>
+__device__ __forceinline__ void map_step(Orbit (&o)[OPL], const FwdDesc &d) {
+  using F = FormPattern<FORM>;
+  constexpr int NK = F::NK;
+  if constexpr (F::LEAD) {
+#pragma unroll
+    for (int i = 0; i < NK; ++i) {
+#pragma unroll
+      for (int j = 0; j < OPL; ++j) drift<TAN>(o[j], d.drift[F::drift_idx[i]]);
+#pragma unroll
+      for (int j = 0; j < OPL; ++j) kick<TAN>(o[j], d.ka2[F::kick_idx[i]], d.ka4[F::kick_idx[i]]);
+    }
+#pragma unroll
+    for (int j = 0; j < OPL; ++j) drift<TAN>(o[j], d.drift[F::drift_idx[NK]]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < OPL; ++j) kick<TAN>(o[j], d.ka2[0], d.ka4[0]);
+#pragma unroll
+    for (int j = 0; j < OPL; ++j) drift<TAN>(o[j], d.drift[0]);
+  }
+}
+
+// Select row r of the nine per-orbit results without dynamic indexing.
+__device__ __forceinline__ double pick9(const double v[9], int r) {
+  double o = v[0];
+#pragma unroll
+  for (int k = 1; k < 9; ++k) o = (r == k) ? v[k] : o;
+  return o;
+}
+
+__device__ __forceinline__ uint32_t bin_of(double a, double b, double lo0, double hi0, double lo1,
+                                           double hi1, int W, int H, bool closed) {
+#pragma clang fp contract(off)
+  if (!isfinite(a) || !isfinite(b)) return BIN_DROP;
+  double fi = floor((a - lo0) / (hi0 - lo0) * (double)W);
+  double fj = floor((b - lo1) / (hi1 - lo1) * (double)H);
+  if (closed) {
+    if (fi == (double)W && a == hi0) fi = (double)(W - 1);
+    if (fj == (double)H && b == hi1) fj = (double)(H - 1);
+  }
+  if (!(fi >= 0.0) || fi >= (double)W || !(fj >= 0.0) || fj >= (double)H) return BIN_DROP;
+  return (uint32_t)fj * (uint32_t)W + (uint32_t)fi;
+}
+
+__device__ __forceinline__ void vdir_key(double vx, double vy, double vz, double &phi, double &mu) {
+#pragma clang fp contract(off)
+  const double r = sqrt(vx * vx + vy * vy + vz * vz);
+  if (r == 0.0) {
+    phi = __builtin_nan("");
+    mu = __builtin_nan("");
+    return;
+  }
+  phi = atan2(vy, vx);
+  mu = vz / r;
+}
+
+constexpr double LN2 = 0x1.62e42fefa39efp-1;
+
+// ---------------------------------------------------------------------------
+// Run the orbits first + j*blockDim.x + threadIdx.x (j < OPL) over global
+// steps [k_begin, k_end).
+// ---------------------------------------------------------------------------
+template <int FORM, bool TAN, int OPL, int UNR>
+__device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first) {
+  int64_t n[OPL];
+  bool act[OPL];
+#pragma unroll
+  for (int j = 0; j < OPL; ++j) {
+    const int64_t m = first + (int64_t)j * blockDim.x + threadIdx.x;
+    act[j] = m < d.N;
+    n[j] = act[j] ? m : d.N - 1;  // inactive slots repeat a valid orbit, never stored
+  }
+  if (!act[0]) return;
+
+  Orbit o[OPL];
+#pragma unroll
+  for (int j = 0; j < OPL; ++j) {
+    if (d.k_begin == 0) {
+      double s[6];
+      gen_ic(d, n[j], s);
+      o[j].x = s[0]; o[j].y = s[1]; o[j].z = s[2];
+      o[j].px = s[3]; o[j].py = s[4]; o[j].pz = s[5];
+      o[j].p0x = s[3]; o[j].p0y = s[4]; o[j].p0z = s[5];
+      o[j].jsum = 0.0;
+      o[j].kexp = 0;
+      if (TAN) {
+        double w[6];
+        gen_w0(d.seed_tan, n[j], w);
+        o[j].dx = w[0]; o[j].dy = w[1]; o[j].dz = w[2];
+        o[j].dpx = w[3]; o[j].dpy = w[4]; o[j].dpz = w[5];
+      } else {
+        o[j].dx = o[j].dy = o[j].dz = o[j].dpx = o[j].dpy = o[j].dpz = 0.0;
+      }
+    } else {
+      const double *c = d.carry;
+      const int64_t N = d.N, m = n[j];
+      o[j].x = c[0 * N + m]; o[j].y = c[1 * N + m]; o[j].z = c[2 * N + m];
+      o[j].px = c[3 * N + m]; o[j].py = c[4 * N + m]; o[j].pz = c[5 * N + m];
+      o[j].dx = c[6 * N + m]; o[j].dy = c[7 * N + m]; o[j].dz = c[8 * N + m];
+      o[j].dpx = c[9 * N + m]; o[j].dpy = c[10 * N + m]; o[j].dpz = c[11 * N + m];
+      o[j].p0x = c[15 * N + m]; o[j].p0y = c[16 * N + m]; o[j].p0z = c[17 * N + m];
+      o[j].jsum = c[18 * N + m];
+      o[j].kexp = (int)c[19 * N + m];
+    }
+  }
+
+  // Hot loop.  The trip count and the renormalisation test are uniform.
+  const int64_t k0 = d.k_begin, k1 = d.k_end;
+  const int64_t mask = d.renorm_mask;
+#pragma unroll UNR
+  for (int64_t k = k0; k < k1; ++k) {
+    map_step<FORM, TAN, OPL>(o, d);
+#pragma unroll
+    for (int j = 0; j < OPL; ++j) accum_j(o[j]);
+    if (TAN && ((k + 1) & mask) == 0) {
+#pragma unroll
+      for (int j = 0; j < OPL; ++j) renorm(o[j]);
+    }
+  }
+
+  if (k1 < d.T) {
+    // Intermediate launch: store the resumable carry.
+#pragma unroll
+    for (int j = 0; j < OPL; ++j) {
+      if (!act[j]) continue;
+      double *c = d.carry;
+      const int64_t N = d.N, m = n[j];
+      double s0[6];
+      gen_ic(d, m, s0);
+      c[0 * N + m] = o[j].x; c[1 * N + m] = o[j].y; c[2 * N + m] = o[j].z;
+      c[3 * N + m] = o[j].px; c[4 * N + m] = o[j].py; c[5 * N + m] = o[j].pz;
+      c[6 * N + m] = o[j].dx; c[7 * N + m] = o[j].dy; c[8 * N + m] = o[j].dz;
+      c[9 * N + m] = o[j].dpx; c[10 * N + m] = o[j].dpy; c[11 * N + m] = o[j].dpz;
+      c[12 * N + m] = s0[0]; c[13 * N + m] = s0[1]; c[14 * N + m] = s0[2];
+      c[15 * N + m] = o[j].p0x; c[16 * N + m] = o[j].p0y; c[17 * N + m] = o[j].p0z;
+      c[18 * N + m] = o[j].jsum;
+      c[19 * N + m] = (double)o[j].kexp;
+      c[20 * N + m] = (double)k1;
+    }
+    return;
+  }
+
+  // Final launch: per-orbit observables.
+  uint32_t n_chaotic = 0;
+#pragma unroll
+  for (int j = 0; j < OPL; ++j) {
+    const int64_t N = d.N, m = n[j];
+    double s0[6];
+    gen_ic(d, m, s0);
+    double res[9];
+    double wn = 1.0;
+    if (TAN) {
+      double n2 = o[j].dx * o[j].dx;
+      n2 = __builtin_fma(o[j].dy, o[j].dy, n2);
+      n2 = __builtin_fma(o[j].dz, o[j].dz, n2);
+      n2 = __builtin_fma(o[j].dpx, o[j].dpx, n2);
+      n2 = __builtin_fma(o[j].dpy, o[j].dpy, n2);
+      n2 = __builtin_fma(o[j].dpz, o[j].dpz, n2);
+      const int e = __builtin_amdgcn_frexp_exp(n2);
+      const double mant = __builtin_amdgcn_frexp_mant(n2);
+      const double L = 0.5 * ((double)(2 * o[j].kexp + e) * LN2 + log(mant));
+      res[0] = L;
+      res[1] = L / d.th;
+      res[2] = L / d.lth;
+      wn = sqrt(n2);
+    } else {
+      res[0] = res[1] = res[2] = __builtin_nan("");
+    }
+    res[3] = (o[j].x - s0[0]) / d.th;
+    res[4] = (o[j].y - s0[1]) / d.th;
+    res[5] = (o[j].z - s0[2]) / d.th;
+    const double ex = o[j].px - o[j].p0x, ey = o[j].py - o[j].p0y, ez = o[j].pz - o[j].p0z;
+    res[6] = ex * ex + ey * ey + ez * ez;
+    res[7] = o[j].jsum / (double)d.T;
+    const double E1 = 0.5 * (o[j].px * o[j].px + o[j].py * o[j].py + o[j].pz * o[j].pz) +
+                      d.eps * hp_value(o[j].x, o[j].y, o[j].z);
+    const double E0 = 0.5 * (s0[3] * s0[3] + s0[4] * s0[4] + s0[5] * s0[5]) +
+                      d.eps * hp_value(s0[0], s0[1], s0[2]);
+    res[8] = E1 - E0;
+    const bool chaotic = TAN && (res[2] > d.chi_thr);
+    n_chaotic += (uint32_t)__popcll(__ballot(act[j] && chaotic));
+    if (!act[j]) continue;
+    if (d.out) {
+#pragma unroll
+      for (int r = 0; r < 9; ++r) d.out[r * N + m] = res[r];
+    }
+    if (d.state) {
+      double *st = d.state;
+      st[0 * N + m] = o[j].x; st[1 * N + m] = o[j].y; st[2 * N + m] = o[j].z;
+      st[3 * N + m] = o[j].px; st[4 * N + m] = o[j].py; st[5 * N + m] = o[j].pz;
+      st[6 * N + m] = o[j].dx / wn; st[7 * N + m] = o[j].dy / wn; st[8 * N + m] = o[j].dz / wn;
+      st[9 * N + m] = o[j].dpx / wn; st[10 * N + m] = o[j].dpy / wn; st[11 * N + m] = o[j].dpz / wn;
+    }
+    if (d.cls) d.cls[m] = chaotic ? 1 : 0;
+    if (d.epi == EPI_IC_GRID) {
+      d.img[m] = pick9(res, d.field);
+    } else if (d.epi == EPI_HIST_P0) {
+      double a = s0[0], b = s0[0];
+#pragma unroll
+      for (int k = 1; k < 6; ++k) {
+        a = (d.key0 == k) ? s0[k] : a;
+        b = (d.key1 == k) ? s0[k] : b;
+      }
+      d.bins[m] = bin_of(a, b, d.klo0, d.khi0, d.klo1, d.khi1, d.W, d.H, false);
+      d.vals[m] = pick9(res, d.field);
+    } else if (d.epi == EPI_HIST_VDIR) {
+      double phi, mu;
+      vdir_key(res[3], res[4], res[5], phi, mu);
+      d.bins[m] = bin_of(phi, mu, -M_PI, M_PI, -1.0, 1.0, d.W, d.H, true);
+    }
+  }
+  // Class count of the IC-grid image: one ballot and popcount per wave and
+  // slot (above), one atomic per wave from its lowest active lane.
+  if (d.epi == EPI_IC_GRID && d.n_class != nullptr && TAN) {
+    const uint64_t active = __ballot(1);
+    if ((int)__lane_id() == __ffsll((unsigned long long)active) - 1 && n_chaotic != 0)
+      atomicAdd(d.n_class, n_chaotic);
+  }
+}
+
+template <int FORM, bool TAN, int OPL, int UNR>
+__global__ __launch_bounds__(256) void k_fwd(FwdDesc d) {
+  const int64_t first = (int64_t)blockIdx.x * blockDim.x * OPL;
+  run_orbits<FORM, TAN, OPL, UNR>(d, first);
+}
+
+// Persistent batched propagation: each workgroup takes (ensemble, tile)
+// items from a device counter until the list, sorted longest-first, is empty.
+template <int FORM, bool TAN, int OPL>
+__global__ __launch_bounds__(256) void k_fwd_persist(const FwdDesc *__restrict__ descs,
+                                                     const WorkItem *__restrict__ items,
+                                                     int32_t n_items, uint32_t *head) {
+  __shared__ int32_t s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int32_t)atomicAdd(head, 1u);
+    __syncthreads();
+    const int32_t it = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
+    if (it >= n_items) break;
+    const int32_t e = __builtin_amdgcn_readfirstlane(items[it].ens);
+    const int64_t first = items[it].first;
+    run_orbits<FORM, TAN, OPL, 1>(descs[e], first);
+  }
+}
+
+__global__ void k_zero_u32(uint32_t *p, int32_t n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+__global__ void k_gen_ic(FwdDesc d, double *ic, double *w0) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= d.N) return;
+  double s[6];
+  if (ic) {
+    gen_ic(d, n, s);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) ic[k * d.N + n] = s[k];
+  }
+  if (w0) {
+    gen_w0(d.seed_tan, n, s);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) w0[k * d.N + n] = s[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.
+// ---------------------------------------------------------------------------
+template <int FORM, bool TAN>
+static hipError_t fwd_dispatch_opl(const FwdDesc &d, const Tuning &t, hipStream_t s) {
+  const int64_t per_block = (int64_t)t.block * t.opl;
+  const int64_t blocks = (d.N + per_block - 1) / per_block;
+  if (blocks <= 0) return hipSuccess;
+  dim3 grid((unsigned)blocks), block((unsigned)t.block);
+  if (t.opl == 1 && t.unroll == 1) hipLaunchKernelGGL((k_fwd<FORM, TAN, 1, 1>), grid, block, 0, s, d);
+  else if (t.opl == 1) hipLaunchKernelGGL((k_fwd<FORM, TAN, 1, 2>), grid, block, 0, s, d);
+  else if (t.unroll == 1) hipLaunchKernelGGL((k_fwd<FORM, TAN, 2, 1>), grid, block, 0, s, d);
+  else hipLaunchKernelGGL((k_fwd<FORM, TAN, 2, 2>), grid, block, 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_fwd(const FwdDesc &d, const Tuning &t, int form, bool tan, hipStream_t s) {
+  switch (form) {
+  case 1: return tan ? fwd_dispatch_opl<1, true>(d, t, s) : fwd_dispatch_opl<1, false>(d, t, s);
+  case 2: return tan ? fwd_dispatch_opl<2, true>(d, t, s) : fwd_dispatch_opl<2, false>(d, t, s);
+  case 4: return tan ? fwd_dispatch_opl<4, true>(d, t, s) : fwd_dispatch_opl<4, false>(d, t, s);
+  case 6: return tan ? fwd_dispatch_opl<6, true>(d, t, s) : fwd_dispatch_opl<6, false>(d, t, s);
+  default: return hipErrorInvalidValue;
+  }
+}
+
+template <int FORM, bool TAN>
+static hipError_t persist_dispatch(const FwdDesc *descs, const WorkItem *items, int32_t n_items,
+                                   uint32_t *head, const Tuning &t, int n_wg, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, head, 1);
+  dim3 grid((unsigned)n_wg), block((unsigned)t.block);
+  if (t.opl == 1) hipLaunchKernelGGL((k_fwd_persist<FORM, TAN, 1>), grid, block, 0, s, descs, items, n_items, head);
+  else hipLaunchKernelGGL((k_fwd_persist<FORM, TAN, 2>), grid, block, 0, s, descs, items, n_items, head);
+  return hipGetLastError();
+}
+
+hipError_t launch_fwd_batched(const FwdDesc *descs_dev, const WorkItem *items_dev, int32_t n_items,
+                              uint32_t *head_dev, const Tuning &t, int form, bool tan, int n_wg,
+                              hipStream_t s) {
+  switch (form) {
+  case 1: return tan ? persist_dispatch<1, true>(descs_dev, items_dev, n_items, head_dev, t, n_wg, s)
+                     : persist_dispatch<1, false>(descs_dev, items_dev, n_items, head_dev, t, n_wg, s);
+  case 2: return tan ? persist_dispatch<2, true>(descs_dev, items_dev, n_items, head_dev, t, n_wg, s)
+                     : persist_dispatch<2, false>(descs_dev, items_dev, n_items, head_dev, t, n_wg, s);
+  case 4: return tan ? persist_dispatch<4, true>(descs_dev, items_dev, n_items, head_dev, t, n_wg, s)
+                     : persist_dispatch<4, false>(descs_dev, items_dev, n_items, head_dev, t, n_wg, s);
+  case 6: return tan ? persist_dispatch<6, true>(descs_dev, items_dev, n_items, head_dev, t, n_wg, s)
+                     : persist_dispatch<6, false>(descs_dev, items_dev, n_items, head_dev, t, n_wg, s);
+  default: return hipErrorInvalidValue;
+  }
+}
+
+int persistent_blocks_per_cu(int form, bool tan, const Tuning &t) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+#define AW_OCC(F)                                                                                 \
+  if (form == F) {                                                                                \
+    if (tan) e = t.opl == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_persist<F, true, 1>, t.block, 0) \
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_persist<F, true, 2>, t.block, 0); \
+    else e = t.opl == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_persist<F, false, 1>, t.block, 0) \
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_persist<F, false, 2>, t.block, 0); \
+  }
+  AW_OCC(1) AW_OCC(2) AW_OCC(4) AW_OCC(6)
+#undef AW_OCC
+  return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+hipError_t launch_gen_ic(const FwdDesc &d, double *ic, double *w0, hipStream_t s) {
+  if (d.N <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((d.N + 255) / 256);
+  hipLaunchKernelGGL(k_gen_ic, dim3(blocks), dim3(256), 0, s, d, ic, w0);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(uint32_t *p, int32_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_u32, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+// FP64 instruction counts per map step as built (sincos, kicks, drifts, J,
+// amortised renormalisation excluded).
+void step_op_counts(int form, bool tan, int64_t *fma, int64_t *mul, int64_t *add) {
+  int nk = 0, nd = 0;
+  switch (form) {
+  case 1: nk = 1; nd = 1; break;
+  case 2: nk = 1; nd = 2; break;
+  case 4: nk = 3; nd = 4; break;
+  case 6: nk = 9; nd = 10; break;
+  default: break;
+  }
+  const int kf = tan ? KickOps<true>::fma : KickOps<false>::fma;
+  const int km = tan ? KickOps<true>::mul : KickOps<false>::mul;
+  const int ka = tan ? KickOps<true>::add : KickOps<false>::add;
+  const int df = tan ? DriftOps<true>::fma : DriftOps<false>::fma;
+  *fma = (int64_t)nk * kf + (int64_t)nd * df + 3;  // + 3 fma of the J accumulator
+  *mul = (int64_t)nk * km;
+  *add = (int64_t)nk * ka + 3;                     // + 3 subtractions of the J accumulator
+}
+
+}  // namespace aw

@@ -1,0 +1,257 @@
+// aw_hist.hip -- image reductions of per-orbit (bin, value) items.
+//
+// The W x H image (512 x 512 for the large ensemble: 3 MB of counts and
+// sums) does not fit in the 160 KB LDS of a CU, so the reduction is:
+//   1. count   : each block counts its items per image tile in LDS;
+//   2. scan    : one workgroup turns the (tile, block) counts, tile-major, into
+//                offsets, so every tile's items become one contiguous range;
+//   3. scatter : each block moves its items to their tile's range (LDS cursors);
+//   4. accumulate: one workgroup per tile adds its items into a TILE_W x TILE_H
+//                tile of counts (ds_add_u32) and sums (ds_add_f64) held in LDS
+//                and writes the finished tile out -- no global atomics.
+// Counts are exact and independent of scheduling; the order of the float
+// additions inside a tile is not, so sums can differ in the last bits.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "aw_internal.hpp"
+#include "aw_launch.hpp"
+
+namespace aw {
+
+__device__ __forceinline__ uint32_t bin_of_h(double a, double b, double lo0, double hi0, double lo1,
+                                             double hi1, int W, int H, bool closed) {
+#pragma clang fp contract(off)
+  if (!isfinite(a) || !isfinite(b)) return BIN_DROP;
+  double fi = floor((a - lo0) / (hi0 - lo0) * (double)W);
+  double fj = floor((b - lo1) / (hi1 - lo1) * (double)H);
+  if (closed) {
+    if (fi == (double)W && a == hi0) fi = (double)(W - 1);
+    if (fj == (double)H && b == hi1) fj = (double)(H - 1);
+  }
+  if (!(fi >= 0.0) || fi >= (double)W || !(fj >= 0.0) || fj >= (double)H) return BIN_DROP;
+  return (uint32_t)fj * (uint32_t)W + (uint32_t)fi;
+}
+
+__global__ void k_hist_bins(int64_t N, const double *__restrict__ a, const double *__restrict__ b,
+                            const double *__restrict__ v, double lo0, double hi0, double lo1,
+                            double hi1, int W, int H, int closed, uint32_t *__restrict__ bins,
+                            double *__restrict__ vals) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  bins[n] = bin_of_h(a[n], b[n], lo0, hi0, lo1, hi1, W, H, closed != 0);
+  if (vals) vals[n] = v ? v[n] : 0.0;
+}
+
+__global__ void k_vdir_keys(int64_t N, const double *__restrict__ V, double *__restrict__ phi,
+                            double *__restrict__ mu) {
+#pragma clang fp contract(off)
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const double vx = V[n], vy = V[N + n], vz = V[2 * N + n];
+  const double r = sqrt(vx * vx + vy * vy + vz * vz);
+  if (r == 0.0) {
+    phi[n] = __builtin_nan("");
+    mu[n] = __builtin_nan("");
+    return;
+  }
+  phi[n] = atan2(vy, vx);
+  mu[n] = vz / r;
+}
+
+struct TileGeom {
+  int W, H, tiles_x, n_tiles;
+};
+
+__device__ __forceinline__ void tile_of(uint32_t bin, const TileGeom &g, int &tile, int &local) {
+  const int i = (int)(bin % (uint32_t)g.W), j = (int)(bin / (uint32_t)g.W);
+  tile = (j / TILE_H) * g.tiles_x + i / TILE_W;
+  local = (j % TILE_H) * TILE_W + (i % TILE_W);
+}
+
+// 1. Per-block tile counts; dropped items per block.
+__global__ __launch_bounds__(HIST_BLOCK) void k_tile_count(int64_t N, const uint32_t *__restrict__ bins,
+                                                           TileGeom g, int32_t G,
+                                                           uint32_t *__restrict__ block_counts,
+                                                           uint32_t *__restrict__ block_dropped) {
+  __shared__ uint32_t cnt[MAX_TILES];
+  __shared__ uint32_t drop;
+  for (int t = threadIdx.x; t < g.n_tiles; t += blockDim.x) cnt[t] = 0u;
+  if (threadIdx.x == 0) drop = 0u;
+  __syncthreads();
+  const int64_t beg = (int64_t)blockIdx.x * HIST_ITEMS_PER_BLOCK;
+  const int64_t end = beg + HIST_ITEMS_PER_BLOCK < N ? beg + HIST_ITEMS_PER_BLOCK : N;
+  uint32_t my_drop = 0;
+  for (int64_t n = beg + threadIdx.x; n < end; n += blockDim.x) {
+    const uint32_t bin = bins[n];
+    if (bin == BIN_DROP) {
+      ++my_drop;
+      continue;
+    }
+    int tile, local;
+    tile_of(bin, g, tile, local);
+    atomicAdd(&cnt[tile], 1u);
+  }
+  if (my_drop) atomicAdd(&drop, my_drop);
+  __syncthreads();
+  for (int t = threadIdx.x; t < g.n_tiles; t += blockDim.x)
+    block_counts[(int64_t)t * G + blockIdx.x] = cnt[t];
+  if (threadIdx.x == 0) block_dropped[blockIdx.x] = drop;
+}
+
+// 2. Exclusive scan of the tile-major counts (one workgroup of 1024 lanes).
+//    tile_start[t] = first sorted position of tile t; tile_start[n_tiles] = kept.
+__global__ __launch_bounds__(1024) void k_tile_scan(int64_t n_entries, uint32_t *__restrict__ counts,
+                                                    int32_t n_tiles, int32_t G,
+                                                    const uint32_t *__restrict__ block_dropped,
+                                                    uint32_t *__restrict__ tile_start,
+                                                    uint64_t *__restrict__ dropped_out) {
+  __shared__ uint32_t part[1024];
+  const int tid = threadIdx.x;
+  const int64_t per = (n_entries + 1023) / 1024;
+  const int64_t beg = tid * per;
+  const int64_t end = beg + per < n_entries ? beg + per : n_entries;
+  uint32_t s = 0;
+  for (int64_t e = beg; e < end; ++e) s += counts[e];
+  part[tid] = s;
+  __syncthreads();
+  // Hillis-Steele inclusive scan of the 1024 partial sums.
+  for (int off = 1; off < 1024; off <<= 1) {
+    const uint32_t v = tid >= off ? part[tid - off] : 0u;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  uint32_t run = tid > 0 ? part[tid - 1] : 0u;
+  for (int64_t e = beg; e < end; ++e) {
+    const uint32_t c = counts[e];
+    counts[e] = run;
+    if (e % G == 0) tile_start[e / G] = run;
+    run += c;
+  }
+  if (tid == 1023) tile_start[n_tiles] = part[1023];
+  if (tid == 0 && dropped_out) {
+    uint64_t d = 0;
+    for (int b = 0; b < G; ++b) d += block_dropped[b];
+    *dropped_out = d;
+  }
+}
+
+// 3. Move each block's items to their tile ranges.
+__global__ __launch_bounds__(HIST_BLOCK) void k_tile_scatter(int64_t N, const uint32_t *__restrict__ bins,
+                                                             const double *__restrict__ vals, TileGeom g,
+                                                             int32_t G, const uint32_t *__restrict__ offsets,
+                                                             uint16_t *__restrict__ sorted_local,
+                                                             double *__restrict__ sorted_val) {
+  __shared__ uint32_t cur[MAX_TILES];
+  for (int t = threadIdx.x; t < g.n_tiles; t += blockDim.x) cur[t] = offsets[(int64_t)t * G + blockIdx.x];
+  __syncthreads();
+  const int64_t beg = (int64_t)blockIdx.x * HIST_ITEMS_PER_BLOCK;
+  const int64_t end = beg + HIST_ITEMS_PER_BLOCK < N ? beg + HIST_ITEMS_PER_BLOCK : N;
+  for (int64_t n = beg + threadIdx.x; n < end; n += blockDim.x) {
+    const uint32_t bin = bins[n];
+    if (bin == BIN_DROP) continue;
+    int tile, local;
+    tile_of(bin, g, tile, local);
+    const uint32_t pos = atomicAdd(&cur[tile], 1u);
+    sorted_local[pos] = (uint16_t)local;
+    if (vals) sorted_val[pos] = vals[n];
+  }
+}
+
+// 4. One workgroup per tile: LDS accumulation, then the tile is written out.
+//    mode 0: counts + sums; 1: counts + mean; 2: counts + density (count*norm).
+__global__ __launch_bounds__(HIST_BLOCK) void k_tile_accum(const uint32_t *__restrict__ tile_start,
+                                                           const uint16_t *__restrict__ sorted_local,
+                                                           const double *__restrict__ sorted_val,
+                                                           TileGeom g, int32_t mode, double norm,
+                                                           uint32_t *__restrict__ counts_out,
+                                                           double *__restrict__ f_out) {
+  __shared__ uint32_t c[TILE_BINS];
+  __shared__ double s[TILE_BINS];
+  const int t = blockIdx.x;
+  for (int k = threadIdx.x; k < TILE_BINS; k += blockDim.x) {
+    c[k] = 0u;
+    s[k] = 0.0;
+  }
+  __syncthreads();
+  const uint32_t beg = tile_start[t], end = tile_start[t + 1];
+  const bool have_vals = sorted_val != nullptr;
+  for (uint32_t p = beg + threadIdx.x; p < end; p += blockDim.x) {
+    const int loc = sorted_local[p];
+    atomicAdd(&c[loc], 1u);
+    if (have_vals) atomicAdd(&s[loc], sorted_val[p]);
+  }
+  __syncthreads();
+  const int tx = t % g.tiles_x, ty = t / g.tiles_x;
+  for (int k = threadIdx.x; k < TILE_BINS; k += blockDim.x) {
+    const int i = tx * TILE_W + (k % TILE_W), j = ty * TILE_H + (k / TILE_W);
+    if (i >= g.W || j >= g.H) continue;
+    const int64_t o = (int64_t)j * g.W + i;
+    const uint32_t cc = c[k];
+    if (counts_out) counts_out[o] = cc;
+    if (f_out) {
+      double f;
+      if (mode == 0) f = s[k];
+      else if (mode == 1) f = cc ? s[k] / (double)cc : 0.0;
+      else f = (double)cc * norm;
+      f_out[o] = f;
+    }
+  }
+}
+
+hipError_t launch_hist_bins(int64_t N, const double *a, const double *b, const double *v, double lo0,
+                            double hi0, double lo1, double hi1, int W, int H, int closed, uint32_t *bins,
+                            double *vals, hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hist_bins, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, a, b, v, lo0,
+                     hi0, lo1, hi1, W, H, closed, bins, vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_vdir_keys(int64_t N, const double *V, double *phi, double *mu, hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_vdir_keys, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, V, phi, mu);
+  return hipGetLastError();
+}
+
+HistPlan hist_plan(int64_t N, int W, int H) {
+  HistPlan p;
+  p.W = W;
+  p.H = H;
+  p.tiles_x = (W + TILE_W - 1) / TILE_W;
+  p.n_tiles = p.tiles_x * ((H + TILE_H - 1) / TILE_H);
+  p.G = (int32_t)((N + HIST_ITEMS_PER_BLOCK - 1) / HIST_ITEMS_PER_BLOCK);
+  if (p.G < 1) p.G = 1;
+  p.bytes_block_counts = sizeof(uint32_t) * (size_t)p.n_tiles * (size_t)p.G;
+  p.bytes_block_dropped = sizeof(uint32_t) * (size_t)p.G;
+  p.bytes_tile_start = sizeof(uint32_t) * (size_t)(p.n_tiles + 1);
+  p.bytes_sorted_local = sizeof(uint16_t) * (size_t)(N > 0 ? N : 1);
+  p.bytes_sorted_val = sizeof(double) * (size_t)(N > 0 ? N : 1);
+  return p;
+}
+
+hipError_t launch_hist_reduce(int64_t N, const uint32_t *bins, const double *vals, const HistPlan &p,
+                              const HistScratch &w, int mode, double norm, uint32_t *counts_out,
+                              double *f_out, uint64_t *dropped_out, hipStream_t s) {
+  TileGeom g{p.W, p.H, p.tiles_x, p.n_tiles};
+  if (N > 0) {
+    hipLaunchKernelGGL(k_tile_count, dim3((unsigned)p.G), dim3(HIST_BLOCK), 0, s, N, bins, g, p.G,
+                       w.block_counts, w.block_dropped);
+  } else {
+    hipError_t e = launch_zero_u32(w.block_counts, p.n_tiles * p.G, s);
+    if (e != hipSuccess) return e;
+    e = launch_zero_u32(w.block_dropped, p.G, s);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, (int64_t)p.n_tiles * p.G, w.block_counts,
+                     p.n_tiles, p.G, w.block_dropped, w.tile_start, dropped_out);
+  if (N > 0)
+    hipLaunchKernelGGL(k_tile_scatter, dim3((unsigned)p.G), dim3(HIST_BLOCK), 0, s, N, bins, vals, g, p.G,
+                       w.block_counts, w.sorted_local, vals ? w.sorted_val : nullptr);
+  hipLaunchKernelGGL(k_tile_accum, dim3((unsigned)p.n_tiles), dim3(HIST_BLOCK), 0, s, w.tile_start,
+                     w.sorted_local, vals ? w.sorted_val : nullptr, g, mode, norm, counts_out, f_out);
+  return hipGetLastError();
+}
+
+}  // namespace aw

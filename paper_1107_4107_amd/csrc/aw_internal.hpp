@@ -1,0 +1,125 @@
+// aw_internal.hpp -- descriptors passed from the host library to the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace aw {
+
+constexpr int MAX_KICKS = 9;
+constexpr int MAX_DRIFTS = 10;
+constexpr int MAX_UNIQUE = 4;  // distinct kick (and drift) weights of any form
+
+// Stage pattern of each map form: stage i of the step uses weight
+// kick_idx[i] (drift_idx[i]) of the distinct weights.  The symmetric
+// compositions are palindromic and the triple jump repeats its weights, so the
+// 9 kicks and 10 drifts of the 6th-order step take only 4 + 4 distinct values;
+// passing those keeps every weight in scalar registers.
+template <int FORM> struct FormPattern;
+template <> struct FormPattern<1> {
+  static constexpr int NK = 1, ND = 1;
+  static constexpr bool LEAD = false;
+  static constexpr int kick_idx[1] = {0};
+  static constexpr int drift_idx[1] = {0};
+};
+template <> struct FormPattern<2> {
+  static constexpr int NK = 1, ND = 2;
+  static constexpr bool LEAD = true;
+  static constexpr int kick_idx[1] = {0};
+  static constexpr int drift_idx[2] = {0, 0};
+};
+template <> struct FormPattern<4> {
+  static constexpr int NK = 3, ND = 4;
+  static constexpr bool LEAD = true;
+  static constexpr int kick_idx[3] = {0, 1, 0};
+  static constexpr int drift_idx[4] = {0, 1, 1, 0};
+};
+template <> struct FormPattern<6> {
+  static constexpr int NK = 9, ND = 10;
+  static constexpr bool LEAD = true;
+  static constexpr int kick_idx[9] = {0, 1, 0, 2, 3, 2, 0, 1, 0};
+  static constexpr int drift_idx[10] = {0, 1, 1, 2, 3, 3, 2, 1, 1, 0};
+};
+constexpr uint32_t BIN_DROP = 0xffffffffu;
+
+// Image epilogue selector of the propagation kernel.
+enum EpiKind : int32_t { EPI_NONE = 0, EPI_IC_GRID = 1, EPI_HIST_P0 = 2, EPI_HIST_VDIR = 3 };
+
+// One ensemble as the kernels see it.  Distinct stage weights, pre-multiplied:
+// drift[u] = c h, ka2[u] = 2 w h eps, ka4[u] = 4 w h eps.
+struct FwdDesc {
+  double drift[MAX_UNIQUE];
+  double ka2[MAX_UNIQUE];
+  double ka4[MAX_UNIQUE];
+  double eps;
+  double th;         // T h
+  double lth;        // ln(1 + T h)
+  double chi_thr;
+  int64_t T;         // total steps of the run
+  int64_t k_begin;   // first global step of this launch
+  int64_t k_end;     // one past the last global step of this launch
+  int64_t N;         // orbits
+  // initial conditions
+  int32_t ic_kind;   // 0 GRID2, 1 BOX, 2 EXPLICIT
+  int32_t ax0, ax1;
+  int32_t renorm_mask;  // renormalise after global step k when (k+1) & mask == 0
+  int64_t nx;
+  double lo0, d0, lo1, d1;
+  double base[6];
+  double box_lo[6], box_span[6];
+  uint64_t seed_ic, seed_tan;
+  const double *ic;  // EXPLICIT [6][N]
+  double *carry;     // [AW_NCARRY][N] or null
+  double *out;       // [AW_NOUT][N] or null
+  double *state;     // [12][N] or null
+  uint8_t *cls;      // [N] or null
+  // image epilogue
+  int32_t epi;       // EpiKind
+  int32_t field;     // orbit_out row imaged / averaged
+  int32_t W, H;
+  int32_t key0, key1;
+  double klo0, khi0, klo1, khi1;
+  double *img;       // IC_GRID: [H][W]
+  uint32_t *n_class; // IC_GRID: one counter of class-1 orbits, or null
+  uint32_t *bins;    // HIST: per-orbit bin index j*W + i or BIN_DROP
+  double *vals;      // HIST_P0: per-orbit value
+};
+
+// Work item of the batched persistent launch: (ensemble, first orbit).
+struct WorkItem {
+  int32_t ens;
+  int32_t pad;
+  int64_t first;
+};
+
+// Histogram reduction geometry: the W x H image is cut into tiles of
+// TILE_W x TILE_H bins; a tile's counts and sums fit in LDS.
+constexpr int TILE_W = 64;
+constexpr int TILE_H = 32;
+constexpr int TILE_BINS = TILE_W * TILE_H;
+constexpr int HIST_BLOCK = 256;
+constexpr int HIST_ITEMS_PER_BLOCK = 8192;  // items per block in count/scatter
+constexpr int MAX_TILES = 4096;
+
+// Adjoint descriptor.
+struct AdjDesc {
+  double drift[MAX_UNIQUE];
+  double ka2[MAX_UNIQUE];
+  double ka4[MAX_UNIQUE];
+  double kw2[MAX_UNIQUE];  // 2 w h (for d/deps)
+  double kw4[MAX_UNIQUE];  // 4 w h
+  double eps;
+  int64_t T;
+  int64_t N;
+  int64_t ckpt;           // steps per segment
+  int64_t n_seg;          // ceil(T / ckpt)
+  const double *ic;       // [6][N]
+  const double *gJ;       // [N] or null
+  double *J;              // [N] or null
+  double *gic;            // [6][N]
+  double *geps;           // [N]
+  double *ckpts;          // [n_seg][6][N]
+  double *steps;          // [ckpt][6][N] (per-segment step states)
+};
+
+}  // namespace aw

@@ -1,0 +1,57 @@
+// aw_launch.hpp -- host-side launchers of the kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "aw_internal.hpp"
+
+namespace aw {
+
+struct Tuning {
+  int block = 256;
+  int opl = 1;
+  int unroll = 1;
+  int renorm = 8;
+  int pwgs = 0;
+};
+
+// Propagation.
+hipError_t launch_fwd(const FwdDesc &d, const Tuning &t, int form, bool tan, hipStream_t s);
+hipError_t launch_fwd_batched(const FwdDesc *descs_dev, const WorkItem *items_dev, int32_t n_items,
+                              uint32_t *head_dev, const Tuning &t, int form, bool tan, int n_wg,
+                              hipStream_t s);
+int persistent_blocks_per_cu(int form, bool tan, const Tuning &t);
+hipError_t launch_gen_ic(const FwdDesc &d, double *ic, double *w0, hipStream_t s);
+hipError_t launch_zero_u32(uint32_t *p, int32_t n, hipStream_t s);
+void step_op_counts(int form, bool tan, int64_t *fma, int64_t *mul, int64_t *add);
+
+// Histogram reduction.
+struct HistPlan {
+  int W = 0, H = 0, tiles_x = 0, n_tiles = 0;
+  int32_t G = 0;
+  size_t bytes_block_counts = 0, bytes_block_dropped = 0, bytes_tile_start = 0;
+  size_t bytes_sorted_local = 0, bytes_sorted_val = 0;
+};
+struct HistScratch {
+  uint32_t *block_counts = nullptr;
+  uint32_t *block_dropped = nullptr;
+  uint32_t *tile_start = nullptr;
+  uint16_t *sorted_local = nullptr;
+  double *sorted_val = nullptr;
+};
+HistPlan hist_plan(int64_t N, int W, int H);
+hipError_t launch_hist_bins(int64_t N, const double *a, const double *b, const double *v, double lo0,
+                            double hi0, double lo1, double hi1, int W, int H, int closed, uint32_t *bins,
+                            double *vals, hipStream_t s);
+hipError_t launch_vdir_keys(int64_t N, const double *V, double *phi, double *mu, hipStream_t s);
+hipError_t launch_hist_reduce(int64_t N, const uint32_t *bins, const double *vals, const HistPlan &p,
+                              const HistScratch &w, int mode, double norm, uint32_t *counts_out,
+                              double *f_out, uint64_t *dropped_out, hipStream_t s);
+
+// Adjoint.
+hipError_t launch_adj_forward(const AdjDesc &d, int form, const Tuning &t, hipStream_t s);
+hipError_t launch_adj_backward(const AdjDesc &d, int form, const Tuning &t, hipStream_t s);
+
+}  // namespace aw

@@ -1,0 +1,125 @@
+"""The C-ABI library: it loads, exports every function include/aw.h declares,
+its ctypes mirrors match the C struct layouts, and the host-side validation
+rejects bad descriptors before touching a device.  CPU only."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1107_4107_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "aw.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(aw_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = _abi.load()
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_abi.EXPORTS)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "aw.h"
+int main(void) {
+  printf("%zu %zu %zu\\n", sizeof(aw_ensemble), sizeof(aw_tuning), sizeof(aw_image_spec));
+  printf("%zu %zu %zu %zu %zu\\n", offsetof(aw_ensemble, n_steps), offsetof(aw_ensemble, nx),
+         offsetof(aw_ensemble, n_orbits), offsetof(aw_ensemble, chi_threshold), offsetof(aw_ensemble, flags));
+  printf("%zu %zu\\n", offsetof(aw_image_spec, key_axis), offsetof(aw_image_spec, lo));
+  return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    E, T, S = _abi.AwEnsemble, _abi.AwTuning, _abi.AwImageSpec
+    got = [ctypes.sizeof(E), ctypes.sizeof(T), ctypes.sizeof(S), E.n_steps.offset, E.nx.offset,
+           E.n_orbits.offset, E.chi_threshold.offset, E.flags.offset, S.key_axis.offset, S.lo.offset]
+    assert [int(v) for v in out] == got
+
+
+def _ens(**kw):
+    from paper_1107_4107_amd import Ensemble
+    return Ensemble(**{**dict(eps=1e-2, n_steps=10, nx=8, ny=8), **kw}).to_c()
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(M=4), _abi.AW_EUNSUPPORTED),
+    (dict(map_form=3), _abi.AW_EINVAL),
+    (dict(n_steps=0), _abi.AW_EINVAL),
+    (dict(h=0.0), _abi.AW_EINVAL),
+    (dict(eps=float("nan")), _abi.AW_EINVAL),
+    (dict(axis=(3, 3)), _abi.AW_EINVAL),
+    (dict(axis=(3, 6)), _abi.AW_EINVAL),
+    (dict(nx=0), _abi.AW_EINVAL),
+    (dict(ic_kind="explicit", n_orbits=5), _abi.AW_EINVAL),  # no ic array
+    (dict(chi_threshold=float("nan")), _abi.AW_EINVAL),
+])
+def test_host_validation_rejects_bad_descriptors(kw, status):
+    lib = _abi.load()
+    e = _ens(**kw)
+    outs = _abi.ptr_array([None])
+    st = lib.aw_map_ensemble(ctypes.byref(e), 1, None, outs, None, None, None, None)
+    assert st == status
+    assert lib.aw_last_error()
+
+
+def test_bad_tuning_is_rejected():
+    lib = _abi.load()
+    e = _ens()
+    for t in [(100, 1, 1, 8, 0), (256, 3, 1, 8, 0), (256, 1, 3, 8, 0), (256, 1, 1, 3, 0), (256, 1, 1, 32, 0)]:
+        tun = _abi.AwTuning(*t)
+        st = lib.aw_map_ensemble(ctypes.byref(e), 1, None, _abi.ptr_array([None]), None, None,
+                                 ctypes.byref(tun), None)
+        assert st == _abi.AW_EINVAL, t
+
+
+def test_batched_ensembles_must_share_form():
+    lib = _abi.load()
+    arr = (_abi.AwEnsemble * 2)(_ens(), _ens(map_form="stdmap"))
+    st = lib.aw_map_ensemble(arr, 2, None, _abi.ptr_array([None, None]), None, None, None, None)
+    assert st == _abi.AW_EINVAL
+
+
+def test_grad_workspace_size():
+    lib = _abi.load()
+    e = _ens(ic_kind="explicit", n_orbits=1000, n_steps=10_000)
+    nb = ctypes.c_size_t()
+    assert lib.aw_indicator_grad_workspace(ctypes.byref(e), 100, ctypes.byref(nb)) == 0
+    # 100 checkpoints + 100 step states, 6 doubles per orbit each.
+    assert nb.value == 8 * 6 * 1000 * (100 + 100)
+    assert lib.aw_indicator_grad_workspace(ctypes.byref(e), 0, ctypes.byref(nb)) == _abi.AW_EINVAL
+
+
+def test_step_op_counts_match_the_stage_structure():
+    """Per map step: 9 kicks (3 sincos each) and 10 drifts for the 6th-order
+    map; the counts are those of the kernel's formulas (one sincos = 20 fma,
+    2 mul, 1 add)."""
+    from paper_1107_4107_amd import step_op_counts
+    f, m, a = step_op_counts("s6", True)
+    assert (f, m, a) == (9 * (60 + 3 + 10) + 10 * 6 + 3, 9 * (6 + 7 + 7), 9 * 3 + 3)
+    f1, m1, a1 = step_op_counts("stdmap", True)
+    assert (f1, m1, a1) == ((60 + 3 + 10) + 6 + 3, 6 + 7 + 7, 3 + 3)
+    f0, m0, a0 = step_op_counts("s6", False)
+    assert (f0, m0, a0) == (9 * (60 + 3) + 10 * 3 + 3, 9 * (6 + 7), 9 * 3 + 3)
+
+
+def test_ensemble_size():
+    lib = _abi.load()
+    assert lib.aw_ensemble_size(ctypes.byref(_ens(nx=7, ny=5))) == 35
+    assert lib.aw_ensemble_size(ctypes.byref(_ens(ic_kind="box", n_orbits=123))) == 123
+    assert lib.aw_ensemble_size(ctypes.byref(_ens(nx=0))) == -1

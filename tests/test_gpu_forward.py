@@ -1,0 +1,165 @@
+"""GPU parity of the propagation kernel against the CPU oracle.
+
+Bars: initial conditions bitwise; states to 1e-12 relative (floor 1) for
+T <= 50; on regular orbits (oracle chi < 1.5) the indicators to 1e-6
+relative; the regular/chaotic class on >= 99.5% of points with every
+disagreement inside the band chi in [1.5, 2.5].  Per-orbit results must be
+bitwise independent of the launch shape, of batching and of splitting a run
+into several launches."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import H, assert_close, class_agreement, gpu, need_gpu, np_, print_case
+
+pytestmark = gpu
+
+
+@pytest.fixture(scope="module")
+def aw():
+    need_gpu()
+    import paper_1107_4107_amd as m
+    return m
+
+
+def slice_ens(aw, eps, n, T, form="s6", pz0=0.0, nx=None, ny=None, tangent=True):
+    return aw.Ensemble(eps=eps, n_steps=T, map_form=form, nx=nx or n, ny=ny or n,
+                       base=(0, 0, 0, 0, 0, pz0), tangent=tangent)
+
+
+def oracle_ic(e):
+    ic = oracle.ic_grid2(tuple(e.axis), tuple(e.lo), tuple(e.hi), e.nx, e.ny, list(e.base))
+    return ic, oracle.w0(e.seed_tangent, e.nx * e.ny)
+
+
+def test_initial_conditions_are_bitwise(aw):
+    print_case("ic bitwise")
+    e = slice_ens(aw, 1e-2, 64, 10, nx=64, ny=48)
+    ic, w0 = aw.generate_ic(e)
+    ic_o, w0_o = oracle_ic(e)
+    np.testing.assert_array_equal(np_(ic), ic_o)
+    np.testing.assert_array_equal(np_(w0), w0_o)
+    from paper_1107_4107_amd import workloads
+    b = workloads.c5(n_orbits=5000)
+    ic, w0 = aw.generate_ic(b)
+    np.testing.assert_array_equal(np_(ic), oracle.ic_box(b.box_lo, b.box_hi, b.seed_ic, 5000))
+    np.testing.assert_array_equal(np_(w0), oracle.w0(b.seed_tangent, 5000))
+
+
+@pytest.mark.parametrize("form", ["s6", "stdmap", "s2", "s4"])
+def test_states_match_for_short_runs(aw, form):
+    print_case("states T=50", form)
+    e = slice_ens(aw, 1e-2, 64, 50, form)
+    r = aw.map_ensemble(e, want_state=True)
+    ic, w0 = oracle_ic(e)
+    out_o, st_o = oracle.ensemble(form, e.eps, H, 50, ic, w0, want_state=True)
+    st = np_(r.state)
+    assert_close(st[:6], st_o[:6], 1e-12, what="state")
+    assert_close(st[6:], st_o[6:], 1e-10, what="unit tangent")
+    out = np_(r.orbit_out)
+    assert_close(out[0], out_o[0], 1e-10, what="L")
+    assert_close(out[3:6], out_o[3:6], 1e-11, what="V")
+    assert_close(out[6:8], out_o[6:8], 1e-9, floor=1e-6, what="dP2, J")
+    assert np.max(np.abs(out[8] - out_o[8])) < 1e-13
+
+
+@pytest.mark.parametrize("form,pz0", [("s6", 0.0), ("s6", 1.0), ("stdmap", 0.0)])
+def test_indicators_64x64_T1000(aw, form, pz0):
+    """The 64 x 64 slice, eps = 1e-2, T = 1000 (and its p_z0 = 1 companion)."""
+    print_case("indicators 64x64 T=1000", form, pz0)
+    e = slice_ens(aw, 1e-2, 64, 1000, form, pz0)
+    r = aw.map_ensemble(e)
+    ic, w0 = oracle_ic(e)
+    out_o = oracle.ensemble(form, e.eps, H, 1000, ic, w0)
+    out = np_(r.orbit_out)
+    chi_o = out_o[2]
+    reg = chi_o < 1.5
+    assert reg.sum() > 1000
+    assert_close(out[0, reg], out_o[0, reg], 1e-6, what="L (regular)")
+    assert_close(out[1:3, reg], out_o[1:3, reg], 1e-6, what="lambda, chi (regular)")
+    assert_close(out[3:8, reg], out_o[3:8, reg], 1e-6, floor=1e-9, what="V, dP2, J (regular)")
+    class_agreement(out[2], chi_o)
+    cls = np_(r.cls)
+    np.testing.assert_array_equal(cls, (out[2] > 2.0).astype(np.uint8))
+
+
+def test_integrable_limit_on_gpu(aw):
+    print_case("eps=0")
+    e = slice_ens(aw, 0.0, 32, 300, "s6", pz0=0.7)
+    r = aw.map_ensemble(e, want_state=True)
+    ic, w0 = oracle_ic(e)
+    st, out = np_(r.state), np_(r.orbit_out)
+    th = 300 * H
+    np.testing.assert_array_equal(st[3:6], ic[3:6])
+    assert_close(st[0:3], ic[0:3] + th * ic[3:6], 1e-12)
+    L = 0.5 * np.log(np.sum((w0[0:3] + th * w0[3:6]) ** 2, axis=0) + np.sum(w0[3:6] ** 2, axis=0))
+    assert_close(out[0], L, 1e-11)
+    assert np.all(out[6] == 0) and np.all(out[7] == 0)
+
+
+def test_invariant_plane_is_exact_on_gpu(aw):
+    print_case("invariant plane")
+    e = slice_ens(aw, 5e-2, 32, 2000)
+    r = aw.map_ensemble(e, want_state=True)
+    st = np_(r.state)
+    assert np.all(st[2] == 0.0) and np.all(st[5] == 0.0)
+
+
+def test_chunked_run_is_bitwise_equal(aw):
+    import torch
+    print_case("chunked")
+    e = slice_ens(aw, 3e-2, 40, 777, nx=40, ny=37)
+    full = aw.map_ensemble(e, want_state=True)
+    N = e.size
+    carry = torch.empty((aw.NCARRY, N), dtype=torch.float64, device="cuda")
+    out = torch.empty((aw.NOUT, N), dtype=torch.float64, device="cuda")
+    st = torch.empty((12, N), dtype=torch.float64, device="cuda")
+    cls = torch.empty((N,), dtype=torch.uint8, device="cuda")
+    bounds = [0, 1, 100, 333, 600, 777]
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        aw.map_ensemble_steps(e, carry, a, b, orbit_out=out, state=st, cls=cls)
+    np.testing.assert_array_equal(np_(out), np_(full.orbit_out))
+    np.testing.assert_array_equal(np_(st), np_(full.state))
+    np.testing.assert_array_equal(np_(cls), np_(full.cls))
+
+
+@pytest.mark.parametrize("tun", [(64, 1, 1, 8), (128, 2, 1, 8), (256, 1, 2, 1), (256, 2, 2, 16), (64, 2, 1, 4)])
+def test_results_do_not_depend_on_the_launch_shape(aw, tun):
+    print_case("tuning", tun)
+    e = slice_ens(aw, 2e-2, 50, 300, nx=50, ny=43)   # ragged against every block
+    ref = aw.map_ensemble(e, want_state=True)
+    t = aw.Tuning(block=tun[0], orbits_per_lane=tun[1], unroll=tun[2], renorm_every=tun[3])
+    got = aw.map_ensemble(e, want_state=True, tuning=t)
+    np.testing.assert_array_equal(np_(got.orbit_out), np_(ref.orbit_out))
+    np.testing.assert_array_equal(np_(got.state), np_(ref.state))
+
+
+def test_explicit_initial_conditions(aw):
+    import torch
+    print_case("explicit")
+    e = slice_ens(aw, 1e-2, 24, 200)
+    ref = aw.map_ensemble(e, want_state=True)
+    ic, _ = aw.generate_ic(e)
+    x = aw.Ensemble(eps=1e-2, n_steps=200, ic_kind="explicit", n_orbits=e.size)
+    got = aw.map_ensemble(x, ic, want_state=True)
+    np.testing.assert_array_equal(np_(got.orbit_out), np_(ref.orbit_out))
+    # Edge cases: one orbit, and an empty ensemble.
+    one = aw.Ensemble(eps=1e-2, n_steps=5, ic_kind="explicit", n_orbits=1)
+    r1 = aw.map_ensemble(one, ic[:, :1].contiguous())
+    o1 = oracle.ensemble("s6", 1e-2, H, 5, np_(ic[:, :1]), oracle.w0(0, 1))
+    assert_close(np_(r1.orbit_out)[0], o1[0], 1e-10)
+    zero = aw.Ensemble(eps=1e-2, n_steps=5, ic_kind="explicit", n_orbits=0)
+    r0 = aw.map_ensemble(zero, torch.empty((6, 0), dtype=torch.float64, device="cuda"))
+    assert r0.orbit_out.shape == (9, 0)
+
+
+def test_hyperbolic_fixed_point_ftle(aw):
+    """X = 0, P = 0: the FTLE tends to sqrt(4 eps) (closed form, see the oracle pins)."""
+    import torch
+    print_case("fixed point")
+    ic = torch.zeros((6, 1), dtype=torch.float64, device="cuda")
+    e = aw.Ensemble(eps=0.1, n_steps=20000, ic_kind="explicit", n_orbits=1)
+    out = np_(aw.map_ensemble(e, ic).orbit_out)
+    assert abs(out[1, 0] - math.sqrt(0.4)) < 0.01
