@@ -191,7 +191,7 @@ aw_status aw_indicator_image(const aw_ensemble *ens, int32_t n_ens, const aw_ima
                              uint8_t *const *cls_dev, const aw_tuning *tuning, void *stream);
 
 /* The histogram reduction on its own, over caller keys a_dev[N], b_dev[N] and
- * values v_dev[N] (v_dev may be NULL: sums are then not formed): bin along
+ * values v_dev[N] (v_dev may be NULL: the sums are then zero): bin along
  * each axis floor((key - lo)/(hi - lo) * W); closed_upper = 0: half-open
  * ranges, out-of-range and non-finite keys dropped; closed_upper = 1: a key
  * equal to hi goes to the last bin.  counts_dev [H][W] uint32, sums_dev

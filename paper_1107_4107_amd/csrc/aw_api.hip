@@ -642,8 +642,8 @@ aw_status aw_histogram2d(int64_t N, const double *a_dev, const double *b_dev, co
   if ((e = launch_hist_bins(N, a_dev, b_dev, v_dev, lo0, hi0, lo1, hi1, W, H, closed_upper, (uint32_t *)sc.bins.p,
                             vals, s)) != hipSuccess)
     return hip_fail(e, "histogram bins");
-  if ((e = launch_hist_reduce(N, (uint32_t *)sc.bins.p, vals, p, w, 0, 1.0, counts_dev, v_dev ? sums_dev : nullptr,
-                              dropped_dev, s)) != hipSuccess)
+  if ((e = launch_hist_reduce(N, (uint32_t *)sc.bins.p, vals, p, w, 0, 1.0, counts_dev, sums_dev, dropped_dev,
+                              s)) != hipSuccess)
     return hip_fail(e, "histogram reduction");
   return AW_OK;
 }
