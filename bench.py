@@ -11,14 +11,24 @@ Default workload (c2): eps = 1e-3, a 1024 x 1024 slice of (px, py) in
 start seed 0; one bench step = initial conditions + propagation + per-orbit
 indicators + the chi image, the class map and the chaotic count.
 
+Other workloads (measurement records, not the default line):
+  c1  the 64 x 64, T = 1e3 slice at eps = 1e-2 (latency-bound);
+  c3  64 ensembles (eps sweep, mixed grids and horizons): one persistent
+      launch captured in a HIP graph against the sum of 64 separate launches;
+  c4  gradient of J on the 512 x 512, T = 1e4 slice with checkpoints every
+      100 steps: adjoint time against the forward pass;
+  c5  1e7 orbits uniform on [0, 2 pi)^6, eps = 5e-3, T = 1e6, run in chunks
+      of 1e5 steps with the state carried in HBM, then the momentum-drift image
+      and the direction density on the sphere (512 x 512 each).
+
 Prints ONE JSON line.  Single GPU only.
 """
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -29,6 +39,7 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
 KERNEL_SOURCES = ["paper_1107_4107_amd/csrc/aw_fwd.hip", "paper_1107_4107_amd/csrc/aw_device.hpp",
                   "paper_1107_4107_amd/csrc/aw_sincos_coef.h", "paper_1107_4107_amd/csrc/aw_internal.hpp"]
+METRIC = "orbit map-steps/sec (with tangent map)"
 
 
 def log(*a):
@@ -69,64 +80,64 @@ def host_threads() -> int:
 
 
 def cpu_baseline(ens, target_s: float, threads: int):
-    """The oracle on a bounded sample of the same workload: a strided set of
-    orbits of the slice, each run for the full T steps."""
+    """The oracle as it stands on a bounded sample of the same workload: an
+    evenly strided set of its orbits, each run for the full T steps."""
     import numpy as np
 
     import oracle
-    N = ens.nx * ens.ny
-    h = ens.h
+    N = ens.size
+
+    def sample(m):
+        idx = np.linspace(0, N - 1, m).astype(np.int64)
+        if ens.ic_kind == "grid2":
+            ic = oracle.ic_grid2(tuple(ens.axis), tuple(ens.lo), tuple(ens.hi), ens.nx, ens.ny, list(ens.base),
+                                 idx=idx)
+        else:
+            ic = oracle.ic_box(ens.box_lo, ens.box_hi, ens.seed_ic, idx=idx)
+        return ic, oracle.w0(ens.seed_tangent, idx=idx)
 
     def run(m):
-        idx = np.linspace(0, N - 1, m).astype(np.int64)
-        ic = oracle.ic_grid2(tuple(ens.axis), tuple(ens.lo), tuple(ens.hi), ens.nx, ens.ny, list(ens.base), idx=idx)
-        w0 = oracle.w0(ens.seed_tangent, idx=idx)
+        ic, w0 = sample(m)
         t0 = time.perf_counter()
-        oracle.ensemble(ens.map_form, ens.eps, h, ens.n_steps, ic, w0, nthreads=threads)
+        oracle.ensemble(ens.map_form, ens.eps, ens.h, ens.n_steps, ic, w0, nthreads=threads)
         return time.perf_counter() - t0
 
-    m0 = max(threads, 16)
+    m0 = threads
     t0 = run(m0)
     rate0 = m0 * ens.n_steps / t0
     m = int(max(m0, min(N, rate0 * target_s / ens.n_steps)))
     m = max(threads, (m // threads) * threads)
     t = run(m)
+    where = f"{ens.nx}x{ens.ny} slice" if ens.ic_kind == "grid2" else f"{N} orbits"
     return {"value": m * ens.n_steps / t, "unit": "map-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{m} orbits (evenly strided over the {ens.nx}x{ens.ny} slice) x {ens.n_steps} steps, "
+            "sample": f"{m} orbits (evenly strided over the {where}) x {ens.n_steps} steps each, "
                       f"{t:.1f} s on {threads} host threads"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2"])
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--block", type=int, default=256)
-    ap.add_argument("--opl", type=int, default=1)
-    ap.add_argument("--unroll", type=int, default=1)
-    args = ap.parse_args()
+def roofline(aw, ens, kernel_ms, workload):
+    fma, mul, add = aw.step_op_counts(ens.map_form, ens.tangent)
+    flop = 2 * fma + mul + add
+    achieved = flop * ens.size * ens.n_steps / (kernel_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic_for(workload),
+            "kernel": f"k_fwd<{ {'s6': 6, 's4': 4, 's2': 2, 'stdmap': 1}[ens.map_form]},"
+                      f"{'true' if ens.tangent else 'false'}> (propagation)",
+            "kernel_ms": kernel_ms, "flop_per_map_step": flop,
+            "fp64_ops_per_map_step": {"fma": fma, "mul": mul, "add": add}}
 
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the ensemble path has no multi-GPU mode in this build "
-              "(orbits are independent; see the sharding notes).", file=sys.stderr)
-        sys.exit(2)
 
-    import torch
+def base_record(value, steps, warmup, ms_per_step, dtype="f64"):
+    return {"metric": METRIC, "value": value, "unit": "map-steps/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+            "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": dtype, "data": "synthetic"}
 
-    import paper_1107_4107_amd as aw
-    from paper_1107_4107_amd import workloads as wl
 
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        sys.exit(1)
-    torch.cuda.set_device(0)
+# ---------------------------------------------------------------------------
+def run_slice(args, aw, wl, torch):
     ens = wl.c2() if args.workload == "c2" else wl.c1()
     desc = {"c2": "eps=1e-3 1024x1024 (px,py) slice, T=1e5, S6 + tangent, chi image + class map",
             "c1": "eps=1e-2 64x64 (px,py) slice, T=1e3, S6 + tangent, chi image"}[args.workload]
-    N, T = ens.nx * ens.ny, ens.n_steps
+    N, T = ens.size, ens.n_steps
     spec = wl.chi_image(ens.nx)
     tuning = aw.Tuning(block=args.block, orbits_per_lane=args.opl, unroll=args.unroll)
 
@@ -149,44 +160,200 @@ def main():
     aw.timing_enable(False)
     kern_ms, launches = aw.timing_read()
     n_chaotic = int(cnt.cpu().numpy().view("uint32")[0])
+    rec = base_record(N * T * args.steps / elapsed, args.steps, args.warmup, elapsed / args.steps * 1e3)
+    rec["config"] = {"workload": f"{args.workload}: {desc}", "eps": ens.eps, "grid": [ens.nx, ens.ny],
+                     "n_orbits": N, "n_steps": T, "h": ens.h, "map": ens.map_form, "tangent": True,
+                     "tuning": {"block": args.block, "orbits_per_lane": args.opl, "unroll": args.unroll}}
+    rec["roofline"] = roofline(aw, ens, kern_ms / max(launches, 1), args.workload)
+    rec["chaotic_fraction"] = n_chaotic / N
+    return rec, ens
 
-    fma, mul, add = aw.step_op_counts(ens.map_form, True)
-    flop_per_step = 2 * fma + mul + add
-    kms = kern_ms / max(launches, 1)
-    achieved = flop_per_step * N * T / (kms * 1e-3) / 1e12
-    value = N * T * args.steps / elapsed
 
-    cpu = None
+def run_batched(args, aw, wl, torch):
+    """One graph launch of the 64-ensemble batch vs 64 separate launches."""
+    from paper_1107_4107_amd.autotune import autotune
+    ens = wl.c3(t_scale=args.t_scale)
+    total = sum(e.size * e.n_steps for e in ens)
+    log(f"c3: {len(ens)} ensembles, {sum(e.size for e in ens)} orbits, {total:.4g} map-steps")
+    tun = autotune(ens, verbose=True)
+    log(f"autotuned: {tun}")
+    # chi image of every ensemble on its own grid (W = H = 0) and its chaotic count
+    spec = aw.ImageSpec(kind="ic_grid", field=aw.OUT_CHI, W=0, H=0)
+    imgs = [torch.empty((e.ny, e.nx), dtype=torch.float64, device="cuda") for e in ens]
+    cnts = [torch.empty((1,), dtype=torch.int32, device="cuda") for e in ens]
+    graph = aw.Graph(ens, spec, imgs, cnts, tuning=tun)
+    small = [dataclasses.replace(e, n_steps=10) for e in ens]
+    aw.map_ensembles(small, tuning=tun)   # warm-up of the kernels on tiny horizons
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    graph.launch()
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    log(f"batched (one graph launch): {tb:.2f} s")
+    sep = []
+    t0 = time.perf_counter()
+    for e in ens:
+        sep.append(aw.indicator_image(e, spec, want_counts=True, tuning=tun))
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    log(f"separate (64 launches): {ts:.2f} s")
+    same = all(torch.equal(a, b[0]) and torch.equal(c, b[1]) for a, c, b in zip(imgs, cnts, sep))
+    graph.close()
+    rec = base_record(total / tb, 1, 0, tb * 1e3)
+    rec["config"] = {"workload": f"c3: 64 ensembles, eps 1e-4..1e-1 log-spaced, grids 128^2..1024^2 and T "
+                                 f"1e4/3e4/1e5 drawn with seed 1 (horizons x{args.t_scale}), one persistent launch",
+                     "n_orbits": sum(e.size for e in ens), "map_steps": total,
+                     "tuning": dataclasses.asdict(tun)}
+    rec["batched_s"] = tb
+    rec["separate_s"] = ts
+    rec["batched_over_separate_throughput"] = ts / tb
+    rec["batched_equals_separate_bitwise"] = bool(same)
+    return rec, None
+
+
+def run_adjoint(args, aw, wl, torch):
+    s = wl.c4()
+    N, T = s.size, s.n_steps
+    ic, _ = aw.generate_ic(s)
+    fwd = aw.Ensemble(eps=s.eps, n_steps=T, ic_kind="explicit", n_orbits=N, tangent=False)
+    fwd_t = dataclasses.replace(fwd, tangent=True)
+    ws = torch.empty((aw.grad_workspace_bytes(fwd, wl.C4_CKPT),), dtype=torch.uint8, device="cuda")
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ts.sort()
+        return ts[len(ts) // 2]
+
+    t_fwd = timed(lambda: aw.map_ensemble(fwd, ic, want_class=False))
+    t_fwd_tan = timed(lambda: aw.map_ensemble(fwd_t, ic, want_class=False))
+    t_grad = timed(lambda: aw.indicator_grad(fwd, ic, ckpt_every=wl.C4_CKPT, workspace=ws))
+    log(f"forward {t_fwd:.3f} s, forward+tangent {t_fwd_tan:.3f} s, gradient {t_grad:.3f} s")
+    rec = base_record(N * T / t_grad, 3, 1, t_grad * 1e3)
+    rec["metric"] = "orbit map-steps/sec through the adjoint (forward + checkpoints + reverse)"
+    rec["config"] = {"workload": "c4: eps=1e-2 512x512 (px,py) slice, T=1e4, checkpoint every 100 steps, "
+                                 "gradient of J w.r.t. (x,p) and eps", "n_orbits": N, "n_steps": T}
+    rec["forward_s"] = t_fwd
+    rec["forward_tangent_s"] = t_fwd_tan
+    rec["gradient_s"] = t_grad
+    rec["gradient_over_forward"] = t_grad / t_fwd
+    rec["gradient_over_forward_tangent"] = t_grad / t_fwd_tan
+    return rec, None
+
+
+def run_large(args, aw, wl, torch):
+    """1e7 orbits, T = 1e6 (scaled by --t-scale), chunks of 1e5 steps."""
+    import numpy as np
+    T = max(1, int(round(1_000_000 * args.t_scale)))
+    e = wl.c5(n_orbits=args.n_orbits, T=T)
+    N = e.size
+    chunk = min(T, 100_000)
+    carry = torch.empty((aw.NCARRY, N), dtype=torch.float64, device="cuda")
+    out = torch.empty((aw.NOUT, N), dtype=torch.float64, device="cuda")
+    cls = torch.empty((N,), dtype=torch.uint8, device="cuda")
+    aw.timing_read()
+    aw.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    k = 0
+    while k < T:
+        k1 = min(T, k + chunk)
+        aw.map_ensemble_steps(e, carry, k, k1, orbit_out=out if k1 == T else None, cls=cls if k1 == T else None)
+        torch.cuda.synchronize()
+        log(f"steps {k1}/{T} done ({time.perf_counter() - t0:.1f} s)")
+        k = k1
+    aw.timing_enable(False)
+    kern_ms, launches = aw.timing_read()
+    p0 = torch.empty((2, N), dtype=torch.float64, device="cuda")
+    ic, _ = aw.generate_ic(e)
+    spec = wl.c5_p0_image()
+    cnt, sums, drop = aw.histogram2d(ic[3].contiguous(), ic[4].contiguous(), out[aw.OUT_DP2].contiguous(),
+                                     spec.lo, spec.hi, spec.W, spec.H)
+    phi, mu = aw.vdir_keys(out[aw.OUT_VX:aw.OUT_VZ + 1].contiguous())
+    vcnt, _, vdrop = aw.histogram2d(phi, mu, None, (-np.pi, -1.0), (np.pi, 1.0), 512, 512, closed_upper=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    c = cnt.cpu().numpy().view(np.uint32)
+    rec = base_record(N * T / elapsed, 1, 0, elapsed * 1e3)
+    rec["config"] = {"workload": f"c5: {N} orbits uniform on [0,2pi)^6 (seed 2), eps=5e-3, T={T}, S6 + tangent, "
+                                 f"chunks of {chunk} steps, |P-P0|^2 image keyed on (px0,py0) 512x512 + V-direction "
+                                 f"density 512x512", "n_orbits": N, "n_steps": T}
+    rec["roofline"] = roofline(aw, e, kern_ms / max(launches, 1), "c5")
+    rec["roofline"]["note"] = "average over the chunk launches"
+    rec["hist_p0_count_sum"] = int(c.sum())
+    rec["hist_p0_dropped"] = int(drop.cpu()[0])
+    rec["hist_vdir_dropped"] = int(vdrop.cpu()[0])
+    rec["chaotic_fraction"] = float(cls.float().mean())
+    # sampled parity of the full-horizon run against the oracle
     if not args.no_cpu_baseline:
+        import oracle
+        idx = np.sort(np.random.default_rng(2).choice(N, 32, replace=False))
+        ic_o = oracle.ic_box(e.box_lo, e.box_hi, e.seed_ic, idx=idx)
+        t1 = time.perf_counter()
+        out_o = oracle.ensemble("s6", e.eps, e.h, T, ic_o, oracle.w0(e.seed_tangent, idx=idx), nthreads=host_threads())
+        log(f"oracle sample of 32 orbits: {time.perf_counter() - t1:.1f} s")
+        g = out.cpu().numpy()[:, idx]
+        reg = out_o[2] < 1.5
+        rec["sample_parity"] = {"orbits": 32, "regular": int(reg.sum()),
+                                "max_rel_err_L_regular": float(np.max(np.abs(g[0, reg] - out_o[0, reg]) /
+                                                                      np.maximum(1, np.abs(out_o[0, reg])))),
+                                "class_disagreements": int(np.sum((g[2] > 2) != (out_o[2] > 2)))}
+    return rec, e
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--t-scale", type=float, default=1.0, help="c3/c5: scale the horizons")
+    ap.add_argument("--n-orbits", type=int, default=10_000_000, help="c5: ensemble size")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--opl", type=int, default=1)
+    ap.add_argument("--unroll", type=int, default=1)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run a plain device-to-device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the ensemble path has no multi-GPU mode in this build "
+              "(orbits are independent; see the sharding notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1107_4107_amd as aw
+    from paper_1107_4107_amd import workloads as wl
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    if args.copy_mib > 0:
+        n = args.copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.copy_mib} MiB done")
+        del src, dst
+    runner = {"c1": run_slice, "c2": run_slice, "c3": run_batched, "c4": run_adjoint, "c5": run_large}
+    rec, ens = runner[args.workload](args, aw, wl, torch)
+    rec.setdefault("cpu_baseline", None)
+    if ens is not None and not args.no_cpu_baseline and args.workload in ("c1", "c2", "c5"):
         threads = host_threads()
         log(f"cpu baseline on {threads} threads ...")
-        cpu = cpu_baseline(ens, args.cpu_seconds, threads)
-
-    rec = {
-        "metric": "orbit map-steps/sec (with tangent map)",
-        "value": value,
-        "unit": "map-steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {desc}", "eps": ens.eps, "grid": [ens.nx, ens.ny],
-                   "n_orbits": N, "n_steps": T, "h": ens.h, "map": ens.map_form, "tangent": True,
-                   "tuning": {"block": args.block, "orbits_per_lane": args.opl, "unroll": args.unroll}},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic_for(args.workload),
-                     "kernel": "k_fwd<6,true,1,1> (propagation)", "kernel_ms": kms,
-                     "flop_per_map_step": flop_per_step, "fp64_ops_per_map_step": {"fma": fma, "mul": mul, "add": add}},
-        "cpu_baseline": cpu,
-        "chaotic_fraction": n_chaotic / N,
-    }
-    if cpu:
-        rec["speedup_vs_oracle"] = value / cpu["value"]
+        rec["cpu_baseline"] = cpu_baseline(ens, args.cpu_seconds, threads)
+        rec["speedup_vs_oracle"] = rec["value"] / rec["cpu_baseline"]["value"]
     print(json.dumps(rec), flush=True)
 
 

@@ -159,7 +159,8 @@ aw_status aw_map_ensemble_steps(const aw_ensemble *ens, const double *ic_dev,
 
 /* Images (section "Main results"; Figs. 2-4).
  *  IC_GRID:   GRID2 ensembles only; image[j][i] = orbit_out row `field` of
- *             orbit j*nx + i (W = nx, H = ny).  counts, if non-NULL, is one
+ *             orbit j*nx + i (W = nx, H = ny; W = H = 0 takes every
+ *             ensemble's own nx, ny, so one batch may mix grid sizes).  counts, if non-NULL, is one
  *             uint32: the number of orbits with class 1 (needs AW_F_TANGENT).
  *  HIST_P0:   key = initial coordinates (key_axis[0], key_axis[1]); bin
  *             floor((a - lo)/(hi - lo) * W) per axis, half-open ranges, items

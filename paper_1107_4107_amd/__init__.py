@@ -220,7 +220,10 @@ def indicator_images(ens: List[Ensemble], spec: ImageSpec, want_counts: bool = T
     n = len(ens)
     c_ens = (_abi.AwEnsemble * n)(*[e.to_c() for e in ens])
     sizes = [e.size for e in ens]
-    imgs = [torch.empty((spec.H, spec.W), dtype=torch.float64, device=dev) for _ in ens]
+    if spec.kind == "ic_grid" and spec.W == 0 and spec.H == 0:   # each ensemble's own grid
+        imgs = [torch.empty((e.ny, e.nx), dtype=torch.float64, device=dev) for e in ens]
+    else:
+        imgs = [torch.empty((spec.H, spec.W), dtype=torch.float64, device=dev) for _ in ens]
     if want_counts:
         shape = (1,) if spec.kind == "ic_grid" else (spec.H, spec.W)
         cnts = [torch.empty(shape, dtype=torch.int32, device=dev) for _ in ens]  # uint32 bits

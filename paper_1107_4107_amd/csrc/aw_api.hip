@@ -392,15 +392,16 @@ aw_status validate_batch(const aw_ensemble *ens, int32_t n_ens, const double *co
 aw_status apply_image(const aw_image_spec *sp, const aw_ensemble &e, int idx, FwdDesc &d, double *img,
                       uint32_t *cnt) {
   if (!sp) return fail(AW_EINVAL, "null image spec");
-  if (sp->W < 1 || sp->H < 1) return fail(AW_EINVAL, "image W, H must be >= 1");
+  const bool own_grid = sp->kind == AW_IMG_IC_GRID && sp->W == 0 && sp->H == 0;
+  if (!own_grid && (sp->W < 1 || sp->H < 1)) return fail(AW_EINVAL, "image W, H must be >= 1");
   if (!img) return fail(AW_EINVAL, "ensemble %d: null image buffer", idx);
-  d.W = sp->W;
-  d.H = sp->H;
+  d.W = own_grid ? (int32_t)e.nx : sp->W;
+  d.H = own_grid ? (int32_t)e.ny : sp->H;
   d.field = sp->field;
   switch (sp->kind) {
   case AW_IMG_IC_GRID:
     if (e.ic_kind != AW_IC_GRID2) return fail(AW_EINVAL, "ensemble %d: IC_GRID images need a GRID2 ensemble", idx);
-    if (sp->W != e.nx || sp->H != e.ny) return fail(AW_EINVAL, "ensemble %d: IC_GRID needs W = nx, H = ny", idx);
+    if (d.W != e.nx || d.H != e.ny) return fail(AW_EINVAL, "ensemble %d: IC_GRID needs W = nx, H = ny", idx);
     if (sp->field < 0 || sp->field >= AW_NOUT) return fail(AW_EINVAL, "image field out of range");
     d.epi = EPI_IC_GRID;
     d.img = img;

@@ -19,10 +19,11 @@ namespace aw {
 // ---------------------------------------------------------------------------
 // sin and cos of an unwrapped angle.
 // x = q pi + r with q = nearest integer to x/pi (by adding 1.5*2^52, whose
-// low mantissa word then holds q), r reduced with a three-part pi; the first
-// fused step is exact for |x| < 2^20 pi.  sin x = (-1)^q sin r,
-// cos x = (-1)^q cos r.  The sign (-1)^q is NOT applied here: `par` returns
-// q's low bit in bit 0 so that callers can fold signs of products together.
+// low mantissa word then holds q), r reduced with a two-part pi: the first
+// fused step is exact for |x| < 2^20 pi and the neglected tail of pi adds at
+// most 1e-27 to r there.  sin x = (-1)^q sin r, cos x = (-1)^q cos r.  The
+// sign (-1)^q is NOT applied here: `par` returns q's low bit in bit 0 so that
+// callers can fold signs of products together.
 // ---------------------------------------------------------------------------
 struct SinCos {
   double c, s;     // cos r, sin r
@@ -34,7 +35,6 @@ __device__ __forceinline__ SinCos sincos_red(double x) {
   const double q = t - AW_ROUND_MAGIC;
   double r = __builtin_fma(-q, AW_PI_A, x);
   r = __builtin_fma(-q, AW_PI_B, r);
-  r = __builtin_fma(-q, AW_PI_C, r);
   const double u = r * r;
   double ps = AW_SIN_C[AW_SIN_NC - 1];
 #pragma unroll
@@ -55,7 +55,7 @@ __device__ __forceinline__ double flip(double v, uint32_t sgn) {
 }
 
 // FP64 operation counts of one sincos_red (for the roofline accounting).
-constexpr int SC_FMA = 1 + 3 + (AW_SIN_NC - 1) + 1 + (AW_COS_NC - 1) + 1;
+constexpr int SC_FMA = 1 + 2 + (AW_SIN_NC - 1) + 1 + (AW_COS_NC - 1) + 1;
 constexpr int SC_MUL = 2;  // r*r, r*u
 constexpr int SC_ADD = 1;  // t - magic
 

@@ -107,15 +107,15 @@ def test_grad_workspace_size():
 
 def test_step_op_counts_match_the_stage_structure():
     """Per map step: 9 kicks (3 sincos each) and 10 drifts for the 6th-order
-    map; the counts are those of the kernel's formulas (one sincos = 20 fma,
+    map; the counts are those of the kernel's formulas (one sincos = 19 fma,
     2 mul, 1 add)."""
     from paper_1107_4107_amd import step_op_counts
     f, m, a = step_op_counts("s6", True)
-    assert (f, m, a) == (9 * (60 + 3 + 10) + 10 * 6 + 3, 9 * (6 + 7 + 7), 9 * 3 + 3)
+    assert (f, m, a) == (9 * (57 + 3 + 10) + 10 * 6 + 3, 9 * (6 + 7 + 7), 9 * 3 + 3)
     f1, m1, a1 = step_op_counts("stdmap", True)
-    assert (f1, m1, a1) == ((60 + 3 + 10) + 6 + 3, 6 + 7 + 7, 3 + 3)
+    assert (f1, m1, a1) == ((57 + 3 + 10) + 6 + 3, 6 + 7 + 7, 3 + 3)
     f0, m0, a0 = step_op_counts("s6", False)
-    assert (f0, m0, a0) == (9 * (60 + 3) + 10 * 3 + 3, 9 * (6 + 7), 9 * 3 + 3)
+    assert (f0, m0, a0) == (9 * (57 + 3) + 10 * 3 + 3, 9 * (6 + 7), 9 * 3 + 3)
 
 
 def test_ensemble_size():

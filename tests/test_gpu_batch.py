@@ -89,3 +89,22 @@ def test_eps_sweep_batch_against_oracle(aw):
         chi_g.append(out[2])
         chi_o.append(out_o[2])
     class_agreement(np.concatenate(chi_g), np.concatenate(chi_o), min_frac=0.99)
+
+
+def test_graph_over_mixed_grids(aw):
+    """W = H = 0: every ensemble images on its own grid inside one graph."""
+    import torch
+    print_case("graph mixed grids")
+    ens = _mixed(aw)
+    spec = aw.ImageSpec(kind="ic_grid", field=aw.OUT_DP2, W=0, H=0)
+    imgs = [torch.empty((e.ny, e.nx), dtype=torch.float64, device="cuda") for e in ens]
+    cnts = [torch.empty((1,), dtype=torch.int32, device="cuda") for e in ens]
+    g = aw.Graph(ens, spec, imgs, cnts)
+    eager_imgs, eager_cnts, _ = aw.indicator_images(ens, spec)
+    for _ in range(2):
+        g.launch()
+        torch.cuda.synchronize()
+        for a, b, c, d in zip(imgs, eager_imgs, cnts, eager_cnts):
+            np.testing.assert_array_equal(np_(a), np_(b))
+            np.testing.assert_array_equal(np_(c), np_(d))
+    g.close()
