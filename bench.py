@@ -114,10 +114,14 @@ def cpu_baseline(ens, target_s: float, threads: int):
                       f"{t:.1f} s on {threads} host threads"}
 
 
-def roofline(aw, ens, kernel_ms, workload):
+def roofline(aw, ens, kernel_ms, workload, steps_per_launch=None):
+    """FP64 roofline of the propagation kernel: algorithmic flops of one
+    launch (flop per map step x orbits x steps the launch runs) over its
+    average duration."""
     fma, mul, add = aw.step_op_counts(ens.map_form, ens.tangent)
     flop = 2 * fma + mul + add
-    achieved = flop * ens.size * ens.n_steps / (kernel_ms * 1e-3) / 1e12
+    steps = ens.n_steps if steps_per_launch is None else steps_per_launch
+    achieved = flop * ens.size * steps / (kernel_ms * 1e-3) / 1e12
     return {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic_for(workload),
             "kernel": f"k_fwd<{ {'s6': 6, 's4': 4, 's2': 2, 'stdmap': 1}[ens.map_form]},"
@@ -284,8 +288,8 @@ def run_large(args, aw, wl, torch):
     rec["config"] = {"workload": f"c5: {N} orbits uniform on [0,2pi)^6 (seed 2), eps=5e-3, T={T}, S6 + tangent, "
                                  f"chunks of {chunk} steps, |P-P0|^2 image keyed on (px0,py0) 512x512 + V-direction "
                                  f"density 512x512", "n_orbits": N, "n_steps": T}
-    rec["roofline"] = roofline(aw, e, kern_ms / max(launches, 1), "c5")
-    rec["roofline"]["note"] = "average over the chunk launches"
+    rec["roofline"] = roofline(aw, e, kern_ms / max(launches, 1), "c5", steps_per_launch=chunk)
+    rec["roofline"]["note"] = f"average over the {launches} chunk launches of {chunk} steps each"
     rec["hist_p0_count_sum"] = int(c.sum())
     rec["hist_p0_dropped"] = int(drop.cpu()[0])
     rec["hist_vdir_dropped"] = int(vdrop.cpu()[0])
@@ -300,11 +304,61 @@ def run_large(args, aw, wl, torch):
         log(f"oracle sample of 32 orbits: {time.perf_counter() - t1:.1f} s")
         g = out.cpu().numpy()[:, idx]
         reg = out_o[2] < 1.5
+        err = np.abs(g[0] - out_o[0]) / np.maximum(1, np.abs(out_o[0]))
         rec["sample_parity"] = {"orbits": 32, "regular": int(reg.sum()),
-                                "max_rel_err_L_regular": float(np.max(np.abs(g[0, reg] - out_o[0, reg]) /
-                                                                      np.maximum(1, np.abs(out_o[0, reg])))),
+                                "max_rel_err_L_regular": float(np.max(err[reg])),
+                                "median_rel_err_L_regular": float(np.median(err[reg])),
+                                "per_orbit": [{"n": int(idx[k]), "chi_oracle": float(out_o[2, k]),
+                                               "rel_err_L": float(err[k]),
+                                               "rel_err_dP2": float(abs(g[6, k] - out_o[6, k]) /
+                                                                    max(1e-9, abs(out_o[6, k])))}
+                                              for k in range(32)],
                                 "class_disagreements": int(np.sum((g[2] > 2) != (out_o[2] > 2)))}
     return rec, e
+
+
+def run_sphere(args, aw, wl, torch):
+    """The paper's Fig. 2 experiment (section "Main results"): eps = 1,
+    E = 400, N = 1e8 orbits with the direction of P uniform on the momentum
+    sphere and X uniform on the torus, propagated for Delta t = 50 T (5000
+    steps), reduced to the density F of the direction of V (1024 x 512).  The
+    paper propagates the state only, so the tangent is off here (the metric of
+    this record is map-steps/s without the tangent).  fig3: E = 15, a zoom
+    window with the stay-in-area selection."""
+    if args.workload == "fig2":
+        e = wl.fig2(n_orbits=args.n_orbits if args.n_orbits != 10_000_000 else 100_000_000)
+        spec = wl.sphere_image(1024, 512)
+    else:
+        e = wl.fig3_zoom(n_orbits=args.n_orbits if args.n_orbits != 10_000_000 else 20_000_000)
+        spec = wl.sphere_image(512, 512, e.window)
+    N, T = e.size, e.n_steps
+    small = dataclasses.replace(e, n_steps=10, n_orbits=min(N, 1_000_000))
+    aw.indicator_image(small, spec)
+    torch.cuda.synchronize()
+    aw.timing_read()
+    aw.timing_enable(True)
+    t0 = time.perf_counter()
+    img, cnt, _ = aw.indicator_image(e, spec)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    aw.timing_enable(False)
+    kern_ms, launches = aw.timing_read()
+    log(f"{args.workload}: {N} orbits x {T} steps in {elapsed:.2f} s")
+    import numpy as np
+    c = cnt.cpu().numpy().view(np.uint32)
+    F = img.cpu().numpy()
+    rec = base_record(N * T / elapsed, 1, 1, elapsed * 1e3)
+    rec["metric"] = "orbit map-steps/sec (state only, as in the paper's experiment)"
+    rec["config"] = {"workload": f"{args.workload}: E={e.energy}, eps=1, N={N}, T={T} (Delta t = {T / 100:g} T), "
+                                 f"window={list(e.window)}, stay_in_window={e.stay_in_window}, "
+                                 f"F image {spec.W}x{spec.H}", "n_orbits": N, "n_steps": T}
+    rec["roofline"] = roofline(aw, e, kern_ms / max(launches, 1), args.workload)
+    rec["wall_s"] = elapsed
+    rec["paper_wall_s"] = 45 * 60.0
+    rec["paper_hardware"] = "NVIDIA Tesla M2050, FP64 (section Main results: 45 minutes per experiment)"
+    rec["binned"] = int(c.sum())
+    rec["median_density_over_uniform"] = float(np.median(F) * 4 * np.pi) if args.workload == "fig2" else None
+    return rec, None
 
 
 def main():
@@ -312,7 +366,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "fig2", "fig3"])
     ap.add_argument("--t-scale", type=float, default=1.0, help="c3/c5: scale the horizons")
     ap.add_argument("--n-orbits", type=int, default=10_000_000, help="c5: ensemble size")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -346,7 +400,8 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy of {args.copy_mib} MiB done")
         del src, dst
-    runner = {"c1": run_slice, "c2": run_slice, "c3": run_batched, "c4": run_adjoint, "c5": run_large}
+    runner = {"c1": run_slice, "c2": run_slice, "c3": run_batched, "c4": run_adjoint, "c5": run_large,
+              "fig2": run_sphere, "fig3": run_sphere}
     rec, ens = runner[args.workload](args, aw, wl, torch)
     rec.setdefault("cpu_baseline", None)
     if ens is not None and not args.no_cpu_baseline and args.workload in ("c1", "c2", "c5"):

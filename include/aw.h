@@ -66,14 +66,30 @@ typedef enum { AW_MAP_STDMAP = 1, AW_MAP_S2 = 2, AW_MAP_S4 = 4, AW_MAP_S6 = 6 } 
  *            s[axis[1]] = lo[1] + j * ((hi[1]-lo[1])/ny)  (left edges).
  *  BOX:      s_k = box_lo[k] + (box_hi[k]-box_lo[k]) * U(seed_ic, 16 n + k).
  *  EXPLICIT: the caller's ic_dev[6][N].
+ *  SPHERE:   fixed energy (Figs. 2-3): X_k = box_lo[k] + (box_hi[k]-box_lo[k])
+ *            U(seed_ic, 16 n + k) for k < 3 (the torus); the direction of P
+ *            uniform in area on the sphere segment phi in [window[0], window[1]),
+ *            mu = cos(theta) in [window[2], window[3]):
+ *            mu = window[2] + (window[3]-window[2]) U(seed_ic, 16 n + 3),
+ *            phi = window[0] + (window[1]-window[0]) U(seed_ic, 16 n + 4),
+ *            P = |P| (sqrt(1-mu^2) cos phi, sqrt(1-mu^2) sin phi, mu) with
+ *            |P| = sqrt(2 (energy - eps Hp(X))), so H = energy (eq. 1).
+ *            Needs energy > 2|eps| and -pi <= window[0] < window[1] <= pi,
+ *            -1 <= window[2] < window[3] <= 1.
  * U(seed, c) = (SplitMix64 output number c of the stream seeded with `seed`,
  * i.e. mix(seed + (c+1)*0x9E3779B97F4A7C15)) >> 11, times 2^-53.
  * The tangent start of orbit n is w0 = u/|u|, u_k = 2 U(seed_tangent, 16 n + k) - 1,
  * for every ic_kind.  Coordinate order is (x, y, z, px, py, pz). */
-typedef enum { AW_IC_GRID2 = 0, AW_IC_BOX = 1, AW_IC_EXPLICIT = 2 } aw_ic_kind;
+typedef enum { AW_IC_GRID2 = 0, AW_IC_BOX = 1, AW_IC_EXPLICIT = 2, AW_IC_SPHERE = 3 } aw_ic_kind;
 
 /* flags */
 #define AW_F_TANGENT 1u  /* propagate the tangent vector (L, lambda, chi, class) */
+#define AW_F_WINDOW 2u   /* "remained within the area" (section "Main results", Fig. 3):
+                          * test after every step (and at the start) that the direction
+                          * of P, phi = atan2(py, px), mu = pz/|P|, lies in the closed
+                          * window [window[0], window[1]] x [window[2], window[3]];
+                          * orbits that ever leave get bit 1 of their class byte set and
+                          * are left out of the HIST images.  Same window limits as SPHERE. */
 
 /* Rows of the per-orbit output orbit_out[AW_NOUT][N]:
  *  L      = ln(|w_T| / |w_0|), the tangent-vector growth (FTLE numerator);
@@ -83,7 +99,8 @@ typedef enum { AW_IC_GRID2 = 0, AW_IC_BOX = 1, AW_IC_EXPLICIT = 2 } aw_ic_kind;
  *  DP2    = |P_T - P_0|^2, the momentum drift of the model section;
  *  J      = (1/T) sum_{k=1..T} |P_k - P_0|^2;
  *  DE     = H(s_T) - H(s_0).
- * Without AW_F_TANGENT the rows L, LAMBDA, CHI hold NaN and class is 0. */
+ * Without AW_F_TANGENT the rows L, LAMBDA, CHI hold NaN and class bit 0 is 0.
+ * Class byte: bit 0 = chi > chi_threshold, bit 1 = left the window (AW_F_WINDOW). */
 enum {
   AW_OUT_L = 0, AW_OUT_LAMBDA, AW_OUT_CHI, AW_OUT_VX, AW_OUT_VY, AW_OUT_VZ,
   AW_OUT_DP2, AW_OUT_J, AW_OUT_DE, AW_NOUT
@@ -106,6 +123,8 @@ typedef struct {
   uint64_t seed_tangent;  /* tangent start */
   double chi_threshold;   /* class = chi > chi_threshold */
   uint32_t flags;         /* AW_F_* */
+  double energy;          /* SPHERE: total energy E of eq. 1 */
+  double window[4];       /* SPHERE segment / AW_F_WINDOW area: phi_lo, phi_hi, mu_lo, mu_hi */
 } aw_ensemble;
 
 /* Launch shape.  NULL = defaults (block 256, one orbit per lane, step loop not
@@ -143,8 +162,9 @@ aw_status aw_map_ensemble(const aw_ensemble *ens, int32_t n_ens,
                           double *const *state_out_dev, uint8_t *const *cls_dev,
                           const aw_tuning *tuning, void *stream);
 
-/* Rows of the resumable carry[AW_NCARRY][N]. */
-#define AW_NCARRY 21
+/* Rows of the resumable carry[AW_NCARRY][N]: X, P, tangent (scaled), X0, P0,
+ * J sum, tangent scale exponent, steps done, left-the-window flag. */
+#define AW_NCARRY 22
 
 /* Resumable form of aw_map_ensemble for one ensemble: runs global steps
  * [k_begin, k_end) with 0 <= k_begin < k_end <= n_steps.  k_begin == 0 starts
@@ -167,9 +187,12 @@ aw_status aw_map_ensemble_steps(const aw_ensemble *ens, const double *ic_dev,
  *             outside dropped; image = per-bin mean of row `field` (0 where
  *             empty), counts = per-bin count.
  *  HIST_VDIR: the density F of the direction of V on the momentum sphere:
- *             phi = atan2(Vy, Vx) over [-pi, pi] (W bins), mu = Vz/|V| over
- *             [-1, 1] (H bins), closed at the top; image = count / (N dphi dmu),
- *             counts = per-bin count.  A zero V is dropped.
+ *             phi = atan2(Vy, Vx) over [lo[0], hi[0]] (W bins), mu = Vz/|V|
+ *             over [lo[1], hi[1]] (H bins), closed at the top; all four zero
+ *             means the whole sphere [-pi, pi] x [-1, 1] (a zoom otherwise);
+ *             image = count / (N dphi dmu) with N the ensemble size,
+ *             counts = per-bin count.  A zero V is dropped, and so are
+ *             orbits that left the window under AW_F_WINDOW.
  * Histograms are built by a counting sort of items by image tile followed by
  * per-tile LDS accumulation; counts are exact and deterministic, float sums
  * may differ in the last bits between runs. */

@@ -66,6 +66,8 @@ def _load():
         "oracle_u01": (d, [u64, u64]),
         "oracle_ic_grid2": (i, [i, i, d, d, d, d, l, l, _dp, _lp, l, _dp]),
         "oracle_ic_box": (None, [_dp, _dp, u64, _lp, l, _dp]),
+        "oracle_ic_sphere": (None, [d, d, d, d, d, d, _dp, _dp, u64, _lp, l, _dp]),
+        "oracle_ensemble_window": (i, [i, d, d, l, l, _dp, _dp, _dp, _dp, ctypes.POINTER(ctypes.c_uint8), _dp, i]),
         "oracle_w0": (None, [u64, _lp, l, _dp]),
         "oracle_hist2d": (l, [l, _dp, _dp, _dp, d, d, d, d, i, i, i, _up, _dp]),
         "oracle_vdir_keys": (None, [l, _dp, _dp, _dp]),
@@ -133,6 +135,34 @@ def ic_box(lo, hi, seed, n_orbits=None, idx=None):
     lo_, hi_ = _f64(lo, (6,)), _f64(hi, (6,))
     _load().oracle_ic_box(_ptr(lo_), _ptr(hi_), seed, ip, M, _ptr(ic))
     return ic
+
+
+def ic_sphere(E, eps, phi, mu, xlo, xhi, seed, n_orbits=None, idx=None):
+    """Fixed-energy initial conditions: X uniform on [xlo, xhi), direction of P
+    uniform on the sphere segment phi x mu, |P| = sqrt(2 (E - eps Hp(X)))."""
+    idx, ip = _idx(idx)
+    M = n_orbits if idx is None else len(idx)
+    ic = np.empty((6, M))
+    lo_, hi_ = _f64(xlo, (3,)), _f64(xhi, (3,))
+    _load().oracle_ic_sphere(E, eps, phi[0], phi[1], mu[0], mu[1], _ptr(lo_), _ptr(hi_), seed, ip, M, _ptr(ic))
+    return ic
+
+
+def ensemble_window(form, eps, h, T, ic, w0_, window, nthreads=0):
+    """oracle ensemble plus the stay-in-window test; returns (out, left, margin)."""
+    ic = _f64(ic)
+    w = _f64(w0_)
+    N = ic.shape[1]
+    out = np.empty((9, N))
+    left = np.empty(N, dtype=np.uint8)
+    margin = np.empty(N)
+    win = _f64(window, (4,))
+    rc = _load().oracle_ensemble_window(_form(form), eps, h, int(T), N, _ptr(ic), _ptr(w), _ptr(win), _ptr(out),
+                                        left.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), _ptr(margin),
+                                        int(nthreads))
+    if rc:
+        raise ValueError("oracle_ensemble_window rejected its arguments")
+    return out, left, margin
 
 
 def w0(seed, n_orbits=None, idx=None):

@@ -446,6 +446,84 @@ void oracle_w0(uint64_t seed, const long *idx, long M, double *w0)
     }
 }
 
+/* Fixed-energy initial conditions (section "Main results", Figs. 2-3):
+ * X uniform on the box [xlo, xhi) (the torus), the direction of P uniform on
+ * the part of the sphere with phi in [phi_lo, phi_hi), mu = cos(theta) in
+ * [mu_lo, mu_hi) -- uniform in (phi, mu) is uniform in area -- and |P| from
+ * the energy condition H(P, X) = E:  |P| = sqrt(2 (E - eps Hp(X))).
+ * Draws: X_k = U(seed, 16 n + k), k < 3; mu: U(seed, 16 n + 3); phi: U(seed, 16 n + 4). */
+void oracle_ic_sphere(double E, double eps, double phi_lo, double phi_hi, double mu_lo, double mu_hi,
+                      const double xlo[3], const double xhi[3], uint64_t seed, const long *idx, long M,
+                      double *ic)
+{
+    for (long m = 0; m < M; m++) {
+        long n = pick(idx, m);
+        uint64_t c = 16u * (uint64_t)n;
+        double X[3];
+        for (int k = 0; k < 3; k++) X[k] = xlo[k] + (xhi[k] - xlo[k]) * oracle_u01(seed, c + (uint64_t)k);
+        double mu = mu_lo + (mu_hi - mu_lo) * oracle_u01(seed, c + 3u);
+        double phi = phi_lo + (phi_hi - phi_lo) * oracle_u01(seed, c + 4u);
+        double st = sqrt(1.0 - mu * mu);
+        double p = sqrt(2.0 * (E - eps * hp_value(X)));
+        double P[3] = {p * st * cos(phi), p * st * sin(phi), p * mu};
+        for (int k = 0; k < 3; k++) {
+            ic[k * M + m] = X[k];
+            ic[(3 + k) * M + m] = P[k];
+        }
+    }
+}
+
+/* Signed distance of the direction of P from the window in (phi, mu)
+ * coordinates, phi = atan2(py, px), mu = pz / |P|: positive inside (the
+ * smallest distance to an edge), negative outside. */
+static double window_margin(const double P[3], const double win[4])
+{
+    double r = sqrt(P[0] * P[0] + P[1] * P[1] + P[2] * P[2]);
+    double phi = atan2(P[1], P[0]);
+    double mu = P[2] / r;
+    double d = phi - win[0];
+    if (win[1] - phi < d) d = win[1] - phi;
+    if (mu - win[2] < d) d = mu - win[2];
+    if (win[3] - mu < d) d = win[3] - mu;
+    return d;
+}
+
+/* As oracle_ensemble, and in addition the "remained within the area" test of
+ * section "Main results": after every step the direction of P must lie in the
+ * window win = (phi_lo, phi_hi, mu_lo, mu_hi) (edges included).  left[n] = 1
+ * if it ever left; margin[n] = the smallest window margin met (negative once
+ * outside), for judging decisions taken right at an edge. */
+int oracle_ensemble_window(int form, double eps, double h, long T, long N, const double *ic,
+                           const double *w0, const double win[4], double *out, uint8_t *left,
+                           double *margin, int nthreads)
+{
+    if (form != OR_STDMAP && form != OR_S2 && form != OR_S4 && form != OR_S6) return -1;
+    if (T < 1 || N < 0) return -1;
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+#endif
+    for (long n = 0; n < N; n++) {
+        double s0[6], u[6], rec[OR_REC], o[OR_NOUT];
+        for (int a = 0; a < 6; a++) {
+            s0[a] = ic[a * N + n];
+            u[a] = w0[a * N + n];
+        }
+        oracle_rec_init(s0, u, rec);
+        double mmin = window_margin(s0 + 3, win);
+        for (long k = 0; k < T; k++) {
+            oracle_rec_advance(form, eps, h, 1, rec);
+            double mk = window_margin(rec + 3, win);
+            if (mk < mmin) mmin = mk;
+        }
+        oracle_rec_finish(rec, eps, h, o);
+        for (int r = 0; r < OR_NOUT; r++) out[r * N + n] = o[r];
+        left[n] = mmin < 0.0 ? 1 : 0;
+        margin[n] = mmin;
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Images.                                                                  */
 /* ------------------------------------------------------------------------ */

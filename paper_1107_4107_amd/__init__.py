@@ -18,7 +18,7 @@ from typing import List, Optional, Sequence
 import torch
 
 from . import _abi
-from ._abi import (AwError, F_TANGENT, IC_BOX, IC_EXPLICIT, IC_GRID2, IMG_HIST_P0, IMG_HIST_VDIR,
+from ._abi import (AwError, F_TANGENT, F_WINDOW, IC_BOX, IC_EXPLICIT, IC_GRID2, IC_SPHERE, IMG_HIST_P0, IMG_HIST_VDIR,
                    IMG_IC_GRID, MAP_S2, MAP_S4, MAP_S6, MAP_STDMAP, NCARRY, NOUT, OUT_CHI, OUT_DE,
                    OUT_DP2, OUT_J, OUT_L, OUT_LAMBDA, OUT_VX, OUT_VY, OUT_VZ)
 
@@ -65,7 +65,7 @@ class Ensemble:
     n_steps: int
     h: float = H_PAPER
     map_form: str = "s6"
-    ic_kind: str = "grid2"              # "grid2" | "box" | "explicit"
+    ic_kind: str = "grid2"              # "grid2" | "box" | "explicit" | "sphere"
     axis: Sequence[int] = (3, 4)        # GRID2: varied coordinates (px, py by default)
     lo: Sequence[float] = (0.0, 0.0)
     hi: Sequence[float] = (2 * math.pi, 2 * math.pi)
@@ -80,6 +80,9 @@ class Ensemble:
     chi_threshold: float = 2.0
     tangent: bool = True
     M: int = 3
+    energy: float = 0.0                 # sphere: total energy E (eq. 1)
+    window: Sequence[float] = (-math.pi, math.pi, -1.0, 1.0)   # phi_lo, phi_hi, mu_lo, mu_hi
+    stay_in_window: bool = False        # the "remained within the area" test
 
     def to_c(self) -> _abi.AwEnsemble:
         e = _abi.AwEnsemble()
@@ -88,7 +91,7 @@ class Ensemble:
         e.eps = float(self.eps)
         e.h = float(self.h)
         e.n_steps = int(self.n_steps)
-        e.ic_kind = {"grid2": IC_GRID2, "box": IC_BOX, "explicit": IC_EXPLICIT}[self.ic_kind]
+        e.ic_kind = {"grid2": IC_GRID2, "box": IC_BOX, "explicit": IC_EXPLICIT, "sphere": IC_SPHERE}[self.ic_kind]
         e.axis[:] = [int(a) for a in self.axis]
         e.lo[:] = [float(v) for v in self.lo]
         e.hi[:] = [float(v) for v in self.hi]
@@ -100,7 +103,9 @@ class Ensemble:
         e.seed_ic = int(self.seed_ic) & 0xFFFFFFFFFFFFFFFF
         e.seed_tangent = int(self.seed_tangent) & 0xFFFFFFFFFFFFFFFF
         e.chi_threshold = float(self.chi_threshold)
-        e.flags = F_TANGENT if self.tangent else 0
+        e.flags = (F_TANGENT if self.tangent else 0) | (F_WINDOW if self.stay_in_window else 0)
+        e.energy = float(self.energy)
+        e.window[:] = [float(v) for v in self.window]
         return e
 
     @property
@@ -132,8 +137,8 @@ class ImageSpec:
     W: int = 64
     H: int = 64
     key_axis: Sequence[int] = (3, 4)
-    lo: Sequence[float] = (0.0, 0.0)
-    hi: Sequence[float] = (2 * math.pi, 2 * math.pi)
+    lo: Optional[Sequence[float]] = None   # hist_p0: key ranges (default [0, 2 pi)^2);
+    hi: Optional[Sequence[float]] = None   # hist_vdir: (phi, mu) zoom (default: whole sphere)
 
     def to_c(self) -> _abi.AwImageSpec:
         s = _abi.AwImageSpec()
@@ -141,8 +146,12 @@ class ImageSpec:
         s.field = int(self.field)
         s.W, s.H = int(self.W), int(self.H)
         s.key_axis[:] = [int(a) for a in self.key_axis]
-        s.lo[:] = [float(v) for v in self.lo]
-        s.hi[:] = [float(v) for v in self.hi]
+        if self.lo is None or self.hi is None:
+            lo, hi = ((0.0, 0.0), (2 * math.pi, 2 * math.pi)) if self.kind == "hist_p0" else ((0.0, 0.0), (0.0, 0.0))
+        else:
+            lo, hi = self.lo, self.hi
+        s.lo[:] = [float(v) for v in lo]
+        s.hi[:] = [float(v) for v in hi]
         return s
 
 

@@ -11,10 +11,11 @@ AW_OK, AW_EINVAL, AW_EUNSUPPORTED, AW_EDEVICE, AW_ENOMEM, AW_EWORKSPACE = range(
 STATUS_NAMES = {0: "AW_OK", 1: "AW_EINVAL", 2: "AW_EUNSUPPORTED", 3: "AW_EDEVICE", 4: "AW_ENOMEM",
                 5: "AW_EWORKSPACE"}
 MAP_STDMAP, MAP_S2, MAP_S4, MAP_S6 = 1, 2, 4, 6
-IC_GRID2, IC_BOX, IC_EXPLICIT = 0, 1, 2
+IC_GRID2, IC_BOX, IC_EXPLICIT, IC_SPHERE = 0, 1, 2, 3
 F_TANGENT = 1
+F_WINDOW = 2
 OUT_L, OUT_LAMBDA, OUT_CHI, OUT_VX, OUT_VY, OUT_VZ, OUT_DP2, OUT_J, OUT_DE, NOUT = range(10)
-NCARRY = 21
+NCARRY = 22
 IMG_IC_GRID, IMG_HIST_P0, IMG_HIST_VDIR = 0, 1, 2
 
 EXPORTS = [
@@ -47,6 +48,8 @@ class AwEnsemble(ctypes.Structure):
         ("seed_tangent", ctypes.c_uint64),
         ("chi_threshold", ctypes.c_double),
         ("flags", ctypes.c_uint32),
+        ("energy", ctypes.c_double),
+        ("window", ctypes.c_double * 4),
     ]
 
 

@@ -222,7 +222,17 @@ aw_status check_ensemble(const aw_ensemble *e, const double *ic, int idx) {
   if (!is_fin(e->eps)) return fail(AW_EINVAL, "ensemble %d: eps must be finite", idx);
   if (!is_fin(e->h) || e->h == 0.0) return fail(AW_EINVAL, "ensemble %d: h must be finite and non-zero", idx);
   if (e->n_steps < 1) return fail(AW_EINVAL, "ensemble %d: n_steps must be >= 1", idx);
-  if (e->flags & ~AW_F_TANGENT) return fail(AW_EINVAL, "ensemble %d: unknown flags 0x%x", idx, e->flags);
+  if (e->flags & ~(AW_F_TANGENT | AW_F_WINDOW))
+    return fail(AW_EINVAL, "ensemble %d: unknown flags 0x%x", idx, e->flags);
+  if (e->ic_kind == AW_IC_SPHERE || (e->flags & AW_F_WINDOW)) {
+    const double *w = e->window;
+    for (int k = 0; k < 4; ++k)
+      if (!is_fin(w[k])) return fail(AW_EINVAL, "ensemble %d: window not finite", idx);
+    if (!(-M_PI <= w[0] && w[0] < w[1] && w[1] <= M_PI))
+      return fail(AW_EINVAL, "ensemble %d: window needs -pi <= phi_lo < phi_hi <= pi", idx);
+    if (!(-1.0 <= w[2] && w[2] < w[3] && w[3] <= 1.0))
+      return fail(AW_EINVAL, "ensemble %d: window needs -1 <= mu_lo < mu_hi <= 1", idx);
+  }
   {
     double k[MAX_UNIQUE], dr[MAX_UNIQUE];
     if (!unique_weights(e->map_form, e->h, k, dr))
@@ -248,6 +258,13 @@ aw_status check_ensemble(const aw_ensemble *e, const double *ic, int idx) {
     break;
   case AW_IC_EXPLICIT:
     if (N > 0 && !ic) return fail(AW_EINVAL, "ensemble %d: EXPLICIT needs ic_dev", idx);
+    break;
+  case AW_IC_SPHERE:
+    for (int k = 0; k < 3; ++k)
+      if (!is_fin(e->box_lo[k]) || !is_fin(e->box_hi[k]) || !is_fin(e->box_hi[k] - e->box_lo[k]))
+        return fail(AW_EINVAL, "ensemble %d: SPHERE position range not finite", idx);
+    if (!is_fin(e->energy) || !(e->energy > 2.0 * std::fabs(e->eps)))
+      return fail(AW_EINVAL, "ensemble %d: SPHERE needs energy > 2|eps| (|Hp| <= 2, eq. 2)", idx);
     break;
   default:
     return fail(AW_EINVAL, "ensemble %d: unknown ic_kind %d", idx, e->ic_kind);
@@ -294,6 +311,18 @@ FwdDesc make_desc(const aw_ensemble &e, const double *ic, const Tuning &t) {
   d.seed_tan = e.seed_tangent;
   d.ic = ic;
   d.epi = EPI_NONE;
+  d.energy = e.energy;
+  for (int k = 0; k < 4; ++k) d.win[k] = e.window[k];
+  d.filter = (e.flags & AW_F_WINDOW) ? 1 : 0;
+  if (d.filter) {
+    const double w = e.window[1] - e.window[0];
+    d.e0x = std::cos(e.window[0]);
+    d.e0y = std::sin(e.window[0]);
+    d.e1x = std::cos(e.window[1]);
+    d.e1y = std::sin(e.window[1]);
+    d.win_phi = (e.window[0] == -M_PI && e.window[1] == M_PI) ? 0 : (w <= M_PI ? 1 : 2);
+    d.win_mu = (e.window[2] == -1.0 && e.window[3] == 1.0) ? 0 : 1;
+  }
   return d;
 }
 
@@ -384,6 +413,8 @@ aw_status validate_batch(const aw_ensemble *ens, int32_t n_ens, const double *co
     if (st != AW_OK) return st;
     if (ens[e].map_form != ens[0].map_form || ens[e].flags != ens[0].flags)
       return fail(AW_EINVAL, "batched ensembles must share map_form and flags (ensemble %d differs)", e);
+    if (n_ens > 1 && (ens[e].flags & AW_F_WINDOW))
+      return fail(AW_EUNSUPPORTED, "the window test runs in single-ensemble launches only");
   }
   return AW_OK;
 }
@@ -424,6 +455,20 @@ aw_status apply_image(const aw_image_spec *sp, const aw_ensemble &e, int idx, Fw
     break;
   case AW_IMG_HIST_VDIR:
     d.epi = EPI_HIST_VDIR;
+    if (sp->lo[0] == 0.0 && sp->hi[0] == 0.0 && sp->lo[1] == 0.0 && sp->hi[1] == 0.0) {
+      d.klo0 = -M_PI;
+      d.khi0 = M_PI;
+      d.klo1 = -1.0;
+      d.khi1 = 1.0;
+    } else {
+      if (!(sp->lo[0] < sp->hi[0]) || !(sp->lo[1] < sp->hi[1]) || !is_fin(sp->hi[0] - sp->lo[0]) ||
+          !is_fin(sp->hi[1] - sp->lo[1]))
+        return fail(AW_EINVAL, "HIST_VDIR zoom ranges must satisfy lo < hi");
+      d.klo0 = sp->lo[0];
+      d.khi0 = sp->hi[0];
+      d.klo1 = sp->lo[1];
+      d.khi1 = sp->hi[1];
+    }
     break;
   default:
     return fail(AW_EINVAL, "unknown image kind %d", sp->kind);
@@ -503,7 +548,8 @@ aw_status image_run(const aw_ensemble *ens, int32_t n_ens, const aw_image_spec *
     st = hist_scratch(sc, p, descs[e].N, spec->kind == AW_IMG_HIST_P0, w);
     if (st != AW_OK) return st;
     const int mode = spec->kind == AW_IMG_HIST_P0 ? 1 : 2;
-    const double norm = 1.0 / ((double)descs[e].N * (2.0 * M_PI / spec->W) * (2.0 / spec->H));
+    const double norm = 1.0 / ((double)descs[e].N * ((descs[e].khi0 - descs[e].klo0) / spec->W) *
+                               ((descs[e].khi1 - descs[e].klo1) / spec->H));
     herr = launch_hist_reduce(descs[e].N, descs[e].bins, descs[e].vals, p, w, mode, norm,
                               counts ? counts[e] : nullptr, image[e], nullptr, s);
     if (herr != hipSuccess) return hip_fail(herr, "histogram reduction");

@@ -16,8 +16,10 @@
 namespace aw {
 
 // ---------------------------------------------------------------------------
-// Initial conditions and tangent start (exact operations only, so the values
-// are bitwise those of any IEEE implementation of the same formulas).
+// Initial conditions and tangent start.  GRID2, BOX, EXPLICIT and the tangent
+// start use exact or correctly rounded operations only, so the values are
+// bitwise those of any IEEE implementation of the same formulas; SPHERE also
+// takes a cosine, a sine and Hp(X), so it agrees to a few ulps.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void gen_ic(const FwdDesc &d, int64_t n, double s[6]) {
 #pragma clang fp contract(off)
@@ -31,6 +33,21 @@ __device__ __forceinline__ void gen_ic(const FwdDesc &d, int64_t n, double s[6])
 #pragma unroll
     for (int k = 0; k < 6; ++k)
       s[k] = d.box_lo[k] + d.box_span[k] * u01(d.seed_ic, 16ull * (uint64_t)n + (uint64_t)k);
+  } else if (d.ic_kind == 3) {
+    // Fixed energy: X on the torus, direction uniform in area on the (phi, mu)
+    // segment, |P| from H(P, X) = E.
+    const uint64_t c = 16ull * (uint64_t)n;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s[k] = d.box_lo[k] + d.box_span[k] * u01(d.seed_ic, c + (uint64_t)k);
+    const double mu = d.win[2] + (d.win[3] - d.win[2]) * u01(d.seed_ic, c + 3ull);
+    const double phi = d.win[0] + (d.win[1] - d.win[0]) * u01(d.seed_ic, c + 4ull);
+    const double st = sqrt(1.0 - mu * mu);
+    const double p = sqrt(2.0 * (d.energy - d.eps * hp_value(s[0], s[1], s[2])));
+    double sp, cp;
+    sincos_full(phi, sp, cp);
+    s[3] = p * st * cp;
+    s[4] = p * st * sp;
+    s[5] = p * mu;
   } else {
 #pragma unroll
     for (int k = 0; k < 6; ++k) s[k] = d.ic[k * d.N + n];
@@ -112,11 +129,30 @@ __device__ __forceinline__ void vdir_key(double vx, double vy, double vz, double
 
 constexpr double LN2 = 0x1.62e42fefa39efp-1;
 
+// Is the direction of P inside the closed window phi in [phi_lo, phi_hi],
+// mu = pz/|P| in [mu_lo, mu_hi]?  The phi test uses half-plane (cross
+// product) tests against the edge directions e0, e1 instead of atan2: for a
+// window of width w <= pi, phi is inside iff e0 x d >= 0 and d x e1 >= 0; for
+// w > pi, iff d is not strictly inside the complementary sector.
+__device__ __forceinline__ bool in_window(double px, double py, double pz, const FwdDesc &d) {
+  bool ok = true;
+  if (d.win_phi != 0) {
+    const double c0 = d.e0x * py - d.e0y * px;   // e0 x d
+    const double c1 = px * d.e1y - py * d.e1x;   // d x e1
+    ok = d.win_phi == 1 ? (c0 >= 0.0 && c1 >= 0.0) : !(c0 < 0.0 && c1 < 0.0);
+  }
+  if (d.win_mu != 0) {
+    const double r = sqrt(px * px + py * py + pz * pz);
+    ok = ok && pz >= d.win[2] * r && pz <= d.win[3] * r;
+  }
+  return ok;
+}
+
 // ---------------------------------------------------------------------------
 // Run the orbits first + j*blockDim.x + threadIdx.x (j < OPL) over global
-// steps [k_begin, k_end).
+// steps [k_begin, k_end).  FILT: test the window after every step.
 // ---------------------------------------------------------------------------
-template <int FORM, bool TAN, int OPL, int UNR>
+template <int FORM, bool TAN, int OPL, int UNR, bool FILT = false>
 __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first) {
   int64_t n[OPL];
   bool act[OPL];
@@ -129,8 +165,10 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first) {
   if (!act[0]) return;
 
   Orbit o[OPL];
+  bool left[OPL];
 #pragma unroll
   for (int j = 0; j < OPL; ++j) {
+    left[j] = false;
     if (d.k_begin == 0) {
       double s[6];
       gen_ic(d, n[j], s);
@@ -147,6 +185,7 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first) {
       } else {
         o[j].dx = o[j].dy = o[j].dz = o[j].dpx = o[j].dpy = o[j].dpz = 0.0;
       }
+      if (FILT) left[j] = !in_window(s[3], s[4], s[5], d);
     } else {
       const double *c = d.carry;
       const int64_t N = d.N, m = n[j];
@@ -157,6 +196,7 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first) {
       o[j].p0x = c[15 * N + m]; o[j].p0y = c[16 * N + m]; o[j].p0z = c[17 * N + m];
       o[j].jsum = c[18 * N + m];
       o[j].kexp = (int)c[19 * N + m];
+      if (FILT) left[j] = c[21 * N + m] != 0.0;
     }
   }
 
@@ -168,6 +208,10 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first) {
     map_step<FORM, TAN, OPL>(o, d);
 #pragma unroll
     for (int j = 0; j < OPL; ++j) accum_j(o[j]);
+    if (FILT) {
+#pragma unroll
+      for (int j = 0; j < OPL; ++j) left[j] = left[j] || !in_window(o[j].px, o[j].py, o[j].pz, d);
+    }
     if (TAN && ((k + 1) & mask) == 0) {
 #pragma unroll
       for (int j = 0; j < OPL; ++j) renorm(o[j]);
@@ -192,6 +236,7 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first) {
       c[18 * N + m] = o[j].jsum;
       c[19 * N + m] = (double)o[j].kexp;
       c[20 * N + m] = (double)k1;
+      c[21 * N + m] = left[j] ? 1.0 : 0.0;
     }
     return;
   }
@@ -247,7 +292,7 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first) {
       st[6 * N + m] = o[j].dx / wn; st[7 * N + m] = o[j].dy / wn; st[8 * N + m] = o[j].dz / wn;
       st[9 * N + m] = o[j].dpx / wn; st[10 * N + m] = o[j].dpy / wn; st[11 * N + m] = o[j].dpz / wn;
     }
-    if (d.cls) d.cls[m] = chaotic ? 1 : 0;
+    if (d.cls) d.cls[m] = (uint8_t)((chaotic ? 1 : 0) | (left[j] ? 2 : 0));
     if (d.epi == EPI_IC_GRID) {
       d.img[m] = pick9(res, d.field);
     } else if (d.epi == EPI_HIST_P0) {
@@ -257,12 +302,12 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first) {
         a = (d.key0 == k) ? s0[k] : a;
         b = (d.key1 == k) ? s0[k] : b;
       }
-      d.bins[m] = bin_of(a, b, d.klo0, d.khi0, d.klo1, d.khi1, d.W, d.H, false);
+      d.bins[m] = left[j] ? BIN_DROP : bin_of(a, b, d.klo0, d.khi0, d.klo1, d.khi1, d.W, d.H, false);
       d.vals[m] = pick9(res, d.field);
     } else if (d.epi == EPI_HIST_VDIR) {
       double phi, mu;
       vdir_key(res[3], res[4], res[5], phi, mu);
-      d.bins[m] = bin_of(phi, mu, -M_PI, M_PI, -1.0, 1.0, d.W, d.H, true);
+      d.bins[m] = left[j] ? BIN_DROP : bin_of(phi, mu, d.klo0, d.khi0, d.klo1, d.khi1, d.W, d.H, true);
     }
   }
   // Class count of the IC-grid image: one ballot and popcount per wave and
@@ -274,10 +319,10 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first) {
   }
 }
 
-template <int FORM, bool TAN, int OPL, int UNR>
+template <int FORM, bool TAN, int OPL, int UNR, bool FILT = false>
 __global__ __launch_bounds__(256) void k_fwd(FwdDesc d) {
   const int64_t first = (int64_t)blockIdx.x * blockDim.x * OPL;
-  run_orbits<FORM, TAN, OPL, UNR>(d, first);
+  run_orbits<FORM, TAN, OPL, UNR, FILT>(d, first);
 }
 
 // Persistent batched propagation: each workgroup takes (ensemble, tile)
@@ -329,7 +374,11 @@ static hipError_t fwd_dispatch_opl(const FwdDesc &d, const Tuning &t, hipStream_
   const int64_t blocks = (d.N + per_block - 1) / per_block;
   if (blocks <= 0) return hipSuccess;
   dim3 grid((unsigned)blocks), block((unsigned)t.block);
-  if (t.opl == 1 && t.unroll == 1) hipLaunchKernelGGL((k_fwd<FORM, TAN, 1, 1>), grid, block, 0, s, d);
+  if (d.filter) {
+    // The window test runs with one orbit per lane and no unrolling.
+    const int64_t wblocks = (d.N + t.block - 1) / t.block;
+    hipLaunchKernelGGL((k_fwd<FORM, TAN, 1, 1, true>), dim3((unsigned)wblocks), block, 0, s, d);
+  } else if (t.opl == 1 && t.unroll == 1) hipLaunchKernelGGL((k_fwd<FORM, TAN, 1, 1>), grid, block, 0, s, d);
   else if (t.opl == 1) hipLaunchKernelGGL((k_fwd<FORM, TAN, 1, 2>), grid, block, 0, s, d);
   else if (t.unroll == 1) hipLaunchKernelGGL((k_fwd<FORM, TAN, 2, 1>), grid, block, 0, s, d);
   else hipLaunchKernelGGL((k_fwd<FORM, TAN, 2, 2>), grid, block, 0, s, d);

@@ -68,6 +68,15 @@ struct FwdDesc {
   double base[6];
   double box_lo[6], box_span[6];
   uint64_t seed_ic, seed_tan;
+  // fixed-energy (SPHERE) initial conditions and the stay-in-window test
+  double energy;
+  double win[4];          // phi_lo, phi_hi, mu_lo, mu_hi
+  double e0x, e0y;        // (cos phi_lo, sin phi_lo)
+  double e1x, e1y;        // (cos phi_hi, sin phi_hi)
+  int32_t win_phi;        // 0: every phi; 1: sector of width <= pi; 2: complement of a sector < pi
+  int32_t win_mu;         // 0: every mu; 1: test mu_lo <= pz/|P| <= mu_hi
+  int32_t filter;         // test the window after every step
+  int32_t pad_;
   const double *ic;  // EXPLICIT [6][N]
   double *carry;     // [AW_NCARRY][N] or null
   double *out;       // [AW_NOUT][N] or null
@@ -78,7 +87,7 @@ struct FwdDesc {
   int32_t field;     // orbit_out row imaged / averaged
   int32_t W, H;
   int32_t key0, key1;
-  double klo0, khi0, klo1, khi1;
+  double klo0, khi0, klo1, khi1;   // HIST_P0 key ranges; HIST_VDIR (phi, mu) ranges
   double *img;       // IC_GRID: [H][W]
   uint32_t *n_class; // IC_GRID: one counter of class-1 orbits, or null
   uint32_t *bins;    // HIST: per-orbit bin index j*W + i or BIN_DROP

@@ -90,3 +90,37 @@ def c5_vdir_image() -> ImageSpec:
 
 def chi_image(n: int) -> ImageSpec:
     return ImageSpec(kind="ic_grid", field=OUT_CHI, W=n, H=n)
+
+
+# ---------------------------------------------------------------------------
+# The paper's own geometry (section "Main results", Figs. 2-3): eps = 1, the
+# direction of P uniform on the momentum sphere at fixed energy E, X uniform on
+# the torus [0, 2 pi)^3, averaging time Delta t = 50 T = 5000 steps.
+
+FIG2_E = 400.0      # eps_eff = 2/E = 0.005, the weak regime (Fig. 2)
+FIG3_E = 15.0       # eps_eff = 2/15, moderate perturbation (Fig. 3)
+DT50 = 5000         # Delta t = 50 T with T = 2 pi, h = T/100
+
+
+def sphere_ensemble(E: float, n_orbits: int, T: int = DT50, window=(-math.pi, math.pi, -1.0, 1.0),
+                    stay_in_window: bool = False, tangent: bool = False, seed: int = 4) -> Ensemble:
+    return Ensemble(eps=1.0, n_steps=T, ic_kind="sphere", n_orbits=n_orbits, energy=E, window=tuple(window),
+                    box_lo=(0.0,) * 6, box_hi=(TWO_PI,) * 6, seed_ic=seed, seed_tangent=0,
+                    stay_in_window=stay_in_window, tangent=tangent)
+
+
+def fig2(n_orbits: int = 100_000_000, T: int = DT50) -> Ensemble:
+    """Fig. 2: E = 400, the whole sphere, N ~ 1e8, Delta t = 50 T."""
+    return sphere_ensemble(FIG2_E, n_orbits, T)
+
+
+def fig3_zoom(n_orbits: int = 4_000_000, T: int = DT50) -> Ensemble:
+    """Fig. 3 (b, c) style zoom: E = 15, a segment of the sphere, keeping only
+    the orbits whose momentum stays inside it."""
+    return sphere_ensemble(FIG3_E, n_orbits, T, window=(0.55, 1.05, -0.25, 0.25), stay_in_window=True)
+
+
+def sphere_image(W: int = 1024, H: int = 512, window=None) -> ImageSpec:
+    if window is None:
+        return ImageSpec(kind="hist_vdir", W=W, H=H)
+    return ImageSpec(kind="hist_vdir", W=W, H=H, lo=(window[0], window[2]), hi=(window[1], window[3]))

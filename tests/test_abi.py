@@ -40,6 +40,7 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu\\n", offsetof(aw_ensemble, n_steps), offsetof(aw_ensemble, nx),
          offsetof(aw_ensemble, n_orbits), offsetof(aw_ensemble, chi_threshold), offsetof(aw_ensemble, flags));
   printf("%zu %zu\\n", offsetof(aw_image_spec, key_axis), offsetof(aw_image_spec, lo));
+  printf("%zu %zu\\n", offsetof(aw_ensemble, energy), offsetof(aw_ensemble, window));
   return 0;
 }
 """)
@@ -48,7 +49,8 @@ int main(void) {
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
     E, T, S = _abi.AwEnsemble, _abi.AwTuning, _abi.AwImageSpec
     got = [ctypes.sizeof(E), ctypes.sizeof(T), ctypes.sizeof(S), E.n_steps.offset, E.nx.offset,
-           E.n_orbits.offset, E.chi_threshold.offset, E.flags.offset, S.key_axis.offset, S.lo.offset]
+           E.n_orbits.offset, E.chi_threshold.offset, E.flags.offset, S.key_axis.offset, S.lo.offset,
+           E.energy.offset, E.window.offset]
     assert [int(v) for v in out] == got
 
 
@@ -68,6 +70,10 @@ def _ens(**kw):
     (dict(nx=0), _abi.AW_EINVAL),
     (dict(ic_kind="explicit", n_orbits=5), _abi.AW_EINVAL),  # no ic array
     (dict(chi_threshold=float("nan")), _abi.AW_EINVAL),
+    (dict(ic_kind="sphere", n_orbits=4, energy=1.0, eps=1.0), _abi.AW_EINVAL),      # E <= 2|eps|
+    (dict(ic_kind="sphere", n_orbits=4, energy=15.0, eps=1.0, window=(0.5, 0.2, -1, 1)), _abi.AW_EINVAL),
+    (dict(ic_kind="sphere", n_orbits=4, energy=15.0, eps=1.0, window=(-4.0, 0.2, -1, 1)), _abi.AW_EINVAL),
+    (dict(stay_in_window=True, window=(0, 1, -1.5, 1)), _abi.AW_EINVAL),
 ])
 def test_host_validation_rejects_bad_descriptors(kw, status):
     lib = _abi.load()

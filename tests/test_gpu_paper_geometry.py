@@ -1,0 +1,119 @@
+"""The paper's own experiments (section "Main results", Figs. 2-3): fixed
+energy on the momentum sphere, eps = 1, the density F of the direction of the
+mean velocity V, zooms and the "remained within the area" selection.
+
+Parity: initial positions bitwise, momenta to a few ulps (they take a cosine,
+a sine and Hp), states to 1e-12 at T = 50 at E = 400, window decisions equal
+except for orbits that pass within 1e-9 of an edge.  Physics: the qualitative
+facts the paper states about Fig. 2 (parity with its figures is unpinned:
+they are not printed)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import H, assert_close, gpu, need_gpu, np_, print_case
+
+pytestmark = gpu
+
+
+@pytest.fixture(scope="module")
+def aw():
+    need_gpu()
+    import paper_1107_4107_amd as m
+    return m
+
+
+def _oracle_ic(e, idx=None):
+    return oracle.ic_sphere(e.energy, e.eps, e.window[:2], e.window[2:], e.box_lo[:3], e.box_hi[:3], e.seed_ic,
+                            n_orbits=None if idx is not None else e.n_orbits, idx=idx)
+
+
+def test_sphere_initial_conditions(aw):
+    print_case("sphere ic")
+    from paper_1107_4107_amd import workloads as wl
+    for e in (wl.sphere_ensemble(400.0, 20000), wl.sphere_ensemble(15.0, 20000, window=(0.3, 1.2, -0.4, 0.1))):
+        ic, _ = aw.generate_ic(e)
+        g = np_(ic)
+        o = _oracle_ic(e)
+        np.testing.assert_array_equal(g[:3], o[:3])
+        assert_close(g[3:], o[3:], 4e-16, floor=1.0, what="P")
+        Hs = [oracle.energy(g[:, n], 1.0) for n in range(0, 20000, 101)]
+        np.testing.assert_allclose(Hs, e.energy, rtol=1e-14)
+
+
+def test_states_at_E400(aw):
+    """Weak regime of Fig. 2 (E = 400, |P| ~ 28): states after 50 steps."""
+    print_case("E=400 states")
+    from paper_1107_4107_amd import workloads as wl
+    e = wl.sphere_ensemble(400.0, 4096, T=50, tangent=True)
+    r = aw.map_ensemble(e, want_state=True)
+    ic = np_(aw.generate_ic(e)[0])           # start both sides from the same state
+    out_o, st_o = oracle.ensemble("s6", 1.0, H, 50, ic, oracle.w0(0, 4096), want_state=True)
+    assert_close(np_(r.state)[:6], st_o[:6], 1e-12, what="state")
+    assert_close(np_(r.orbit_out)[3:6], out_o[3:6], 1e-12, what="V")
+
+
+def test_window_decisions(aw):
+    """Fig. 3 zoom: orbits are kept only while the direction of P stays in the
+    window; decisions must agree unless an orbit came within 1e-9 of an edge."""
+    print_case("window flags")
+    from paper_1107_4107_amd import workloads as wl
+    e = wl.fig3_zoom(n_orbits=4096, T=1000)
+    r = aw.map_ensemble(e)
+    ic = np_(aw.generate_ic(e)[0])
+    _, left, margin = oracle.ensemble_window("s6", 1.0, H, 1000, ic, oracle.w0(0, 4096), e.window)
+    g = (np_(r.cls) >> 1) & 1
+    dis = g != left
+    assert not (dis & (np.abs(margin) > 1e-9)).any(), (dis.sum(), margin[dis][:5])
+    assert 0.05 < left.mean() < 0.95
+
+
+def test_zoomed_direction_density(aw):
+    """F on a zoom window, with and without the stay-in-window selection."""
+    print_case("zoom density")
+    from paper_1107_4107_amd import workloads as wl
+    e = wl.fig3_zoom(n_orbits=50_000, T=300)
+    spec = wl.sphere_image(128, 64, e.window)
+    img, cnt, _ = aw.indicator_image(e, spec)
+    c = np_(cnt).view(np.uint32)
+    ic = np_(aw.generate_ic(e)[0])
+    out_o, left, margin = oracle.ensemble_window("s6", 1.0, H, 300, ic, oracle.w0(0, 50_000), e.window)
+    keep = left == 0
+    safe = np.abs(margin) > 1e-9
+    assert c.sum() <= keep.sum() + (~safe).sum()
+    phi, mu = oracle.vdir_keys(out_o[3:6][:, keep & safe])
+    co, _, _ = oracle.hist2d(phi, mu, np.zeros(phi.size), (e.window[0], e.window[2]), (e.window[1], e.window[3]),
+                             128, 64, closed_upper=True)
+    diff = np.abs(c.astype(np.int64) - co.astype(np.int64))
+    assert diff.sum() <= (~safe).sum() + 2 * 4, diff.sum()   # unsafe orbits and edge items only
+    norm = 1.0 / (50_000 * ((e.window[1] - e.window[0]) / 128) * ((e.window[3] - e.window[2]) / 64))
+    assert_close(np_(img), c * norm, 1e-14, floor=0.0)
+
+
+def test_fig2_web_structure(aw):
+    """Section "Main results", Fig. 2 (E = 400, eps_eff = 0.005, Delta t = 50 T):
+    the uniform initial density stays uniform almost everywhere (regular
+    motion keeps V near P(0)), and the primary resonance m = (1, -1, 0), i.e.
+    Vx = Vy (phi = pi/4 and -3 pi/4 on the sphere), shows as a bright line
+    with a dark zone beside it."""
+    print_case("fig 2 structure")
+    from paper_1107_4107_amd import workloads as wl
+    N = 2_000_000
+    e = wl.fig2(n_orbits=N)
+    spec = wl.sphere_image(512, 256)
+    img, cnt, _ = aw.indicator_image(e, spec)
+    F = np_(img)
+    c = np_(cnt).view(np.uint32)
+    assert c.sum() == N
+    uniform = 1.0 / (4 * math.pi)
+    assert abs(np.median(F) / uniform - 1.0) < 0.05
+    prof = F.mean(axis=0)                     # density against phi, averaged over mu
+    phi = -math.pi + (np.arange(512) + 0.5) * 2 * math.pi / 512
+    med = np.median(prof)
+    for c0 in (math.pi / 4, -3 * math.pi / 4):
+        near = np.abs(phi - c0) < 0.02
+        ring = (np.abs(phi - c0) > 0.03) & (np.abs(phi - c0) < 0.08)
+        assert prof[near].max() > 1.3 * med, (c0, prof[near].max() / med)
+        assert prof[ring].min() < 0.9 * med, (c0, prof[ring].min() / med)

@@ -395,3 +395,47 @@ def test_paper_constants(orc):
         assert abs(np.dot(m, W)) < 1e-14
     assert abs(W @ W - 2 * E) < 1e-12
     assert H_PAPER == pytest.approx(g["step_over_T"]["value"] * 2 * np.pi)
+
+
+# ---------------------------------------------------------------- fixed-energy ensembles
+def test_sphere_initial_conditions_lie_on_the_energy_shell(orc):
+    """Figs. 2-3 start from a fixed total energy (eq. 1): H(P, X) = E exactly
+    up to rounding, the direction of P uniform in area on the chosen segment of
+    the sphere (uniform in phi and in mu = cos theta), X uniform on the torus."""
+    from scipy.stats import kstest
+    g = json.load(open(GOLDEN))
+    for E, seg in ((g["E_weak"]["value"], (-np.pi, np.pi, -1.0, 1.0)), (g["E_moderate"]["value"], (0.3, 0.9, 0.1, 0.4))):
+        N = 20000
+        ic = orc.ic_sphere(E, 1.0, seg[:2], seg[2:], [0, 0, 0], [2 * np.pi] * 3, 7, N)
+        H = np.array([orc.energy(ic[:, n], 1.0) for n in range(0, N, 97)])
+        np.testing.assert_allclose(H, E, rtol=1e-14)
+        P = ic[3:]
+        r = np.sqrt(np.sum(P * P, axis=0))
+        phi, mu = np.arctan2(P[1], P[0]), P[2] / r
+        assert phi.min() >= seg[0] - 1e-12 and phi.max() <= seg[1] + 1e-12
+        assert mu.min() >= seg[2] - 1e-12 and mu.max() <= seg[3] + 1e-12
+        assert kstest((phi - seg[0]) / (seg[1] - seg[0]), "uniform").pvalue > 1e-4
+        assert kstest((mu - seg[2]) / (seg[3] - seg[2]), "uniform").pvalue > 1e-4
+        assert kstest(ic[0] / (2 * np.pi), "uniform").pvalue > 1e-4
+
+
+def test_window_test(orc):
+    """The stay-in-area test: with the whole sphere as window no orbit leaves;
+    at eps = 0 the momentum is constant, so the margin is the initial one; a
+    window around an orbit's start that the orbit crosses flags it."""
+    N = 64
+    ic = orc.ic_sphere(15.0, 1.0, (-np.pi, np.pi), (-1.0, 1.0), [0, 0, 0], [2 * np.pi] * 3, 3, N)
+    w0 = orc.w0(0, N)
+    _, left, margin = orc.ensemble_window("s6", 1.0, H_PAPER, 300, ic, w0, (-np.pi, np.pi, -1.0, 1.0))
+    assert not left.any() and np.all(margin >= 0)
+    seg = (0.2, 0.6, -0.3, 0.2)
+    ic = orc.ic_sphere(15.0, 1.0, seg[:2], seg[2:], [0, 0, 0], [2 * np.pi] * 3, 5, N)
+    _, left0, m0 = orc.ensemble_window("s6", 0.0, H_PAPER, 50, ic, w0, seg)
+    P = ic[3:]
+    phi, mu = np.arctan2(P[1], P[0]), P[2] / np.sqrt(np.sum(P * P, axis=0))
+    init = np.minimum.reduce([phi - seg[0], seg[1] - phi, mu - seg[2], seg[3] - mu])
+    np.testing.assert_allclose(m0, init, atol=1e-15)
+    assert not left0.any()
+    # with the full perturbation most momenta wander out of a narrow window
+    _, left1, m1 = orc.ensemble_window("s6", 1.0, H_PAPER, 2000, ic, w0, seg)
+    assert left1.mean() > 0.5 and np.all((m1 < 0) == (left1 == 1))
