@@ -38,7 +38,8 @@ def test_sphere_initial_conditions(aw):
         g = np_(ic)
         o = _oracle_ic(e)
         np.testing.assert_array_equal(g[:3], o[:3])
-        assert_close(g[3:], o[3:], 4e-16, floor=1.0, what="P")
+        # a cosine, a sine and Hp each within a few ulps: relative to |P|
+        assert_close(g[3:], o[3:], 1e-15, floor=math.sqrt(2 * e.energy), what="P")
         Hs = [oracle.energy(g[:, n], 1.0) for n in range(0, 20000, 101)]
         np.testing.assert_allclose(Hs, e.energy, rtol=1e-14)
 
@@ -95,9 +96,9 @@ def test_zoomed_direction_density(aw):
 def test_fig2_web_structure(aw):
     """Section "Main results", Fig. 2 (E = 400, eps_eff = 0.005, Delta t = 50 T):
     the uniform initial density stays uniform almost everywhere (regular
-    motion keeps V near P(0)), and the primary resonance m = (1, -1, 0), i.e.
-    Vx = Vy (phi = pi/4 and -3 pi/4 on the sphere), shows as a bright line
-    with a dark zone beside it."""
+    motion keeps V near P(0)), and the primary resonances m = (1, -1, 0) and
+    (1, 1, 0), i.e. Vx = Vy (phi = pi/4, -3 pi/4) and Vx = -Vy (phi = -pi/4,
+    3 pi/4), show as bright lines with a dark zone beside them."""
     print_case("fig 2 structure")
     from paper_1107_4107_amd import workloads as wl
     N = 2_000_000
@@ -108,12 +109,17 @@ def test_fig2_web_structure(aw):
     c = np_(cnt).view(np.uint32)
     assert c.sum() == N
     uniform = 1.0 / (4 * math.pi)
-    assert abs(np.median(F) / uniform - 1.0) < 0.05
-    prof = F.mean(axis=0)                     # density against phi, averaged over mu
+    # density against phi, averaged over the mu rows |mu| < 0.7 (~2000 counts a column)
+    mu_c = -1.0 + (np.arange(256) + 0.5) * 2.0 / 256
+    prof = F[np.abs(mu_c) < 0.7].mean(axis=0)
     phi = -math.pi + (np.arange(512) + 0.5) * 2 * math.pi / 512
     med = np.median(prof)
-    for c0 in (math.pi / 4, -3 * math.pi / 4):
+    print(f"median density / uniform = {med / uniform:.4f}", flush=True)
+    assert abs(med / uniform - 1.0) < 0.1
+    for c0 in (math.pi / 4, -3 * math.pi / 4, -math.pi / 4, 3 * math.pi / 4):
         near = np.abs(phi - c0) < 0.02
         ring = (np.abs(phi - c0) > 0.03) & (np.abs(phi - c0) < 0.08)
-        assert prof[near].max() > 1.3 * med, (c0, prof[near].max() / med)
-        assert prof[ring].min() < 0.9 * med, (c0, prof[ring].min() / med)
+        print(f"resonance phi={c0:+.3f}: line max / median = {prof[near].max() / med:.3f}, "
+              f"side min / median = {prof[ring].min() / med:.3f}", flush=True)
+        assert prof[near].max() > 1.3 * med
+        assert prof[ring].min() < 0.9 * med
