@@ -29,6 +29,7 @@ import argparse
 import dataclasses
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -361,12 +362,99 @@ def run_sphere(args, aw, wl, torch):
     return rec, None
 
 
+def run_diffusion(args, aw, wl, torch):
+    """Fig. 4 (section "Main results"): N = 3.2e4 orbits injected at
+    W = (sqrt E, sqrt E, 0), E = 15, F accumulated over consecutive windows of
+    Delta t = 50 T (5000 steps).  The paper runs 1e9 steps per orbit (24 h on a
+    Tesla M2050); this record runs --windows windows and reports the rate, the
+    time the full horizon would take at that rate, and how far the cloud has
+    spread.  The ensemble fills only 500 waves, so the run is latency-bound;
+    blocks of 64 lanes spread it over as many CUs as possible."""
+    import numpy as np
+    n_win = args.windows
+    e = wl.fig4_cloud()
+    N = e.n_orbits
+    w = math.pi / 4
+    spec = aw.ImageSpec(kind="hist_vdir", W=512, H=512, lo=(w - 0.5, -0.5), hi=(w + 0.5, 0.5))
+    carry = torch.empty((aw.NCARRY, N), dtype=torch.float64, device="cuda")
+    counts = torch.zeros((512, 512), dtype=torch.int32, device="cuda")
+    tun = aw.Tuning(block=64)
+    aw.timing_read()
+    aw.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    spread = []
+    while done < n_win:
+        k = min(50, n_win - done)
+        aw.window_density(e, carry, done * wl.DT50, k, wl.DT50, spec, counts, tuning=tun)
+        torch.cuda.synchronize()
+        done += k
+        P = carry[3:6].cpu().numpy()
+        d = np.arctan2(P[1], P[0]) - w
+        spread.append(float(np.std(d)))
+        log(f"windows {done}/{n_win} ({time.perf_counter() - t0:.1f} s), spread of phi(P) {spread[-1]:.4f}")
+    elapsed = time.perf_counter() - t0
+    aw.timing_enable(False)
+    kern_ms, launches = aw.timing_read()
+    steps = n_win * wl.DT50
+    rate = N * steps / elapsed
+    rec = base_record(rate, 1, 0, elapsed * 1e3)
+    rec["metric"] = "orbit map-steps/sec (state only, as in the paper's experiment)"
+    rec["config"] = {"workload": f"fig4: E=15, eps=1, N={N} cloud at W=(sqrt E, sqrt E, 0), sigma_v=0.01, "
+                                 f"{n_win} windows of 50 T (5000 steps), F zoom 512x512 around W",
+                     "n_orbits": N, "n_steps": steps}
+    rec["roofline"] = roofline(aw, e, kern_ms / max(launches, 1), "fig4", steps_per_launch=wl.DT50)
+    rec["wall_s"] = elapsed
+    rec["projected_s_for_1e9_steps"] = N * 1e9 / rate
+    rec["paper_wall_s"] = 24 * 3600.0
+    rec["paper_hardware"] = "NVIDIA Tesla M2050, FP64 (section Main results: 24 hours for 1e9 steps per orbit)"
+    rec["binned_total"] = int(counts.cpu().numpy().view(np.uint32).sum())
+    rec["phi_spread_by_50_windows"] = spread
+    return rec, None
+
+
+def run_sweep(args, aw, wl, torch):
+    """Chaotic fraction (chi > 2) against eps on the literal slice and on the
+    pz0 = 1 companion (256 x 256, T = 3e4, 16 eps values), each slice as one
+    batched launch; the slope of log(fraction) against log(eps) is compared
+    with the sqrt(eps) web-volume scaling of the model section."""
+    import numpy as np
+    rec = None
+    out = {}
+    t_all = 0.0
+    for pz0 in (0.0, 1.0):
+        ens = wl.eps_sweep(pz0=pz0)
+        spec = aw.ImageSpec(kind="ic_grid", field=aw.OUT_CHI, W=0, H=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        imgs, cnts, _ = aw.indicator_images(ens, spec, want_counts=True)
+        torch.cuda.synchronize()
+        t_all += time.perf_counter() - t0
+        eps = np.array([e.eps for e in ens])
+        frac = np.array([int(c.cpu().numpy().view(np.uint32)[0]) for c in cnts]) / (ens[0].nx * ens[0].ny)
+        ok = frac > 0
+        slope = float(np.polyfit(np.log(eps[ok]), np.log(frac[ok]), 1)[0]) if ok.sum() >= 3 else None
+        out[f"pz0={pz0:g}"] = {"eps": eps.tolist(), "chaotic_fraction": frac.tolist(),
+                               "loglog_slope": slope}
+        log(f"pz0={pz0}: fractions {np.array2string(frac, precision=4)} slope {slope}")
+    steps = 2 * sum(e.size * e.n_steps for e in wl.eps_sweep())
+    rec = base_record(steps / t_all, 1, 0, t_all * 1e3)
+    rec["config"] = {"workload": "eps sweep: 16 eps log-spaced 1e-4..1e-1, 256x256 (px,py) slice, T=3e4, "
+                                 "S6 + tangent, literal slice and pz0=1 companion, one batched launch each",
+                     "map_steps": steps}
+    rec["sweep"] = out
+    rec["paper_claim"] = "web volume ~ sqrt(eps) (model section): log-log slope 0.5"
+    return rec, None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "fig2", "fig3"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "fig2", "fig3", "fig4", "sweep"])
+    ap.add_argument("--windows", type=int, default=200, help="fig4: number of 50 T windows")
     ap.add_argument("--t-scale", type=float, default=1.0, help="c3/c5: scale the horizons")
     ap.add_argument("--n-orbits", type=int, default=10_000_000, help="c5: ensemble size")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -401,7 +489,7 @@ def main():
         log(f"calibration copy of {args.copy_mib} MiB done")
         del src, dst
     runner = {"c1": run_slice, "c2": run_slice, "c3": run_batched, "c4": run_adjoint, "c5": run_large,
-              "fig2": run_sphere, "fig3": run_sphere}
+              "fig2": run_sphere, "fig3": run_sphere, "fig4": run_diffusion, "sweep": run_sweep}
     rec, ens = runner[args.workload](args, aw, wl, torch)
     rec.setdefault("cpu_baseline", None)
     if ens is not None and not args.no_cpu_baseline and args.workload in ("c1", "c2", "c5"):

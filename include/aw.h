@@ -79,8 +79,19 @@ typedef enum { AW_MAP_STDMAP = 1, AW_MAP_S2 = 2, AW_MAP_S4 = 4, AW_MAP_S6 = 6 } 
  * U(seed, c) = (SplitMix64 output number c of the stream seeded with `seed`,
  * i.e. mix(seed + (c+1)*0x9E3779B97F4A7C15)) >> 11, times 2^-53.
  * The tangent start of orbit n is w0 = u/|u|, u_k = 2 U(seed_tangent, 16 n + k) - 1,
- * for every ic_kind.  Coordinate order is (x, y, z, px, py, pz). */
-typedef enum { AW_IC_GRID2 = 0, AW_IC_BOX = 1, AW_IC_EXPLICIT = 2, AW_IC_SPHERE = 3 } aw_ic_kind;
+ * for every ic_kind.  Coordinate order is (x, y, z, px, py, pz).
+ *  CLOUD:    the injected cloud of Fig. 4: velocity components
+ *            vx = cloud[0] + cloud[2] g1, vy = cloud[1] + cloud[3] g2 with a
+ *            Box-Muller pair g1 = r cos(2 pi u2), g2 = r sin(2 pi u2),
+ *            r = sqrt(-2 ln(1 - u1)), u1 = U(seed_ic, 128 n + 120),
+ *            u2 = U(seed_ic, 128 n + 121); X uniform on the box (first three
+ *            coordinates) drawn at attempt a = 0, 1, ... < 40 from
+ *            U(seed_ic, 128 n + 3 a + k), taking the first X with
+ *            R = 2 (energy - eps Hp(X)) - vx^2 - vy^2 >= 0 (after 40 failed
+ *            attempts the last X with R clamped to 0); vz = s sqrt(R) with
+ *            s = -1 if U(seed_ic, 128 n + 122) < 1/2 else +1.  H = energy.
+ *            Needs energy > 2|eps| and finite cloud values. */
+typedef enum { AW_IC_GRID2 = 0, AW_IC_BOX = 1, AW_IC_EXPLICIT = 2, AW_IC_SPHERE = 3, AW_IC_CLOUD = 4 } aw_ic_kind;
 
 /* flags */
 #define AW_F_TANGENT 1u  /* propagate the tangent vector (L, lambda, chi, class) */
@@ -123,8 +134,9 @@ typedef struct {
   uint64_t seed_tangent;  /* tangent start */
   double chi_threshold;   /* class = chi > chi_threshold */
   uint32_t flags;         /* AW_F_* */
-  double energy;          /* SPHERE: total energy E of eq. 1 */
+  double energy;          /* SPHERE, CLOUD: total energy E of eq. 1 */
   double window[4];       /* SPHERE segment / AW_F_WINDOW area: phi_lo, phi_hi, mu_lo, mu_hi */
+  double cloud[4];        /* CLOUD: centre (vx, vy) and standard deviations (sigma_x, sigma_y) */
 } aw_ensemble;
 
 /* Launch shape.  NULL = defaults (block 256, one orbit per lane, step loop not
@@ -213,6 +225,24 @@ typedef struct {
 aw_status aw_indicator_image(const aw_ensemble *ens, int32_t n_ens, const aw_image_spec *spec,
                              double *const *image_dev, uint32_t *const *counts_dev,
                              uint8_t *const *cls_dev, const aw_tuning *tuning, void *stream);
+
+/* Time-window density of Fig. 4 (section "Main results"): F averaged over the
+ * windows between two plots.  Runs n_windows consecutive windows of
+ * window_steps map steps each, starting at global step k_begin (0 = from the
+ * initial conditions, else from carry_dev), for one ensemble.  For every
+ * window w the mean velocity V_w = (X(end) - X(start)) / (window_steps h) of
+ * each orbit is binned as in HIST_VDIR (spec->kind must be AW_IMG_HIST_VDIR;
+ * spec->lo/hi zoom as there) and ADDED to counts_accum_dev [H][W] (uint32;
+ * the caller zeroes it once); orbits that left the window under AW_F_WINDOW
+ * are not added.  The state after the last window is left in carry_dev
+ * [AW_NCARRY][N] (required), so consecutive calls continue the run; the
+ * averaged density is counts / (n_windows_total N dphi dmu).  Needs
+ * k_begin + n_windows window_steps <= n_steps.  The per-window results are
+ * bitwise independent of how the windows are split over calls. */
+aw_status aw_window_density(const aw_ensemble *ens, const double *ic_dev, double *carry_dev,
+                            int64_t k_begin, int64_t n_windows, int64_t window_steps,
+                            const aw_image_spec *spec, uint32_t *counts_accum_dev,
+                            const aw_tuning *tuning, void *stream);
 
 /* The histogram reduction on its own, over caller keys a_dev[N], b_dev[N] and
  * values v_dev[N] (v_dev may be NULL: the sums are then zero): bin along

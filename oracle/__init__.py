@@ -67,6 +67,8 @@ def _load():
         "oracle_ic_grid2": (i, [i, i, d, d, d, d, l, l, _dp, _lp, l, _dp]),
         "oracle_ic_box": (None, [_dp, _dp, u64, _lp, l, _dp]),
         "oracle_ic_sphere": (None, [d, d, d, d, d, d, _dp, _dp, u64, _lp, l, _dp]),
+        "oracle_ic_cloud": (None, [d, d, _dp, _dp, _dp, u64, _lp, l, _dp]),
+        "oracle_window_velocities": (i, [i, d, d, l, _dp, l, l, _dp, i]),
         "oracle_ensemble_window": (i, [i, d, d, l, l, _dp, _dp, _dp, _dp, ctypes.POINTER(ctypes.c_uint8), _dp, i]),
         "oracle_w0": (None, [u64, _lp, l, _dp]),
         "oracle_hist2d": (l, [l, _dp, _dp, _dp, d, d, d, d, i, i, i, _up, _dp]),
@@ -146,6 +148,27 @@ def ic_sphere(E, eps, phi, mu, xlo, xhi, seed, n_orbits=None, idx=None):
     lo_, hi_ = _f64(xlo, (3,)), _f64(xhi, (3,))
     _load().oracle_ic_sphere(E, eps, phi[0], phi[1], mu[0], mu[1], _ptr(lo_), _ptr(hi_), seed, ip, M, _ptr(ic))
     return ic
+
+
+def ic_cloud(E, eps, cloud, xlo, xhi, seed, n_orbits=None, idx=None):
+    """Fig. 4 cloud: Gaussian (vx, vy), X on the torus by rejection, vz from H = E."""
+    idx, ip = _idx(idx)
+    M = n_orbits if idx is None else len(idx)
+    ic = np.empty((6, M))
+    _load().oracle_ic_cloud(E, eps, _ptr(_f64(cloud, (4,))), _ptr(_f64(xlo, (3,))), _ptr(_f64(xhi, (3,))), seed, ip,
+                            M, _ptr(ic))
+    return ic
+
+
+def window_velocities(form, eps, h, ic, n_windows, window_steps, nthreads=0):
+    """Mean velocity of every orbit over consecutive windows: V[n_windows, 3, N]."""
+    ic = _f64(ic)
+    N = ic.shape[1]
+    V = np.empty((n_windows, 3, N))
+    if _load().oracle_window_velocities(_form(form), eps, h, N, _ptr(ic), int(n_windows), int(window_steps), _ptr(V),
+                                        int(nthreads)):
+        raise ValueError("oracle_window_velocities rejected its arguments")
+    return V
 
 
 def ensemble_window(form, eps, h, T, ic, w0_, window, nthreads=0):

@@ -64,6 +64,9 @@
 #define OR_DE 8
 #define OR_NOUT 9
 
+/* pi rounded to double (the value of the POSIX M_PI). */
+#define OR_PI 3.14159265358979323846
+
 /* ------------------------------------------------------------------------ */
 /* Eq. 2 and its first and second derivatives, written from the formula.    */
 /* ------------------------------------------------------------------------ */
@@ -471,6 +474,62 @@ void oracle_ic_sphere(double E, double eps, double phi_lo, double phi_hi, double
             ic[(3 + k) * M + m] = P[k];
         }
     }
+}
+
+/* The injected cloud of Fig. 4 (section "Main results"): the velocity
+ * components (vx, vy) Gaussian around cloud[0..1] with standard deviations
+ * cloud[2..3] (Box-Muller: g1 = r cos(2 pi u2), g2 = r sin(2 pi u2),
+ * r = sqrt(-2 ln(1 - u1))), X uniform on the box, redrawn until the energy
+ * condition H = E leaves a real vz: R = 2 (E - eps Hp(X)) - vx^2 - vy^2 >= 0
+ * (at most 40 draws; after that R is taken as 0), vz = +-sqrt(R) with the
+ * sign drawn with probability 1/2.  Counters: X at attempt a from
+ * 128 n + 3 a + k, u1 = 128 n + 120, u2 = 128 n + 121, sign 128 n + 122. */
+void oracle_ic_cloud(double E, double eps, const double cloud[4], const double xlo[3], const double xhi[3],
+                     uint64_t seed, const long *idx, long M, double *ic)
+{
+    for (long m = 0; m < M; m++) {
+        long n = pick(idx, m);
+        uint64_t c = 128u * (uint64_t)n;
+        double u1 = oracle_u01(seed, c + 120u), u2 = oracle_u01(seed, c + 121u);
+        double r = sqrt(-2.0 * log(1.0 - u1));
+        double vx = cloud[0] + cloud[2] * (r * cos(2.0 * OR_PI * u2));
+        double vy = cloud[1] + cloud[3] * (r * sin(2.0 * OR_PI * u2));
+        double X[3] = {0, 0, 0}, R = -1.0;
+        for (int a = 0; a < 40 && R < 0.0; a++) {
+            for (int k = 0; k < 3; k++)
+                X[k] = xlo[k] + (xhi[k] - xlo[k]) * oracle_u01(seed, c + 3u * (uint64_t)a + (uint64_t)k);
+            R = 2.0 * (E - eps * hp_value(X)) - vx * vx - vy * vy;
+        }
+        double vz = sqrt(R > 0.0 ? R : 0.0);
+        if (oracle_u01(seed, c + 122u) < 0.5) vz = -vz;
+        double s[6] = {X[0], X[1], X[2], vx, vy, vz};
+        for (int k = 0; k < 6; k++) ic[k * M + m] = s[k];
+    }
+}
+
+/* Mean velocities over consecutive time windows (section "Main results",
+ * Fig. 4: V_w = [X(t_w + dt) - X(t_w)] / dt with t_w = w dt): V[w][3][N] for
+ * w < n_windows, each window of window_steps map steps.  No tangent. */
+int oracle_window_velocities(int form, double eps, double h, long N, const double *ic, long n_windows,
+                             long window_steps, double *V, int nthreads)
+{
+    if (form != OR_STDMAP && form != OR_S2 && form != OR_S4 && form != OR_S6) return -1;
+    if (n_windows < 1 || window_steps < 1 || N < 0) return -1;
+    double dt = (double)window_steps * h;
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+#endif
+    for (long n = 0; n < N; n++) {
+        double s[6];
+        for (int a = 0; a < 6; a++) s[a] = ic[a * N + n];
+        for (long w = 0; w < n_windows; w++) {
+            double x0[3] = {s[0], s[1], s[2]};
+            oracle_map(form, eps, h, window_steps, s);
+            for (int a = 0; a < 3; a++) V[(w * 3 + a) * N + n] = (s[a] - x0[a]) / dt;
+        }
+    }
+    return 0;
 }
 
 /* Signed distance of the direction of P from the window in (phi, mu)

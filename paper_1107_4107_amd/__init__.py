@@ -83,6 +83,7 @@ class Ensemble:
     energy: float = 0.0                 # sphere: total energy E (eq. 1)
     window: Sequence[float] = (-math.pi, math.pi, -1.0, 1.0)   # phi_lo, phi_hi, mu_lo, mu_hi
     stay_in_window: bool = False        # the "remained within the area" test
+    cloud: Sequence[float] = (0.0, 0.0, 0.0, 0.0)   # cloud: centre (vx, vy), sigma (x, y)
 
     def to_c(self) -> _abi.AwEnsemble:
         e = _abi.AwEnsemble()
@@ -91,7 +92,8 @@ class Ensemble:
         e.eps = float(self.eps)
         e.h = float(self.h)
         e.n_steps = int(self.n_steps)
-        e.ic_kind = {"grid2": IC_GRID2, "box": IC_BOX, "explicit": IC_EXPLICIT, "sphere": IC_SPHERE}[self.ic_kind]
+        e.ic_kind = {"grid2": IC_GRID2, "box": IC_BOX, "explicit": IC_EXPLICIT, "sphere": IC_SPHERE,
+                     "cloud": _abi.IC_CLOUD}[self.ic_kind]
         e.axis[:] = [int(a) for a in self.axis]
         e.lo[:] = [float(v) for v in self.lo]
         e.hi[:] = [float(v) for v in self.hi]
@@ -106,6 +108,7 @@ class Ensemble:
         e.flags = (F_TANGENT if self.tangent else 0) | (F_WINDOW if self.stay_in_window else 0)
         e.energy = float(self.energy)
         e.window[:] = [float(v) for v in self.window]
+        e.cloud[:] = [float(v) for v in self.cloud]
         return e
 
     @property
@@ -250,6 +253,22 @@ def indicator_image(ens: Ensemble, spec: ImageSpec, want_counts: bool = True, wa
                     tuning: Optional[Tuning] = None):
     imgs, cnts, clss = indicator_images([ens], spec, want_counts, want_class, tuning)
     return imgs[0], (cnts[0] if cnts else None), (clss[0] if clss else None)
+
+
+def window_density(ens: Ensemble, carry: torch.Tensor, k_begin: int, n_windows: int, window_steps: int,
+                   spec: ImageSpec, counts: torch.Tensor, ic: Optional[torch.Tensor] = None,
+                   tuning: Optional[Tuning] = None) -> None:
+    """Add the direction counts of V over n_windows consecutive windows to
+    counts[H, W] (int32 holding uint32); the state is carried in carry[22, N]."""
+    N = ens.size
+    _dev_f64(carry, (NCARRY, N), "carry")
+    if counts.dtype != torch.int32 or tuple(counts.shape) != (spec.H, spec.W) or not counts.is_contiguous():
+        raise ValueError("counts must be a contiguous int32 [H, W] tensor")
+    if ic is not None:
+        _dev_f64(ic, (6, N), "ic")
+    _abi.check(_lib().aw_window_density(ctypes.byref(ens.to_c()), _p(ic), _p(carry), int(k_begin), int(n_windows),
+                                        int(window_steps), ctypes.byref(spec.to_c()), _p(counts),
+                                        _tuning_ptr(tuning), _stream()))
 
 
 def histogram2d(a: torch.Tensor, b: torch.Tensor, v: Optional[torch.Tensor], lo, hi, W: int, H: int,

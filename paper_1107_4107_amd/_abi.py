@@ -11,7 +11,7 @@ AW_OK, AW_EINVAL, AW_EUNSUPPORTED, AW_EDEVICE, AW_ENOMEM, AW_EWORKSPACE = range(
 STATUS_NAMES = {0: "AW_OK", 1: "AW_EINVAL", 2: "AW_EUNSUPPORTED", 3: "AW_EDEVICE", 4: "AW_ENOMEM",
                 5: "AW_EWORKSPACE"}
 MAP_STDMAP, MAP_S2, MAP_S4, MAP_S6 = 1, 2, 4, 6
-IC_GRID2, IC_BOX, IC_EXPLICIT, IC_SPHERE = 0, 1, 2, 3
+IC_GRID2, IC_BOX, IC_EXPLICIT, IC_SPHERE, IC_CLOUD = 0, 1, 2, 3, 4
 F_TANGENT = 1
 F_WINDOW = 2
 OUT_L, OUT_LAMBDA, OUT_CHI, OUT_VX, OUT_VY, OUT_VZ, OUT_DP2, OUT_J, OUT_DE, NOUT = range(10)
@@ -20,7 +20,7 @@ IMG_IC_GRID, IMG_HIST_P0, IMG_HIST_VDIR = 0, 1, 2
 
 EXPORTS = [
     "aw_last_error", "aw_version", "aw_release", "aw_ensemble_size", "aw_generate_ic",
-    "aw_map_ensemble", "aw_map_ensemble_steps", "aw_indicator_image", "aw_histogram2d",
+    "aw_map_ensemble", "aw_map_ensemble_steps", "aw_indicator_image", "aw_window_density", "aw_histogram2d",
     "aw_vdir_keys", "aw_indicator_grad_workspace", "aw_indicator_grad", "aw_graph_create",
     "aw_graph_launch", "aw_graph_destroy", "aw_timing_enable", "aw_timing_read",
     "aw_step_op_counts",
@@ -50,6 +50,7 @@ class AwEnsemble(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("energy", ctypes.c_double),
         ("window", ctypes.c_double * 4),
+        ("cloud", ctypes.c_double * 4),
     ]
 
 
@@ -91,6 +92,7 @@ SIGNATURES = {
     "aw_map_ensemble": (_i32, [_PE, _i32, _PP, _PP, _PP, _PP, _PT, _vp]),
     "aw_map_ensemble_steps": (_i32, [_PE, _vp, _vp, _i64, _i64, _vp, _vp, _vp, _PT, _vp]),
     "aw_indicator_image": (_i32, [_PE, _i32, _PS, _PP, _PP, _PP, _PT, _vp]),
+    "aw_window_density": (_i32, [_PE, _vp, _vp, _i64, _i64, _i64, _PS, _vp, _PT, _vp]),
     "aw_histogram2d": (_i32, [_i64, _vp, _vp, _vp, _f64, _f64, _f64, _f64, _i32, _i32, _i32, _vp, _vp, _vp, _vp]),
     "aw_vdir_keys": (_i32, [_i64, _vp, _vp, _vp, _vp]),
     "aw_indicator_grad_workspace": (_i32, [_PE, _i64, ctypes.POINTER(ctypes.c_size_t)]),

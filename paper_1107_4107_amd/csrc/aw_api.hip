@@ -259,6 +259,15 @@ aw_status check_ensemble(const aw_ensemble *e, const double *ic, int idx) {
   case AW_IC_EXPLICIT:
     if (N > 0 && !ic) return fail(AW_EINVAL, "ensemble %d: EXPLICIT needs ic_dev", idx);
     break;
+  case AW_IC_CLOUD:
+    for (int k = 0; k < 3; ++k)
+      if (!is_fin(e->box_lo[k]) || !is_fin(e->box_hi[k]) || !is_fin(e->box_hi[k] - e->box_lo[k]))
+        return fail(AW_EINVAL, "ensemble %d: CLOUD position range not finite", idx);
+    for (int k = 0; k < 4; ++k)
+      if (!is_fin(e->cloud[k])) return fail(AW_EINVAL, "ensemble %d: CLOUD values not finite", idx);
+    if (!is_fin(e->energy) || !(e->energy > 2.0 * std::fabs(e->eps)))
+      return fail(AW_EINVAL, "ensemble %d: CLOUD needs energy > 2|eps| (|Hp| <= 2, eq. 2)", idx);
+    break;
   case AW_IC_SPHERE:
     for (int k = 0; k < 3; ++k)
       if (!is_fin(e->box_lo[k]) || !is_fin(e->box_hi[k]) || !is_fin(e->box_hi[k] - e->box_lo[k]))
@@ -313,6 +322,7 @@ FwdDesc make_desc(const aw_ensemble &e, const double *ic, const Tuning &t) {
   d.epi = EPI_NONE;
   d.energy = e.energy;
   for (int k = 0; k < 4; ++k) d.win[k] = e.window[k];
+  for (int k = 0; k < 4; ++k) d.cloud[k] = e.cloud[k];
   d.filter = (e.flags & AW_F_WINDOW) ? 1 : 0;
   if (d.filter) {
     const double w = e.window[1] - e.window[0];
@@ -662,6 +672,49 @@ aw_status aw_indicator_image(const aw_ensemble *ens, int32_t n_ens, const aw_ima
   Tuning t;
   if ((st = check_tuning(tuning, t)) != AW_OK) return st;
   return image_run(ens, n_ens, spec, image_dev, counts_dev, cls_dev, t, (hipStream_t)stream);
+}
+
+aw_status aw_window_density(const aw_ensemble *ens, const double *ic_dev, double *carry_dev, int64_t k_begin,
+                            int64_t n_windows, int64_t window_steps, const aw_image_spec *spec,
+                            uint32_t *counts_accum_dev, const aw_tuning *tuning, void *stream) {
+  aw_status st = check_ensemble(ens, ic_dev, 0);
+  if (st != AW_OK) return st;
+  Tuning t;
+  if ((st = check_tuning(tuning, t)) != AW_OK) return st;
+  if (!spec || spec->kind != AW_IMG_HIST_VDIR) return fail(AW_EINVAL, "aw_window_density needs a HIST_VDIR spec");
+  if (!carry_dev) return fail(AW_EINVAL, "aw_window_density needs carry_dev");
+  if (!counts_accum_dev) return fail(AW_EINVAL, "null counts_accum_dev");
+  if (k_begin < 0 || n_windows < 1 || window_steps < 1 || n_windows > (ens->n_steps - k_begin) / window_steps)
+    return fail(AW_EINVAL, "need k_begin >= 0, n_windows, window_steps >= 1 and "
+                           "k_begin + n_windows * window_steps <= n_steps");
+  FwdDesc d = make_desc(*ens, ic_dev, t);
+  // The density image is bound to the spec; apply_image checks the zoom and the tile count.
+  double dummy_img = 0.0;
+  if ((st = apply_image(spec, *ens, 0, d, &dummy_img, nullptr)) != AW_OK) return st;
+  d.img = nullptr;
+  d.epi = EPI_NONE;
+  d.window_v = 1;
+  d.wdt = (double)window_steps * ens->h;
+  d.carry = carry_dev;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DevScratch &sc = scratch();
+  hipError_t e;
+  if ((e = grow(sc.bins, sizeof(uint32_t) * (size_t)std::max<int64_t>(d.N, 1))) != hipSuccess)
+    return fail(AW_ENOMEM, "window scratch: %s", hipGetErrorString(e));
+  const HistPlan p = hist_plan(d.N, spec->W, spec->H);
+  HistScratch w;
+  if ((st = hist_scratch(sc, p, d.N, false, w)) != AW_OK) return st;
+  d.bins = (uint32_t *)sc.bins.p;
+  hipStream_t s = (hipStream_t)stream;
+  for (int64_t k = 0; k < n_windows; ++k) {
+    d.k_begin = k_begin + k * window_steps;
+    d.k_end = d.k_begin + window_steps;
+    if ((st = launch_one(d, t, ens->map_form, tangent_on(*ens), s)) != AW_OK) return st;
+    if ((e = launch_hist_reduce(d.N, d.bins, nullptr, p, w, 2, 0.0, counts_accum_dev, nullptr, nullptr, s, 1)) !=
+        hipSuccess)
+      return hip_fail(e, "window histogram");
+  }
+  return AW_OK;
 }
 
 aw_status aw_histogram2d(int64_t N, const double *a_dev, const double *b_dev, const double *v_dev, double lo0,

@@ -48,6 +48,27 @@ __device__ __forceinline__ void gen_ic(const FwdDesc &d, int64_t n, double s[6])
     s[3] = p * st * cp;
     s[4] = p * st * sp;
     s[5] = p * mu;
+  } else if (d.ic_kind == 4) {
+    // Fig. 4 cloud: Gaussian (vx, vy) by Box-Muller, X on the torus by
+    // rejection until the energy condition leaves a real vz.
+    const uint64_t c = 128ull * (uint64_t)n;
+    const double u1 = u01(d.seed_ic, c + 120ull), u2 = u01(d.seed_ic, c + 121ull);
+    const double rr = sqrt(-2.0 * log(1.0 - u1));
+    double sg, cg;
+    sincos_full(2.0 * M_PI * u2, sg, cg);
+    const double vx = d.cloud[0] + d.cloud[2] * (rr * cg);
+    const double vy = d.cloud[1] + d.cloud[3] * (rr * sg);
+    double R = -1.0;
+    for (int a = 0; a < 40 && R < 0.0; ++a) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        s[k] = d.box_lo[k] + d.box_span[k] * u01(d.seed_ic, c + 3ull * (uint64_t)a + (uint64_t)k);
+      R = 2.0 * (d.energy - d.eps * hp_value(s[0], s[1], s[2])) - vx * vx - vy * vy;
+    }
+    const double vz = sqrt(R > 0.0 ? R : 0.0);
+    s[3] = vx;
+    s[4] = vy;
+    s[5] = u01(d.seed_ic, c + 122ull) < 0.5 ? -vz : vz;
   } else {
 #pragma unroll
     for (int k = 0; k < 6; ++k) s[k] = d.ic[k * d.N + n];
@@ -152,7 +173,7 @@ __device__ __forceinline__ bool in_window(double px, double py, double pz, const
 // Run the orbits first + j*blockDim.x + threadIdx.x (j < OPL) over global
 // steps [k_begin, k_end).  FILT: test the window after every step.
 // ---------------------------------------------------------------------------
-template <int FORM, bool TAN, int OPL, int UNR, bool FILT = false>
+template <int FORM, bool TAN, int OPL, int UNR, bool FILT = false, bool WINV = false>
 __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first) {
   int64_t n[OPL];
   bool act[OPL];
@@ -200,6 +221,17 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first) {
     }
   }
 
+  // Positions at the start of this launch (time-window velocity).
+  double xs[OPL], ys[OPL], zs[OPL];
+  if (WINV) {
+#pragma unroll
+    for (int j = 0; j < OPL; ++j) {
+      xs[j] = o[j].x;
+      ys[j] = o[j].y;
+      zs[j] = o[j].z;
+    }
+  }
+
   // Hot loop.  The trip count and the renormalisation test are uniform.
   const int64_t k0 = d.k_begin, k1 = d.k_end;
   const int64_t mask = d.renorm_mask;
@@ -218,11 +250,16 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first) {
     }
   }
 
-  if (k1 < d.T) {
-    // Intermediate launch: store the resumable carry.
+  if (k1 < d.T || WINV) {
+    // Intermediate launch (or a time window): store the resumable carry.
 #pragma unroll
     for (int j = 0; j < OPL; ++j) {
       if (!act[j]) continue;
+      if (WINV) {
+        double phi, mu;
+        vdir_key((o[j].x - xs[j]) / d.wdt, (o[j].y - ys[j]) / d.wdt, (o[j].z - zs[j]) / d.wdt, phi, mu);
+        d.bins[n[j]] = left[j] ? BIN_DROP : bin_of(phi, mu, d.klo0, d.khi0, d.klo1, d.khi1, d.W, d.H, true);
+      }
       double *c = d.carry;
       const int64_t N = d.N, m = n[j];
       double s0[6];
@@ -319,10 +356,10 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first) {
   }
 }
 
-template <int FORM, bool TAN, int OPL, int UNR, bool FILT = false>
+template <int FORM, bool TAN, int OPL, int UNR, bool FILT = false, bool WINV = false>
 __global__ __launch_bounds__(256) void k_fwd(FwdDesc d) {
   const int64_t first = (int64_t)blockIdx.x * blockDim.x * OPL;
-  run_orbits<FORM, TAN, OPL, UNR, FILT>(d, first);
+  run_orbits<FORM, TAN, OPL, UNR, FILT, WINV>(d, first);
 }
 
 // Persistent batched propagation: each workgroup takes (ensemble, tile)
@@ -374,10 +411,13 @@ static hipError_t fwd_dispatch_opl(const FwdDesc &d, const Tuning &t, hipStream_
   const int64_t blocks = (d.N + per_block - 1) / per_block;
   if (blocks <= 0) return hipSuccess;
   dim3 grid((unsigned)blocks), block((unsigned)t.block);
-  if (d.filter) {
-    // The window test runs with one orbit per lane and no unrolling.
-    const int64_t wblocks = (d.N + t.block - 1) / t.block;
-    hipLaunchKernelGGL((k_fwd<FORM, TAN, 1, 1, true>), dim3((unsigned)wblocks), block, 0, s, d);
+  if (d.filter || d.window_v) {
+    // The window test and the time-window velocity run with one orbit per
+    // lane and no unrolling.
+    const dim3 wgrid((unsigned)((d.N + t.block - 1) / t.block));
+    if (d.filter && d.window_v) hipLaunchKernelGGL((k_fwd<FORM, TAN, 1, 1, true, true>), wgrid, block, 0, s, d);
+    else if (d.filter) hipLaunchKernelGGL((k_fwd<FORM, TAN, 1, 1, true, false>), wgrid, block, 0, s, d);
+    else hipLaunchKernelGGL((k_fwd<FORM, TAN, 1, 1, false, true>), wgrid, block, 0, s, d);
   } else if (t.opl == 1 && t.unroll == 1) hipLaunchKernelGGL((k_fwd<FORM, TAN, 1, 1>), grid, block, 0, s, d);
   else if (t.opl == 1) hipLaunchKernelGGL((k_fwd<FORM, TAN, 1, 2>), grid, block, 0, s, d);
   else if (t.unroll == 1) hipLaunchKernelGGL((k_fwd<FORM, TAN, 2, 1>), grid, block, 0, s, d);

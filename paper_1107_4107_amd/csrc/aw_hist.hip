@@ -164,7 +164,7 @@ __global__ __launch_bounds__(HIST_BLOCK) void k_tile_scatter(int64_t N, const ui
 __global__ __launch_bounds__(HIST_BLOCK) void k_tile_accum(const uint32_t *__restrict__ tile_start,
                                                            const uint16_t *__restrict__ sorted_local,
                                                            const double *__restrict__ sorted_val,
-                                                           TileGeom g, int32_t mode, double norm,
+                                                           TileGeom g, int32_t mode, double norm, int32_t accumulate,
                                                            uint32_t *__restrict__ counts_out,
                                                            double *__restrict__ f_out) {
   __shared__ uint32_t c[TILE_BINS];
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(HIST_BLOCK) void k_tile_accum(const uint32_t *__res
     if (i >= g.W || j >= g.H) continue;
     const int64_t o = (int64_t)j * g.W + i;
     const uint32_t cc = c[k];
-    if (counts_out) counts_out[o] = cc;
+    if (counts_out) counts_out[o] = accumulate ? counts_out[o] + cc : cc;
     if (f_out) {
       double f;
       if (mode == 0) f = s[k];
@@ -233,7 +233,7 @@ HistPlan hist_plan(int64_t N, int W, int H) {
 
 hipError_t launch_hist_reduce(int64_t N, const uint32_t *bins, const double *vals, const HistPlan &p,
                               const HistScratch &w, int mode, double norm, uint32_t *counts_out,
-                              double *f_out, uint64_t *dropped_out, hipStream_t s) {
+                              double *f_out, uint64_t *dropped_out, hipStream_t s, int accumulate) {
   TileGeom g{p.W, p.H, p.tiles_x, p.n_tiles};
   if (N > 0) {
     hipLaunchKernelGGL(k_tile_count, dim3((unsigned)p.G), dim3(HIST_BLOCK), 0, s, N, bins, g, p.G,
@@ -250,7 +250,7 @@ hipError_t launch_hist_reduce(int64_t N, const uint32_t *bins, const double *val
     hipLaunchKernelGGL(k_tile_scatter, dim3((unsigned)p.G), dim3(HIST_BLOCK), 0, s, N, bins, vals, g, p.G,
                        w.block_counts, w.sorted_local, vals ? w.sorted_val : nullptr);
   hipLaunchKernelGGL(k_tile_accum, dim3((unsigned)p.n_tiles), dim3(HIST_BLOCK), 0, s, w.tile_start,
-                     w.sorted_local, vals ? w.sorted_val : nullptr, g, mode, norm, counts_out, f_out);
+                     w.sorted_local, vals ? w.sorted_val : nullptr, g, mode, norm, accumulate, counts_out, f_out);
   return hipGetLastError();
 }
 

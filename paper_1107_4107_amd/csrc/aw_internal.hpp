@@ -76,7 +76,9 @@ struct FwdDesc {
   int32_t win_phi;        // 0: every phi; 1: sector of width <= pi; 2: complement of a sector < pi
   int32_t win_mu;         // 0: every mu; 1: test mu_lo <= pz/|P| <= mu_hi
   int32_t filter;         // test the window after every step
-  int32_t pad_;
+  int32_t window_v;       // bin the mean velocity of this launch's steps (time-window density)
+  double cloud[4];        // CLOUD: centre (vx, vy), sigma (x, y)
+  double wdt;             // window_v: length of the window in time (steps x h)
   const double *ic;  // EXPLICIT [6][N]
   double *carry;     // [AW_NCARRY][N] or null
   double *out;       // [AW_NOUT][N] or null

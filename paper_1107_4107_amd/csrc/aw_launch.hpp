@@ -46,9 +46,10 @@ hipError_t launch_hist_bins(int64_t N, const double *a, const double *b, const d
                             double hi0, double lo1, double hi1, int W, int H, int closed, uint32_t *bins,
                             double *vals, hipStream_t s);
 hipError_t launch_vdir_keys(int64_t N, const double *V, double *phi, double *mu, hipStream_t s);
+// accumulate != 0: counts are added to counts_out instead of written.
 hipError_t launch_hist_reduce(int64_t N, const uint32_t *bins, const double *vals, const HistPlan &p,
                               const HistScratch &w, int mode, double norm, uint32_t *counts_out,
-                              double *f_out, uint64_t *dropped_out, hipStream_t s);
+                              double *f_out, uint64_t *dropped_out, hipStream_t s, int accumulate = 0);
 
 // Adjoint.
 hipError_t launch_adj_forward(const AdjDesc &d, int form, const Tuning &t, hipStream_t s);

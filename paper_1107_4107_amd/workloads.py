@@ -60,6 +60,14 @@ def c3(t_scale: float = 1.0) -> List[Ensemble]:
     return [slice_ensemble(e, g, max(1, int(round(t * t_scale)))) for e, g, t in c3_draw()]
 
 
+def eps_sweep(n: int = 256, T: int = 30_000, n_eps: int = 16, pz0: float = 0.0) -> List[Ensemble]:
+    """Chaotic fraction against eps (the model section: the web volume scales
+    as sqrt(eps) and thickens as eps grows): eps log-spaced over 1e-4..1e-1 at
+    one grid size and horizon, on the literal slice (pz0 = 0) or its pz0 = 1
+    companion."""
+    return [slice_ensemble(10.0 ** (-4.0 + 3.0 * k / (n_eps - 1)), n, T, pz0=pz0) for k in range(n_eps)]
+
+
 def c4() -> Ensemble:
     return slice_ensemble(1e-2, 512, 10_000, tangent=False)
 
@@ -124,3 +132,13 @@ def sphere_image(W: int = 1024, H: int = 512, window=None) -> ImageSpec:
     if window is None:
         return ImageSpec(kind="hist_vdir", W=W, H=H)
     return ImageSpec(kind="hist_vdir", W=W, H=H, lo=(window[0], window[2]), hi=(window[1], window[3]))
+
+
+def fig4_cloud(n_orbits: int = 32_000, T: int = 1_000_000_000) -> Ensemble:
+    """Fig. 4: N = 3.2e4 orbits injected at W = (sqrt E, sqrt E, 0), E = 15,
+    Gaussian in (vx, vy) with sigma = 0.01, X on the torus, vz from H = E; the
+    paper propagates them to t_p = 1e7 T (1e9 steps) and averages F over the
+    windows between plots."""
+    w = math.sqrt(FIG3_E)
+    return Ensemble(eps=1.0, n_steps=T, ic_kind="cloud", n_orbits=n_orbits, energy=FIG3_E,
+                    cloud=(w, w, 0.01, 0.01), box_lo=(0.0,) * 6, box_hi=(TWO_PI,) * 6, seed_ic=6, tangent=False)

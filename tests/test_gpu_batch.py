@@ -108,3 +108,20 @@ def test_graph_over_mixed_grids(aw):
             np.testing.assert_array_equal(np_(a), np_(b))
             np.testing.assert_array_equal(np_(c), np_(d))
     g.close()
+
+
+def test_web_thickens_with_eps(aw):
+    """Model section: with growing perturbation the Arnold web becomes
+    thicker.  The chaotic fraction (chi > 2) of the p_z0 = 1 slice, from one
+    batched launch over 8 eps values, must not decrease with eps beyond
+    sampling noise, and must grow overall."""
+    print_case("web thickens")
+    from paper_1107_4107_amd import workloads as wl
+    ens = wl.eps_sweep(n=128, T=10_000, n_eps=8, pz0=1.0)
+    spec = aw.ImageSpec(kind="ic_grid", field=aw.OUT_CHI, W=0, H=0)
+    _, cnts, _ = aw.indicator_images(ens, spec)
+    frac = np.array([int(np_(c).view(np.uint32)[0]) for c in cnts]) / (128 * 128)
+    print("chaotic fractions", frac, flush=True)
+    noise = 3 * np.sqrt(np.maximum(frac, 1.0 / 16384) / 16384)
+    assert np.all(np.diff(frac) >= -noise[1:]), frac
+    assert frac[-1] > frac[0] + 0.01

@@ -148,7 +148,8 @@ def test_explicit_initial_conditions(aw):
     # Edge cases: one orbit, and an empty ensemble.
     one = aw.Ensemble(eps=1e-2, n_steps=5, ic_kind="explicit", n_orbits=1)
     r1 = aw.map_ensemble(one, ic[:, :1].contiguous())
-    o1 = oracle.ensemble("s6", 1e-2, H, 5, np_(ic[:, :1]), oracle.w0(0, 1))
+    ic_o, _ = oracle_ic(e)
+    o1 = oracle.ensemble("s6", 1e-2, H, 5, ic_o[:, :1], oracle.w0(0, 1))
     assert_close(np_(r1.orbit_out)[0], o1[0], 1e-10)
     zero = aw.Ensemble(eps=1e-2, n_steps=5, ic_kind="explicit", n_orbits=0)
     r0 = aw.map_ensemble(zero, torch.empty((6, 0), dtype=torch.float64, device="cuda"))

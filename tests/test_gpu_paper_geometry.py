@@ -50,7 +50,7 @@ def test_states_at_E400(aw):
     from paper_1107_4107_amd import workloads as wl
     e = wl.sphere_ensemble(400.0, 4096, T=50, tangent=True)
     r = aw.map_ensemble(e, want_state=True)
-    ic = np_(aw.generate_ic(e)[0])           # start both sides from the same state
+    ic = _oracle_ic(e)                       # the oracle draws its own (ulp-level equal) states
     out_o, st_o = oracle.ensemble("s6", 1.0, H, 50, ic, oracle.w0(0, 4096), want_state=True)
     assert_close(np_(r.state)[:6], st_o[:6], 1e-12, what="state")
     assert_close(np_(r.orbit_out)[3:6], out_o[3:6], 1e-12, what="V")
@@ -63,7 +63,7 @@ def test_window_decisions(aw):
     from paper_1107_4107_amd import workloads as wl
     e = wl.fig3_zoom(n_orbits=4096, T=1000)
     r = aw.map_ensemble(e)
-    ic = np_(aw.generate_ic(e)[0])
+    ic = _oracle_ic(e)
     _, left, margin = oracle.ensemble_window("s6", 1.0, H, 1000, ic, oracle.w0(0, 4096), e.window)
     g = (np_(r.cls) >> 1) & 1
     dis = g != left
@@ -79,7 +79,7 @@ def test_zoomed_direction_density(aw):
     spec = wl.sphere_image(128, 64, e.window)
     img, cnt, _ = aw.indicator_image(e, spec)
     c = np_(cnt).view(np.uint32)
-    ic = np_(aw.generate_ic(e)[0])
+    ic = _oracle_ic(e)
     out_o, left, margin = oracle.ensemble_window("s6", 1.0, H, 300, ic, oracle.w0(0, 50_000), e.window)
     keep = left == 0
     safe = np.abs(margin) > 1e-9
@@ -123,3 +123,71 @@ def test_fig2_web_structure(aw):
               f"side min / median = {prof[ring].min() / med:.3f}", flush=True)
         assert prof[near].max() > 1.3 * med
         assert prof[ring].min() < 0.9 * med
+
+
+def _cloud(aw, n, T):
+    from paper_1107_4107_amd import workloads as wl
+    return wl.fig4_cloud(n_orbits=n, T=T)
+
+
+def _oracle_cloud(e):
+    return oracle.ic_cloud(e.energy, e.eps, e.cloud, e.box_lo[:3], e.box_hi[:3], e.seed_ic, n_orbits=e.n_orbits)
+
+
+def test_cloud_initial_conditions(aw):
+    """Fig. 4's cloud at W: the rejection draw of X takes the same attempt on
+    both sides (its test is far from 0 for all but a vanishing few orbits),
+    the velocities agree to a few ulps and H = E."""
+    print_case("cloud ic")
+    e = _cloud(aw, 20000, 10)
+    g = np_(aw.generate_ic(e)[0])
+    o = _oracle_cloud(e)
+    same_x = np.all(g[:3] == o[:3], axis=0)
+    assert same_x.mean() >= 0.9999
+    assert_close(g[3:5, same_x], o[3:5, same_x], 2e-15, floor=math.sqrt(2 * e.energy), what="vx, vy")
+    # vz = sqrt(R) with R = 2 (E - Hp) - vx^2 - vy^2 a difference of terms ~ 2E:
+    # R agrees to a few ulps of 2E, vz itself only to that divided by 2 sqrt(R).
+    assert np.all(np.sign(g[5, same_x]) == np.sign(o[5, same_x]))
+    assert_close(g[5, same_x] ** 2, o[5, same_x] ** 2, 1e-13, floor=1.0, what="vz^2")
+    Hs = [oracle.energy(g[:, n], 1.0) for n in range(0, 20000, 97)]
+    np.testing.assert_allclose(Hs, e.energy, rtol=1e-14)
+
+
+def test_window_density_accumulates_over_windows(aw):
+    """F averaged over consecutive windows (Fig. 4): the per-window direction
+    counts of V added over 4 windows of 100 steps, against the oracle's window
+    velocities binned the same way.  Both sides start from their own draws of
+    the cloud (equal to ulps) in a chaotic region, so items within 1e-4 of a
+    bin width from an edge may fall either side; splitting the windows over two
+    calls changes nothing."""
+    import torch
+    print_case("window density")
+    e = _cloud(aw, 4096, 400)
+    w = math.pi / 4
+    spec = aw.ImageSpec(kind="hist_vdir", W=64, H=64, lo=(w - 0.6, -0.6), hi=(w + 0.6, 0.6))
+    N = e.n_orbits
+    carry = torch.empty((aw.NCARRY, N), dtype=torch.float64, device="cuda")
+    cnt = torch.zeros((64, 64), dtype=torch.int32, device="cuda")
+    aw.window_density(e, carry, 0, 4, 100, spec, cnt)
+    c1 = np_(cnt).view(np.uint32).copy()
+    carry1 = np_(carry).copy()
+    carry2 = torch.empty_like(carry)
+    cnt2 = torch.zeros_like(cnt)
+    aw.window_density(e, carry2, 0, 1, 100, spec, cnt2)
+    aw.window_density(e, carry2, 100, 3, 100, spec, cnt2)
+    np.testing.assert_array_equal(np_(cnt2).view(np.uint32), c1)
+    np.testing.assert_array_equal(np_(carry2)[:20], carry1[:20])
+    V = oracle.window_velocities("s6", 1.0, H, _oracle_cloud(e), 4, 100)
+    co = np.zeros((64, 64), dtype=np.int64)
+    amb = 0
+    for k in range(4):
+        phi, mu = oracle.vdir_keys(V[k])
+        ck, _, _ = oracle.hist2d(phi, mu, np.zeros(N), (w - 0.6, -0.6), (w + 0.6, 0.6), 64, 64, closed_upper=True)
+        co += ck
+        fi = (phi - (w - 0.6)) / 1.2 * 64
+        fj = (mu + 0.6) / 1.2 * 64
+        amb += int(np.sum((np.abs(fi - np.round(fi)) < 1e-4) | (np.abs(fj - np.round(fj)) < 1e-4)))
+    diff = np.abs(c1.astype(np.int64) - co)
+    print(f"window counts: {c1.sum()} binned, |diff| sum {diff.sum()}, edge items {amb}", flush=True)
+    assert c1.sum() > 0.5 * 4 * N
+    assert diff.sum() <= 2 * amb + 4

@@ -439,3 +439,30 @@ def test_window_test(orc):
     # with the full perturbation most momenta wander out of a narrow window
     _, left1, m1 = orc.ensemble_window("s6", 1.0, H_PAPER, 2000, ic, w0, seg)
     assert left1.mean() > 0.5 and np.all((m1 < 0) == (left1 == 1))
+
+
+def test_fig4_cloud(orc):
+    """Fig. 4's injected cloud: a Gaussian in (vx, vy) around W = (sqrt E, sqrt E)
+    with the printed dispersions, X uniform on the torus, vz from H = E."""
+    from scipy.stats import kstest
+    g = json.load(open(GOLDEN))
+    E = g["E_moderate"]["value"]
+    W = np.sqrt(E) * np.array(g["W_point_over_sqrtE"]["value"])
+    s = g["fig4_sigma_v"]["value"]
+    ic = orc.ic_cloud(E, 1.0, [W[0], W[1], s, s], [0, 0, 0], [2 * np.pi] * 3, 11, n_orbits=20000)
+    Hs = np.array([orc.energy(ic[:, n], 1.0) for n in range(0, 20000, 37)])
+    np.testing.assert_allclose(Hs, E, rtol=1e-14)
+    for k in (3, 4):
+        assert kstest((ic[k] - W[k - 3]) / s, "norm").pvalue > 1e-4
+    assert abs((ic[5] > 0).mean() - 0.5) < 0.02
+    # a real vz needs Hp(X) <= -sqrt(E) (dvx + dvy) - (dvx^2 + dvy^2)/2, i.e. Hp <~ 0.1 here
+    hp = np.array([orc.energy(np.r_[ic[:3, n], 0, 0, 0], 1.0) for n in range(0, 20000, 37)])
+    assert np.all(hp <= 0.2) and np.mean(hp) < -0.3
+
+
+def test_window_velocities_at_eps0(orc):
+    """At eps = 0 every window's mean velocity is the constant momentum."""
+    ic = orc.ic_box([0] * 6, [2 * np.pi] * 6, 1, 16)
+    V = orc.window_velocities("s6", 0.0, H_PAPER, ic, 4, 25)
+    for w in range(4):
+        np.testing.assert_allclose(V[w], ic[3:], rtol=1e-12, atol=1e-12)
