@@ -19,7 +19,11 @@ Other workloads (measurement records, not the default line):
       100 steps: adjoint time against the forward pass;
   c5  1e7 orbits uniform on [0, 2 pi)^6, eps = 5e-3, T = 1e6, run in chunks
       of 1e5 steps with the state carried in HBM, then the momentum-drift image
-      and the direction density on the sphere (512 x 512 each).
+      and the direction density on the sphere (512 x 512 each);
+  nsweep  map-steps/s against the ensemble size N = 1e3 .. 1e7 at T = 1e4
+      (the c5 distribution): where the device fills;
+  peak    the achievable FP64 rate of independent FMA chains and the shader
+      clock the SIMDs sustain under that load (the probe library).
 
 Prints ONE JSON line.  Single GPU only.
 """
@@ -414,6 +418,68 @@ def run_diffusion(args, aw, wl, torch):
     return rec, None
 
 
+def run_nsweep(args, aw, wl, torch):
+    """Throughput against N at T = 1e4 (orbits uniform on the 6-torus, eps =
+    5e-3, S6 + tangent): one wave per SIMD is 65 536 orbits."""
+    sizes = [1_000, 4_000, 16_000, 32_000, 65_536, 131_072, 262_144, 524_288, 1_048_576, 3_000_000, 10_000_000]
+    T = 10_000
+    fma, mul, add = aw.step_op_counts("s6", True)
+    flop = 2 * fma + mul + add
+    rows = []
+    tot_steps, tot_s = 0, 0.0
+    for n in sizes:
+        e = wl.c5(n_orbits=n, T=T)
+        aw.map_ensemble(dataclasses.replace(e, n_steps=10), want_class=False)
+        torch.cuda.synchronize()
+        aw.timing_read()
+        aw.timing_enable(True)
+        t0 = time.perf_counter()
+        aw.map_ensemble(e, want_class=False)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        aw.timing_enable(False)
+        kms, _ = aw.timing_read()
+        rate = n * T / wall
+        rows.append({"n_orbits": n, "waves_per_simd": n / 64 / 1024, "wall_s": wall, "kernel_ms": kms,
+                     "map_steps_per_s": rate, "kernel_tflops": flop * n * T / (kms * 1e-3) / 1e12,
+                     "frac_of_peak": flop * n * T / (kms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS})
+        tot_steps += n * T
+        tot_s += wall
+        log(f"N={n}: {rate:.4g} map-steps/s, {rows[-1]['frac_of_peak'] * 100:.1f}% of peak")
+    rec = base_record(tot_steps / tot_s, 1, 1, tot_s * 1e3)
+    rec["config"] = {"workload": "N sweep: 1e3..1e7 orbits uniform on [0,2pi)^6 (seed 2), eps=5e-3, T=1e4, "
+                                 "S6 + tangent, one launch per N", "n_steps": T}
+    rec["sweep"] = rows
+    return rec, None
+
+
+def run_peak(args, aw, wl, torch):
+    """Independent-chain FP64 FMA probe: the rate the SIMDs reach on pure
+    v_fma_f64 issue, and the shader clock under that load."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1107_4107_amd", "libaw_probe.so"))
+    lib.awp_fma_peak.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
+    lib.awp_fma_peak.restype = ctypes.c_int
+    torch.cuda.synchronize()
+    rows = []
+    for w in (1, 2, 4, 8):
+        out = (ctypes.c_double * 5)()
+        rc = lib.awp_fma_peak(w, 2_000_000 // w, out)
+        if rc != 0:
+            raise RuntimeError(f"FMA probe failed with code {rc}")
+        rows.append({"waves_per_simd": w, "ms": out[0], "tflops": out[1], "shader_clock_ghz": out[2] / 1e9,
+                     "wall_clock_mhz": out[3] / 1e6, "waves": int(out[4]),
+                     "tflops_at_2p4ghz_equiv": out[1] * 2.4e9 / out[2] if out[2] > 0 else None})
+        log(f"probe {w} waves/SIMD: {out[1]:.2f} TFLOP/s at {out[2] / 1e9:.3f} GHz")
+    best = max(rows, key=lambda r: r["tflops"])
+    rec = base_record(best["tflops"], 1, 1, best["ms"])
+    rec.update({"metric": "FP64 FLOP/s of independent FMA chains (achievable vector peak)", "unit": "TFLOP/s"})
+    rec["config"] = {"workload": "FMA probe: 8 independent v_fma_f64 chains per lane, 1..8 waves per SIMD"}
+    rec["probe"] = rows
+    rec["published_peak_tflops"] = FP64_PEAK_TFLOPS
+    return rec, None
+
+
 def run_sweep(args, aw, wl, torch):
     """Chaotic fraction (chi > 2) against eps on the literal slice and on the
     pz0 = 1 companion (256 x 256, T = 3e4, 16 eps values), each slice as one
@@ -453,12 +519,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "fig2", "fig3", "fig4", "sweep"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "fig2", "fig3", "fig4", "sweep",
+                                                             "nsweep", "peak"])
     ap.add_argument("--windows", type=int, default=200, help="fig4: number of 50 T windows")
     ap.add_argument("--t-scale", type=float, default=1.0, help="c3/c5: scale the horizons")
     ap.add_argument("--n-orbits", type=int, default=10_000_000, help="c5: ensemble size")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-1core", action="store_true",
+                    help="also time the oracle on one host thread (cpu_baseline_1core)")
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--opl", type=int, default=1)
     ap.add_argument("--unroll", type=int, default=1)
@@ -489,7 +558,8 @@ def main():
         log(f"calibration copy of {args.copy_mib} MiB done")
         del src, dst
     runner = {"c1": run_slice, "c2": run_slice, "c3": run_batched, "c4": run_adjoint, "c5": run_large,
-              "fig2": run_sphere, "fig3": run_sphere, "fig4": run_diffusion, "sweep": run_sweep}
+              "fig2": run_sphere, "fig3": run_sphere, "fig4": run_diffusion, "sweep": run_sweep,
+              "nsweep": run_nsweep, "peak": run_peak}
     rec, ens = runner[args.workload](args, aw, wl, torch)
     rec.setdefault("cpu_baseline", None)
     if ens is not None and not args.no_cpu_baseline and args.workload in ("c1", "c2", "c5"):
@@ -497,6 +567,10 @@ def main():
         log(f"cpu baseline on {threads} threads ...")
         rec["cpu_baseline"] = cpu_baseline(ens, args.cpu_seconds, threads)
         rec["speedup_vs_oracle"] = rec["value"] / rec["cpu_baseline"]["value"]
+        if args.cpu_1core:
+            log("cpu baseline on 1 thread ...")
+            rec["cpu_baseline_1core"] = cpu_baseline(ens, args.cpu_seconds, 1)
+            rec["speedup_vs_oracle_1core"] = rec["value"] / rec["cpu_baseline_1core"]["value"]
     print(json.dumps(rec), flush=True)
 
 

@@ -1,4 +1,5 @@
-"""Builds libaw.so (the HIP library, gfx950) in-tree with hipcc."""
+"""Builds libaw.so (the HIP library, gfx950) and libaw_probe.so (the FP64
+peak and clock probe the benchmark uses) in-tree with hipcc."""
 from __future__ import annotations
 
 import os
@@ -12,6 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libaw.so")
 SOURCES = ["aw_api.hip", "aw_fwd.hip", "aw_hist.hip", "aw_adj.hip"]
+PROBE_LIB = os.path.join(HERE, "libaw_probe.so")
+PROBE_SOURCES = ["aw_probe.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -34,23 +37,29 @@ def hipcc() -> str:
     return path
 
 
-def command(out: str = LIB, extra=()) -> list:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+def command(out: str = LIB, extra=(), sources=SOURCES) -> list:
+    srcs = [os.path.join(CSRC, s) for s in sources]
     return [hipcc(), *HIPCC_FLAGS, *extra, "-I", INCLUDE, "-I", CSRC, *srcs, "-o", out]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source into libaw.so (always recompiles)."""
-    tmp = LIB + ".tmp"
-    cmd = command(tmp)
+def _compile(lib: str, sources, verbose: bool) -> str:
+    tmp = lib + ".tmp"
+    cmd = command(tmp, sources=sources)
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libaw.so")
-    os.replace(tmp, LIB)
-    return LIB
+        raise RuntimeError(f"hipcc failed building {os.path.basename(lib)}")
+    os.replace(tmp, lib)
+    return lib
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every HIP source into libaw.so and the probe into
+    libaw_probe.so (always recompiles)."""
+    _compile(PROBE_LIB, PROBE_SOURCES, verbose)
+    return _compile(LIB, SOURCES, verbose)
 
 
 if __name__ == "__main__":

@@ -29,6 +29,16 @@ def test_library_exports_every_declared_function():
     assert set(names) == set(_abi.EXPORTS)
 
 
+def test_probe_library_loads():
+    """The FP64 peak/clock probe the benchmark uses is built beside libaw.so."""
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1107_4107_amd", "libaw_probe.so"))
+    assert hasattr(lib, "awp_fma_peak")
+    lib.awp_fma_peak.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
+    out = (ctypes.c_double * 5)()
+    assert lib.awp_fma_peak(0, 1000, out) == 2      # argument check, no device touched
+    assert lib.awp_fma_peak(1, 1000, None) == 2
+
+
 def test_struct_layouts_match_the_header(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text("""
