@@ -2,7 +2,8 @@
 
 Thin ctypes wrapper around ``aw_oracle.c``: a plain FP64 implementation of the
 ensemble propagation of eqs. 1-2 of arXiv:1107.4107 (symplectic map, tangent
-vector, per-orbit observables, histograms, forward-mode derivatives).  Only the
+vector, per-orbit observables, histograms, forward-mode derivatives of J and
+forward-over-forward derivatives of the tangent growth L).  Only the
 tests, the package smoke check and the benchmark's CPU-baseline leg may import
 this module.  It shares no code with the HIP library.
 
@@ -62,6 +63,9 @@ def _load():
         "oracle_jacobian": (i, [i, d, d, l, _dp, _dp, _dp]),
         "oracle_J_grad": (i, [i, d, d, l, _dp, _dp, _dp]),
         "oracle_J_grad_ensemble": (i, [i, d, d, l, l, _dp, _dp, _dp, i]),
+        "oracle_ftle_grad": (i, [i, d, d, l, _dp, _dp, _dp, _dp, _dp]),
+        "oracle_ftle_grad_ensemble": (i, [i, d, d, l, l, _dp, _dp, _dp, _dp, i]),
+        "oracle_hp_third": (None, [_dp, _dp]),
         "oracle_splitmix64": (u64, [u64, u64]),
         "oracle_u01": (d, [u64, u64]),
         "oracle_ic_grid2": (i, [i, i, d, d, d, d, l, l, _dp, _lp, l, _dp]),
@@ -248,6 +252,33 @@ def J_grad_ensemble(form, eps, h, T, ic, nthreads=0):
     return J, dJ
 
 
+def ftle_grad(form, eps, h, T, s0, w0_):
+    """Returns (L, dL[7], final state and unit tangent [12]) with
+    dL = d/d(x, y, z, px, py, pz, eps) of L = ln(|w_T| / |w_0|) at fixed w0."""
+    s0 = _f64(s0, (6,))
+    w = _f64(w0_, (6,))
+    L = ctypes.c_double()
+    dL = np.empty(7)
+    sT = np.empty(12)
+    if _load().oracle_ftle_grad(_form(form), eps, h, int(T), _ptr(s0), _ptr(w), ctypes.byref(L), _ptr(dL), _ptr(sT)):
+        raise ValueError("bad map form")
+    return L.value, dL, sT
+
+
+def ftle_grad_ensemble(form, eps, h, T, ic, w0_, nthreads=0):
+    """Forward-over-forward L[N] and dL[7, N] for every orbit of ic[6, N] with
+    tangent starts w0[6, N]."""
+    ic = _f64(ic)
+    w = _f64(w0_)
+    N = ic.shape[1]
+    L = np.empty(N)
+    dL = np.empty((7, N))
+    if _load().oracle_ftle_grad_ensemble(_form(form), eps, h, int(T), N, _ptr(ic), _ptr(w), _ptr(L), _ptr(dL),
+                                         int(nthreads)):
+        raise ValueError("bad map form")
+    return L, dL
+
+
 def rec_init(s0, w0_):
     rec = np.empty(REC_LEN)
     _load().oracle_rec_init(_ptr(_f64(s0, (6,))), _ptr(_f64(w0_, (6,))), _ptr(rec))
@@ -316,6 +347,14 @@ def hp_derivs(X):
     H6 = np.empty(6)
     _load().oracle_hp_derivs(_ptr(X), ctypes.byref(hp), _ptr(g), _ptr(H6))
     return hp.value, g, H6
+
+
+def hp_third(X):
+    """Third derivatives of Hp at X as a [3, 3, 3] array."""
+    X = _f64(X, (3,))
+    t = np.empty(27)
+    _load().oracle_hp_third(_ptr(X), _ptr(t))
+    return t.reshape(3, 3, 3)
 
 
 def tj_constants():

@@ -28,6 +28,10 @@
  *   - Forward-mode derivatives of the step-averaged momentum drift
  *     J = (1/T) sum_k |P_k - P_0|^2 with respect to the six initial
  *     coordinates and eps (seven tangent columns).
+ *   - Forward-over-forward derivatives of the tangent-growth indicator
+ *     L = ln(|w_T| / |w_0|) with respect to the same seven parameters: the
+ *     tangent equations differentiated once more, which brings in the third
+ *     derivatives of Hp.
  *   - Histograms of per-orbit values over two key coordinates, and the
  *     equal-area histogram of the direction of V on the momentum sphere (the
  *     density F of the "Main results" section and Figs. 2-4).
@@ -102,6 +106,40 @@ static void hp_hessian(const double X[3], double Hs[3][3])
     Hs[1][0] = Hs[0][1];
     Hs[2][0] = Hs[0][2];
     Hs[2][1] = Hs[1][2];
+}
+
+/* T3[i][j][k] = d^3 Hp / dx_i dx_j dx_k at X (full symmetric array), from
+ * Hp = cx cy (1 + c2z):
+ *   xxx = xyy = sx cy (1 + c2z)     xxy = yyy = cx sy (1 + c2z)
+ *   xxz = yyz = 2 cx cy s2z         xyz = -2 sx sy s2z
+ *   xzz = 4 sx cy c2z               yzz = 4 cx sy c2z
+ *   zzz = 8 cx cy s2z */
+static void hp_third(const double X[3], double T3[3][3][3])
+{
+    double cx = cos(X[0]), sx = sin(X[0]);
+    double cy = cos(X[1]), sy = sin(X[1]);
+    double c2z = cos(2.0 * X[2]), s2z = sin(2.0 * X[2]);
+    double v[3][3][3];
+    v[0][0][0] = sx * cy * (1.0 + c2z);
+    v[0][0][1] = cx * sy * (1.0 + c2z);
+    v[0][0][2] = 2.0 * cx * cy * s2z;
+    v[0][1][1] = sx * cy * (1.0 + c2z);
+    v[0][1][2] = -2.0 * sx * sy * s2z;
+    v[0][2][2] = 4.0 * sx * cy * c2z;
+    v[1][1][1] = cx * sy * (1.0 + c2z);
+    v[1][1][2] = 2.0 * cx * cy * s2z;
+    v[1][2][2] = 4.0 * cx * sy * c2z;
+    v[2][2][2] = 8.0 * cx * cy * s2z;
+    /* fill every permutation from the sorted-index entries */
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++)
+            for (int k = 0; k < 3; k++) {
+                int a = i, b = j, c = k, t;
+                if (a > b) { t = a; a = b; b = t; }
+                if (b > c) { t = b; b = c; c = t; }
+                if (a > b) { t = a; a = b; b = t; }
+                T3[i][j][k] = v[a][b][c];
+            }
 }
 
 /* Eq. 1: total energy of s = (x, y, z, px, py, pz). */
@@ -381,6 +419,178 @@ int oracle_J_grad_ensemble(int form, double eps, double h, long T, long N, const
 }
 
 /* ------------------------------------------------------------------------ */
+/* Derivatives of the tangent-growth indicator, forward over forward.       */
+/*                                                                          */
+/* The orbit carries its state s = (X, P), its tangent w = (dX, dP) and,    */
+/* for each of the seven parameters c (x0, y0, z0, px0, py0, pz0, eps), the */
+/* first derivative of the state, a_c = ds/dc, and of the tangent,          */
+/* b_c = dw/dc.  Differentiating the stages:                                */
+/*   drift D(t): X += t P,  dX += t dP,  a_X += t a_P,  b_X += t b_P;       */
+/*   kick  K(t): P  -= t eps g(X),                                          */
+/*               dP -= t eps Hs(X) dX,                                      */
+/*               a_P -= t eps Hs(X) a_X + [c = eps] t g(X),                 */
+/*               b_P -= t eps (Hs(X) b_X + T3(X)[a_X, dX])                  */
+/*                      + [c = eps] t Hs(X) dX,                             */
+/* with g, Hs, T3 the first, second and third derivatives of Hp, all taken  */
+/* at the pre-kick X (a kick changes neither X nor dX).                     */
+/* The tangent is divided by nu = |w| after every step, L += ln nu, and     */
+/* every b_c is divided by the same nu: the map is linear in w, so with     */
+/* the scales held fixed w = W / S and b_c = dW/dc / S for the unscaled     */
+/* tangent W and one common S, and                                          */
+/*   dL/dc = d ln|W_T| / dc = (W_T . dW_T/dc) / |W_T|^2                     */
+/*         = (w_T . b_c) / |w_T|^2.                                         */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double s[6], w[6];
+    double a[7][6], b[7][6];
+    double eps;
+} orbit2;
+
+static void drift2(orbit2 *o, double t)
+{
+    for (int i = 0; i < 3; i++) {
+        o->s[i] = o->s[i] + t * o->s[3 + i];
+        o->w[i] = o->w[i] + t * o->w[3 + i];
+    }
+    for (int c = 0; c < 7; c++)
+        for (int i = 0; i < 3; i++) {
+            o->a[c][i] = o->a[c][i] + t * o->a[c][3 + i];
+            o->b[c][i] = o->b[c][i] + t * o->b[c][3 + i];
+        }
+}
+
+static void kick2(orbit2 *o, double t)
+{
+    double g[3], Hs[3][3], T3[3][3][3];
+    hp_gradient(o->s, g);
+    hp_hessian(o->s, Hs);
+    hp_third(o->s, T3);
+    const double *dX = o->w;
+    double Hw[3];
+    for (int i = 0; i < 3; i++) Hw[i] = Hs[i][0] * dX[0] + Hs[i][1] * dX[1] + Hs[i][2] * dX[2];
+    for (int c = 0; c < 7; c++) {
+        double de = (c == 6) ? 1.0 : 0.0;
+        const double *aX = o->a[c];
+        const double *bX = o->b[c];
+        double Ha[3], Hb[3], Tab[3];
+        for (int i = 0; i < 3; i++) {
+            Ha[i] = Hs[i][0] * aX[0] + Hs[i][1] * aX[1] + Hs[i][2] * aX[2];
+            Hb[i] = Hs[i][0] * bX[0] + Hs[i][1] * bX[1] + Hs[i][2] * bX[2];
+            Tab[i] = 0.0;
+            for (int j = 0; j < 3; j++)
+                for (int k = 0; k < 3; k++) Tab[i] = Tab[i] + T3[i][j][k] * aX[j] * dX[k];
+        }
+        for (int i = 0; i < 3; i++) {
+            o->a[c][3 + i] = o->a[c][3 + i] - (t * o->eps * Ha[i] + de * t * g[i]);
+            o->b[c][3 + i] = o->b[c][3 + i] - (t * o->eps * (Hb[i] + Tab[i]) + de * t * Hw[i]);
+        }
+    }
+    for (int i = 0; i < 3; i++) {
+        o->w[3 + i] = o->w[3 + i] - t * o->eps * Hw[i];
+        o->s[3 + i] = o->s[3 + i] - t * o->eps * g[i];
+    }
+}
+
+static void map2_s2(orbit2 *o, double t)
+{
+    drift2(o, t / 2.0);
+    kick2(o, t);
+    drift2(o, t / 2.0);
+}
+
+static void map2_s4(orbit2 *o, double t)
+{
+    double g1 = tj_g1(), g0 = 1.0 - 2.0 * g1;
+    map2_s2(o, g1 * t);
+    map2_s2(o, g0 * t);
+    map2_s2(o, g1 * t);
+}
+
+static void map2_s6(orbit2 *o, double t)
+{
+    double d1 = tj_d1(), d0 = 1.0 - 2.0 * d1;
+    map2_s4(o, d1 * t);
+    map2_s4(o, d0 * t);
+    map2_s4(o, d1 * t);
+}
+
+/* L = ln(|w_T| / |w_0|) after T steps from (s0, w0), and dL[7], its exact
+ * derivatives with respect to the initial (x, y, z, px, py, pz) and eps at
+ * fixed w0.  Also returns the final state and unit tangent in sT[12] if
+ * non-NULL. */
+int oracle_ftle_grad(int form, double eps, double h, long T, const double s0[6], const double w0[6],
+                     double *L, double dL[7], double *sT)
+{
+    if (form != OR_STDMAP && form != OR_S2 && form != OR_S4 && form != OR_S6) return -1;
+    orbit2 o;
+    o.eps = eps;
+    double n0 = 0.0;
+    for (int i = 0; i < 6; i++) {
+        o.s[i] = s0[i];
+        o.w[i] = w0[i];
+        n0 = n0 + w0[i] * w0[i];
+    }
+    for (int c = 0; c < 7; c++)
+        for (int i = 0; i < 6; i++) {
+            o.a[c][i] = (i == c) ? 1.0 : 0.0;
+            o.b[c][i] = 0.0;
+        }
+    double Lsum = -0.5 * log(n0);
+    for (long k = 0; k < T; k++) {
+        switch (form) {
+        case OR_STDMAP: kick2(&o, h); drift2(&o, h); break;
+        case OR_S2: map2_s2(&o, h); break;
+        case OR_S4: map2_s4(&o, h); break;
+        default: map2_s6(&o, h); break;
+        }
+        double n2 = 0.0;
+        for (int i = 0; i < 6; i++) n2 = n2 + o.w[i] * o.w[i];
+        double nu = sqrt(n2);
+        Lsum = Lsum + log(nu);
+        for (int i = 0; i < 6; i++) o.w[i] = o.w[i] / nu;
+        for (int c = 0; c < 7; c++)
+            for (int i = 0; i < 6; i++) o.b[c][i] = o.b[c][i] / nu;
+    }
+    double ww = 0.0;
+    for (int i = 0; i < 6; i++) ww = ww + o.w[i] * o.w[i];
+    for (int c = 0; c < 7; c++) {
+        double wb = 0.0;
+        for (int i = 0; i < 6; i++) wb = wb + o.w[i] * o.b[c][i];
+        dL[c] = wb / ww;
+    }
+    *L = Lsum;
+    if (sT)
+        for (int i = 0; i < 6; i++) {
+            sT[i] = o.s[i];
+            sT[6 + i] = o.w[i];
+        }
+    return 0;
+}
+
+/* oracle_ftle_grad over orbits ic[6][N] with tangent starts w0[6][N]:
+ * L[N], dL[7][N].  OpenMP over orbits. */
+int oracle_ftle_grad_ensemble(int form, double eps, double h, long T, long N, const double *ic,
+                              const double *w0, double *L, double *dL, int nthreads)
+{
+    int bad = 0;
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads) reduction(|:bad)
+#endif
+    for (long n = 0; n < N; n++) {
+        double s0[6], u[6], d[7];
+        for (int a = 0; a < 6; a++) {
+            s0[a] = ic[a * N + n];
+            u[a] = w0[a * N + n];
+        }
+        bad |= oracle_ftle_grad(form, eps, h, T, s0, u, &L[n], d, NULL);
+        for (int c = 0; c < 7; c++) dL[c * N + n] = d[c];
+    }
+    return bad ? -1 : 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Counter-based SplitMix64 (Steele, Lea & Flood 2014).                     */
 /* The sequential generator advances state += 0x9E3779B97F4A7C15 and        */
 /* returns mix(state); output number c (from 0) is therefore                */
@@ -635,6 +845,16 @@ void oracle_vdir_keys(long N, const double *V, double *phi, double *mu)
 /* ------------------------------------------------------------------------ */
 
 double oracle_energy(const double s[6], double eps) { return energy(s, eps); }
+
+/* Third derivatives of Hp at X as the full array T27[i*9 + j*3 + k]. */
+void oracle_hp_third(const double X[3], double T27[27])
+{
+    double T3[3][3][3];
+    hp_third(X, T3);
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++)
+            for (int k = 0; k < 3; k++) T27[i * 9 + j * 3 + k] = T3[i][j][k];
+}
 
 /* hp, gradient g[3], Hessian entries H6 = (xx, yy, zz, xy, xz, yz). */
 void oracle_hp_derivs(const double X[3], double *hp, double g[3], double H6[6])

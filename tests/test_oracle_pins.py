@@ -93,6 +93,29 @@ def test_hp_derivatives_against_mpmath(orc):
             assert abs(H6[a] - float(mpmath.diff(f, (x, y, z), order))) < 1e-13
 
 
+def test_hp_third_derivatives_against_mpmath(orc):
+    """All 27 third derivatives of eq. 2's Hp (they enter the derivative of the
+    tangent kick) against mpmath's numerical differentiation."""
+    rng = np.random.default_rng(12)
+    mpmath.mp.dps = 30
+
+    def f(x, y, z):
+        return mpmath.cos(x) * mpmath.cos(y) * (1 + mpmath.cos(2 * z))
+
+    for _ in range(6):
+        X = rng.uniform(-7, 7, 3)
+        T3 = orc.hp_third(X)
+        x, y, z = (mpmath.mpf(float(v)) for v in X)
+        for i in range(3):
+            for j in range(3):
+                for k in range(3):
+                    order = [0, 0, 0]
+                    for a in (i, j, k):
+                        order[a] += 1
+                    ref = float(mpmath.diff(f, (x, y, z), tuple(order)))
+                    assert abs(T3[i, j, k] - ref) < 1e-13, ((i, j, k), T3[i, j, k], ref)
+
+
 def test_hp_fourier_form_and_bound(orc):
     """Product-to-sum form of eq. 2: its Fourier modes are the primary
     resonances (1, +-1, 0) and (1, +-1, +-2); and |Hp| <= 2 (model section)."""
@@ -293,6 +316,72 @@ def test_J_gradient_symmetry_on_invariant_plane(orc):
     exactly on the plane z = p_z = 0."""
     _, dJ = orc.J_grad("s6", 1e-2, H_PAPER, 200, np.array([0.0, 0.0, 0.0, 1.3, 2.1, 0.0]))
     assert dJ[2] == 0.0 and dJ[5] == 0.0
+
+
+@pytest.mark.parametrize("form,eps,T", [("s6", 5e-2, 60), ("s6", 1.0, 40), ("stdmap", 0.3, 80), ("s2", 0.1, 50)])
+def test_ftle_gradient_against_finite_differences(orc, form, eps, T):
+    """Forward-over-forward dL/d(x0..pz0, eps) against central differences of
+    the plain one-tangent oracle's L (a separate code path: no third
+    derivatives), at a fixed tangent start."""
+    rng = np.random.default_rng(21)
+    d = 1e-6
+    for _ in range(3):
+        s0 = np.concatenate([rng.uniform(-3, 3, 3), rng.uniform(-1.5, 1.5, 3)])
+        w = rng.normal(size=6)
+        w /= np.linalg.norm(w)
+        L, dL, _ = orc.ftle_grad(form, eps, H_PAPER, T, s0, w)
+
+        def plain(s, e):
+            return orc.ensemble(form, e, H_PAPER, T, s.reshape(6, 1), w.reshape(6, 1))[0, 0]
+
+        assert abs(L - plain(s0, eps)) <= 1e-13 * max(1.0, abs(L))
+        for c in range(7):
+            if c < 6:
+                e = np.zeros(6)
+                e[c] = d
+                fd = (plain(s0 + e, eps) - plain(s0 - e, eps)) / (2 * d)
+            else:
+                fd = (plain(s0, eps + d) - plain(s0, eps - d)) / (2 * d)
+            assert abs(dL[c] - fd) <= 2e-7 * max(1.0, abs(fd)), (c, dL[c], fd)
+
+
+def test_ftle_gradient_in_the_integrable_limit(orc):
+    """eps = 0: L = 1/2 ln(|dX0 + T h dP0|^2 + |dP0|^2) does not depend on the
+    initial state, so dL/d(x0..pz0) is exactly 0; dL/deps then follows from
+    first-order perturbation of the free flight, checked by differences."""
+    s0 = np.array([0.3, 1.2, -0.4, 0.8, -0.6, 1.1])
+    w = np.array([0.3, -0.2, 0.5, 0.4, 0.1, -0.6])
+    w /= np.linalg.norm(w)
+    T = 120
+    L, dL, _ = orc.ftle_grad("s6", 0.0, H_PAPER, T, s0, w)
+    th = T * H_PAPER
+    assert abs(L - 0.5 * np.log(np.sum((w[:3] + th * w[3:]) ** 2) + np.sum(w[3:] ** 2))) < 1e-13
+    assert np.all(dL[:6] == 0.0)
+    d = 1e-7
+    Lp = orc.ftle_grad("s6", d, H_PAPER, T, s0, w)[0]
+    Lm = orc.ftle_grad("s6", -d, H_PAPER, T, s0, w)[0]
+    assert abs(dL[6] - (Lp - Lm) / (2 * d)) <= 1e-6 * max(1.0, abs(dL[6]))
+
+
+def test_ftle_gradient_ignores_the_tangent_scale(orc):
+    """L is a ratio |w_T| / |w_0|, so scaling w0 changes neither L nor dL."""
+    s0 = np.array([0.5, -0.7, 0.2, 1.1, 0.3, -0.4])
+    w = np.array([0.2, 0.4, -0.1, -0.3, 0.6, 0.5])
+    w /= np.linalg.norm(w)
+    L1, d1, _ = orc.ftle_grad("s6", 0.2, H_PAPER, 80, s0, w)
+    L2, d2, _ = orc.ftle_grad("s6", 0.2, H_PAPER, 80, s0, 8.0 * w)
+    assert abs(L1 - L2) < 1e-13
+    np.testing.assert_allclose(d2, d1, rtol=1e-12, atol=1e-13)
+
+
+def test_ftle_gradient_ensemble_matches_single_orbits(orc):
+    ic = orc.ic_box([0.0] * 6, [2 * np.pi] * 6, 5, 16)
+    w = orc.w0(0, 16)
+    L, dL = orc.ftle_grad_ensemble("s6", 0.05, H_PAPER, 30, ic, w, nthreads=4)
+    for n in (0, 7, 15):
+        L1, d1, _ = orc.ftle_grad("s6", 0.05, H_PAPER, 30, ic[:, n], w[:, n])
+        assert L[n] == L1
+        np.testing.assert_array_equal(dL[:, n], d1)
 
 
 # ---------------------------------------------------------------- resume
