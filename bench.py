@@ -16,7 +16,8 @@ Other workloads (measurement records, not the default line):
   c3  64 ensembles (eps sweep, mixed grids and horizons): one persistent
       launch captured in a HIP graph against the sum of 64 separate launches;
   c4  gradient of J on the 512 x 512, T = 1e4 slice with checkpoints every
-      100 steps: adjoint time against the forward pass;
+      100 steps: adjoint time against the forward pass; also the gradient of
+      the tangent growth L (second-order adjoint) on the same slice;
   c5  1e7 orbits uniform on [0, 2 pi)^6, eps = 5e-3, T = 1e6, run in chunks
       of 1e5 steps with the state carried in HBM, then the momentum-drift image
       and the direction density on the sphere (512 x 512 each);
@@ -244,6 +245,13 @@ def run_adjoint(args, aw, wl, torch):
     t_fwd_tan = timed(lambda: aw.map_ensemble(fwd_t, ic, want_class=False))
     t_grad = timed(lambda: aw.indicator_grad(fwd, ic, ckpt_every=wl.C4_CKPT, workspace=ws))
     log(f"forward {t_fwd:.3f} s, forward+tangent {t_fwd_tan:.3f} s, gradient {t_grad:.3f} s")
+    del ws
+    # Gradient of the tangent growth L (second-order adjoint) on the same slice.
+    _, w0 = aw.generate_ic(fwd_t, ic)
+    ws2 = torch.empty((aw.ftle_grad_workspace_bytes(fwd_t, wl.C4_CKPT),), dtype=torch.uint8, device="cuda")
+    t_fgrad = timed(lambda: aw.ftle_grad(fwd_t, ic, w0, ckpt_every=wl.C4_CKPT, workspace=ws2))
+    log(f"FTLE gradient {t_fgrad:.3f} s")
+    del ws2
     rec = base_record(N * T / t_grad, 3, 1, t_grad * 1e3)
     rec["metric"] = "orbit map-steps/sec through the adjoint (forward + checkpoints + reverse)"
     rec["config"] = {"workload": "c4: eps=1e-2 512x512 (px,py) slice, T=1e4, checkpoint every 100 steps, "
@@ -253,6 +261,8 @@ def run_adjoint(args, aw, wl, torch):
     rec["gradient_s"] = t_grad
     rec["gradient_over_forward"] = t_grad / t_fwd
     rec["gradient_over_forward_tangent"] = t_grad / t_fwd_tan
+    rec["ftle_gradient_s"] = t_fgrad
+    rec["ftle_gradient_over_forward_tangent"] = t_fgrad / t_fwd_tan
     return rec, None
 
 

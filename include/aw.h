@@ -274,6 +274,31 @@ aw_status aw_indicator_grad(const aw_ensemble *ens, const double *ic_dev, const 
                             double *grad_eps_dev, void *workspace_dev, size_t ws_bytes,
                             const aw_tuning *tuning, void *stream);
 
+/* Gradient of the tangent-growth indicator L = ln(|w_T| / |w_0|) -- the
+ * finite-time Lyapunov exponent that the conclusions name as the indicator to
+ * compare with, before its division by T h -- with respect to the initial
+ * state and eps, at a fixed tangent start.  A second-order adjoint: a forward
+ * pass with the tangent stores (state, tangent) every ckpt_every steps; then,
+ * segment by segment from the end, the segment is recomputed and swept
+ * backwards, each stage inverted, with the adjoint of state and tangent
+ * propagated through the kick's second and third derivatives of eq. 2's Hp.
+ * ens->ic_kind must be EXPLICIT.
+ *   ic_dev [6][N], w0_dev [6][N] (the tangent start; need not be unit);
+ *   grad_L_dev [N]: upstream dF/dL_n (NULL = all ones);
+ *   L_out_dev [N] or NULL: L per orbit;
+ *   grad_ic_dev [6][N]: dF/d(initial x..pz);
+ *   grad_eps_dev [N]: per-orbit dF/deps contributions (sum for the scalar).
+ * lambda = L/(T h) and chi = L/ln(1 + T h) scale the same gradients.  On
+ * chaotic orbits the derivative grows like exp(lambda T h) and is only
+ * meaningful where the trajectory is. Requires a caller workspace of
+ * aw_ftle_grad_workspace() bytes (12 doubles per orbit per checkpoint and per
+ * step of a segment). */
+aw_status aw_ftle_grad_workspace(const aw_ensemble *ens, int64_t ckpt_every, size_t *bytes);
+aw_status aw_ftle_grad(const aw_ensemble *ens, const double *ic_dev, const double *w0_dev,
+                       const double *grad_L_dev, int64_t ckpt_every, double *L_out_dev,
+                       double *grad_ic_dev, double *grad_eps_dev, void *workspace_dev, size_t ws_bytes,
+                       const aw_tuning *tuning, void *stream);
+
 /* A captured HIP graph of aw_indicator_image over n_ens ensembles (one
  * persistent launch plus the reductions).  Buffers are bound at creation;
  * the descriptors are copied.  Launching replays the whole batch. */

@@ -29,7 +29,7 @@ OUT_ROWS = ("L", "lambda", "chi", "Vx", "Vy", "Vz", "dP2", "J", "dE")
 __all__ = [
     "Ensemble", "Tuning", "ImageSpec", "map_ensemble", "map_ensembles", "map_ensemble_steps",
     "indicator_image", "indicator_images", "histogram2d", "vdir_keys", "generate_ic",
-    "indicator_grad", "IndicatorJ", "Graph", "timing_enable", "timing_read", "step_op_counts",
+    "indicator_grad", "IndicatorJ", "ftle_grad_workspace_bytes", "ftle_grad", "IndicatorL", "Graph", "timing_enable", "timing_read", "step_op_counts",
     "AwError", "H_PAPER", "OUT_ROWS",
 ]
 
@@ -363,6 +363,70 @@ class IndicatorJ(torch.autograd.Function):
         if ctx.eps_shape is not None:
             g_eps = g_eps.reshape(ctx.eps_shape)
         return gic.t().contiguous(), g_eps, None, None, None, None
+
+
+def ftle_grad_workspace_bytes(ens: Ensemble, ckpt_every: int) -> int:
+    nb = ctypes.c_size_t()
+    _abi.check(_lib().aw_ftle_grad_workspace(ctypes.byref(ens.to_c()), int(ckpt_every), ctypes.byref(nb)))
+    return int(nb.value)
+
+
+def ftle_grad(ens: Ensemble, ic: torch.Tensor, w0: Optional[torch.Tensor] = None,
+              grad_L: Optional[torch.Tensor] = None, ckpt_every: int = 100, tuning: Optional[Tuning] = None,
+              workspace: Optional[torch.Tensor] = None):
+    """Second-order adjoint gradient of the tangent growth L = ln(|w_T|/|w_0|).
+    w0 defaults to the ensemble's seeded tangent start (the one map_ensemble
+    uses).  Returns (L[N], grad_ic[6, N], grad_eps[N])."""
+    if ens.ic_kind != "explicit":
+        raise ValueError("ftle_grad needs an explicit ensemble")
+    N = ens.size
+    _dev_f64(ic, (6, N), "ic")
+    if w0 is None:
+        _, w0 = generate_ic(ens, ic)
+    _dev_f64(w0, (6, N), "w0")
+    if grad_L is not None:
+        _dev_f64(grad_L, (N,), "grad_L")
+    nb = ftle_grad_workspace_bytes(ens, ckpt_every)
+    if workspace is None or workspace.numel() * workspace.element_size() < nb:
+        workspace = torch.empty((max(nb, 8),), dtype=torch.uint8, device=ic.device)
+    L = torch.empty((N,), dtype=torch.float64, device=ic.device)
+    gic = torch.empty((6, N), dtype=torch.float64, device=ic.device)
+    geps = torch.empty((N,), dtype=torch.float64, device=ic.device)
+    _abi.check(_lib().aw_ftle_grad(ctypes.byref(ens.to_c()), _p(ic), _p(w0), _p(grad_L), int(ckpt_every), _p(L),
+                                   _p(gic), _p(geps), _p(workspace), workspace.numel() * workspace.element_size(),
+                                   _tuning_ptr(tuning), _stream()))
+    return L, gic, geps
+
+
+class IndicatorL(torch.autograd.Function):
+    """L_n = ln(|w_T| / |w_0|) per orbit (the tangent growth behind the FTLE
+    lambda = L/(T h) and chi = L/ln(1 + T h)), from the seeded tangent start,
+    differentiable in the initial state ic[N, 6] and in eps (a 0-d float64
+    tensor); the backward pass runs the second-order adjoint kernels."""
+
+    @staticmethod
+    def forward(ctx, ic, eps, n_steps: int, h: float = H_PAPER, map_form: str = "s6", ckpt_every: int = 100,
+                seed_tangent: int = 0):
+        if ic.dim() != 2 or ic.shape[1] != 6:
+            raise ValueError("ic must be [N, 6]")
+        soa = ic.detach().t().contiguous()
+        e = Ensemble(eps=float(eps), n_steps=n_steps, h=h, map_form=map_form, ic_kind="explicit",
+                     n_orbits=ic.shape[0], seed_tangent=seed_tangent, tangent=True)
+        res = map_ensemble(e, soa, want_class=False)
+        ctx.save_for_backward(soa)
+        ctx.ens = e
+        ctx.ckpt = ckpt_every
+        ctx.eps_shape = eps.shape if isinstance(eps, torch.Tensor) else None
+        return res.orbit_out[OUT_L].clone()
+
+    @staticmethod
+    def backward(ctx, gL):
+        (soa,) = ctx.saved_tensors
+        _, gic, geps = ftle_grad(ctx.ens, soa, grad_L=gL.contiguous().to(torch.float64), ckpt_every=ctx.ckpt)
+        g_eps = geps.sum()
+        if ctx.eps_shape is not None:
+            g_eps = g_eps.reshape(ctx.eps_shape)
+        return gic.t().contiguous(), g_eps, None, None, None, None, None
 
 
 class Graph:

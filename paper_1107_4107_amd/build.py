@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libaw.so")
-SOURCES = ["aw_api.hip", "aw_fwd.hip", "aw_hist.hip", "aw_adj.hip"]
+SOURCES = ["aw_api.hip", "aw_fwd.hip", "aw_hist.hip", "aw_adj.hip", "aw_ftle_adj.hip"]
 PROBE_LIB = os.path.join(HERE, "libaw_probe.so")
 PROBE_SOURCES = ["aw_probe.hip"]
 ARCH = "gfx950"

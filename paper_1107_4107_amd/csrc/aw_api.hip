@@ -813,6 +813,65 @@ aw_status aw_indicator_grad(const aw_ensemble *ens, const double *ic_dev, const 
   return AW_OK;
 }
 
+aw_status aw_ftle_grad_workspace(const aw_ensemble *ens, int64_t ckpt_every, size_t *bytes) {
+  if (!bytes) return fail(AW_EINVAL, "null bytes");
+  if (!ens) return fail(AW_EINVAL, "null ensemble");
+  if (ckpt_every < 1) return fail(AW_EINVAL, "ckpt_every must be >= 1");
+  if (ens->n_steps < 1) return fail(AW_EINVAL, "n_steps must be >= 1");
+  const int64_t N = ens_size(*ens);
+  if (N < 0) return fail(AW_EINVAL, "bad ensemble size");
+  const int64_t ck = std::min(ckpt_every, ens->n_steps);
+  const int64_t n_seg = (ens->n_steps + ck - 1) / ck;
+  *bytes = sizeof(double) * 12 * (size_t)N * (size_t)(n_seg + ck);
+  return AW_OK;
+}
+
+aw_status aw_ftle_grad(const aw_ensemble *ens, const double *ic_dev, const double *w0_dev, const double *grad_L_dev,
+                       int64_t ckpt_every, double *L_out_dev, double *grad_ic_dev, double *grad_eps_dev,
+                       void *workspace_dev, size_t ws_bytes, const aw_tuning *tuning, void *stream) {
+  aw_status st = check_ensemble(ens, ic_dev, 0);
+  if (st != AW_OK) return st;
+  if (ens->ic_kind != AW_IC_EXPLICIT) return fail(AW_EINVAL, "aw_ftle_grad needs an EXPLICIT ensemble");
+  Tuning t;
+  if ((st = check_tuning(tuning, t)) != AW_OK) return st;
+  size_t need = 0;
+  if ((st = aw_ftle_grad_workspace(ens, ckpt_every, &need)) != AW_OK) return st;
+  const int64_t N = ens_size(*ens);
+  if (N > 0 && !w0_dev) return fail(AW_EINVAL, "null tangent start");
+  if (N > 0 && (!grad_ic_dev || !grad_eps_dev)) return fail(AW_EINVAL, "null gradient outputs");
+  if (ws_bytes < need || (N > 0 && !workspace_dev))
+    return fail(AW_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  FtleDesc d;
+  std::memset(&d, 0, sizeof d);
+  double tau[MAX_UNIQUE];
+  (void)unique_weights(ens->map_form, ens->h, tau, d.drift);
+  for (int u = 0; u < MAX_UNIQUE; ++u) {
+    d.ka2[u] = 2.0 * tau[u] * ens->eps;
+    d.ka4[u] = 4.0 * tau[u] * ens->eps;
+    d.kw2[u] = 2.0 * tau[u];
+    d.kw4[u] = 4.0 * tau[u];
+  }
+  d.eps = ens->eps;
+  d.T = ens->n_steps;
+  d.N = N;
+  d.ckpt = std::min(ckpt_every, ens->n_steps);
+  d.n_seg = (d.T + d.ckpt - 1) / d.ckpt;
+  d.ic = ic_dev;
+  d.w0 = w0_dev;
+  d.gL = grad_L_dev;
+  d.L = L_out_dev;
+  d.gic = grad_ic_dev;
+  d.geps = grad_eps_dev;
+  d.ckpts = (double *)workspace_dev;
+  d.steps = d.ckpts + (size_t)d.n_seg * 12 * (size_t)N;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_ftle_forward(d, ens->map_form, t, s);
+  if (e != hipSuccess) return hip_fail(e, "FTLE-gradient forward launch");
+  e = launch_ftle_backward(d, ens->map_form, t, s);
+  if (e != hipSuccess) return hip_fail(e, "FTLE-gradient backward launch");
+  return AW_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Graphs of the batched image path.
 // ---------------------------------------------------------------------------

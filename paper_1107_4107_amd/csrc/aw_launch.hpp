@@ -55,4 +55,15 @@ hipError_t launch_hist_reduce(int64_t N, const uint32_t *bins, const double *val
 hipError_t launch_adj_forward(const AdjDesc &d, int form, const Tuning &t, hipStream_t s);
 hipError_t launch_adj_backward(const AdjDesc &d, int form, const Tuning &t, hipStream_t s);
 
+// Gradient of the tangent-growth indicator L: the adjoint descriptor, whose
+// checkpoint and step buffers then hold 12 rows (state and tangent) per
+// orbit, plus the tangent start, the upstream gradient and L.
+struct FtleDesc : AdjDesc {
+  const double *w0;  // [6][N]
+  const double *gL;  // [N] or null (ones)
+  double *L;         // [N] or null
+};
+hipError_t launch_ftle_forward(const FtleDesc &d, int form, const Tuning &t, hipStream_t s);
+hipError_t launch_ftle_backward(const FtleDesc &d, int form, const Tuning &t, hipStream_t s);
+
 }  // namespace aw

@@ -121,6 +121,33 @@ def test_grad_workspace_size():
     assert lib.aw_indicator_grad_workspace(ctypes.byref(e), 0, ctypes.byref(nb)) == _abi.AW_EINVAL
 
 
+def test_ftle_grad_workspace_and_validation():
+    """Workspace of the FTLE gradient: 12 doubles (state and tangent) per orbit
+    per checkpoint and per step of a segment; bad calls are refused on the
+    host before any device work."""
+    lib = _abi.load()
+    e = _ens(ic_kind="explicit", n_orbits=1000, n_steps=10_000)
+    nb = ctypes.c_size_t()
+    assert lib.aw_ftle_grad_workspace(ctypes.byref(e), 100, ctypes.byref(nb)) == 0
+    assert nb.value == 8 * 12 * 1000 * (100 + 100)
+    assert lib.aw_ftle_grad_workspace(ctypes.byref(e), 0, ctypes.byref(nb)) == _abi.AW_EINVAL
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation first
+    # not EXPLICIT
+    g = _ens()
+    assert lib.aw_ftle_grad(ctypes.byref(g), None, fake, None, 100, None, fake, fake, fake, 1 << 40, None,
+                            None) == _abi.AW_EINVAL
+    # no tangent start
+    assert lib.aw_ftle_grad(ctypes.byref(e), fake, None, None, 100, None, fake, fake, fake, 1 << 40, None,
+                            None) == _abi.AW_EINVAL
+    # workspace too small
+    assert lib.aw_ftle_grad(ctypes.byref(e), fake, fake, None, 100, None, fake, fake, fake, nb.value - 8, None,
+                            None) == _abi.AW_EWORKSPACE
+    # no gradient outputs
+    assert lib.aw_ftle_grad(ctypes.byref(e), fake, fake, None, 100, None, None, fake, fake, 1 << 40, None,
+                            None) == _abi.AW_EINVAL
+    assert lib.aw_last_error()
+
+
 def test_step_op_counts_match_the_stage_structure():
     """Per map step: 9 kicks (3 sincos each) and 10 drifts for the 6th-order
     map; the counts are those of the kernel's formulas (one sincos = 19 fma,

@@ -1,0 +1,164 @@
+"""GPU parity of the second-order adjoint: the gradient of the tangent growth
+L = ln(|w_T| / |w_0|) (the FTLE before its division by T h) with respect to
+the initial state and eps.
+
+References: the oracle's forward-over-forward derivatives (pinned against
+finite differences and mpmath third derivatives), central differences of the
+GPU's own forward L, and the autograd wrapper.  Bars: on regular orbits
+(oracle chi < 1.5) the seven derivatives to 1e-8 of the orbit's largest
+derivative and L to 1e-9 at T = 1000 (a relative change of 1e-15 in the
+initial state alone moves the oracle's derivatives by up to 1.6e-10 there;
+measured: 6.6e-10 and 1.9e-11);
+results bitwise independent of the checkpoint interval."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import H, gpu, need_gpu, np_, print_case
+
+pytestmark = gpu
+
+
+@pytest.fixture(scope="module")
+def aw():
+    need_gpu()
+    import paper_1107_4107_amd as m
+    return m
+
+
+def _slice_ic(n, pz0, idx):
+    return oracle.ic_grid2((3, 4), (0.0, 0.0), (2 * np.pi, 2 * np.pi), n, n, [0.0, 0.0, 0.0, 0.0, 0.0, pz0], idx=idx)
+
+
+def _explicit(aw, eps, T, N, form="s6"):
+    return aw.Ensemble(eps=eps, n_steps=T, map_form=form, ic_kind="explicit", n_orbits=N, tangent=True)
+
+
+def _per_orbit_close(g, o, rel, what):
+    """|g - o| <= rel * max_c |o_c| for every orbit (columns = orbits)."""
+    scale = np.maximum(np.max(np.abs(o), axis=0), 1e-300)
+    err = np.max(np.abs(g - o), axis=0) / scale
+    print(f"{what}: max rel err {err.max():.3e}, median {np.median(err):.3e}", flush=True)
+    assert np.all(err <= rel), (what, np.sort(err)[-5:])
+
+
+def _to_dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+@pytest.mark.parametrize("pz0", [0.0, 1.0])
+def test_ftle_gradient_matches_oracle(aw, pz0):
+    """256 orbits of the eps = 1e-2 slice (and its pz0 = 1 companion), T = 1000,
+    checkpoints every 100 steps."""
+    print_case("ftle grad vs oracle", pz0)
+    rng = np.random.default_rng(5)
+    idx = np.sort(rng.choice(128 * 128, 256, replace=False))
+    ic = _slice_ic(128, pz0, idx)
+    w0 = oracle.w0(0, idx=idx)
+    T, eps = 1000, 1e-2
+    Lo, dLo = oracle.ftle_grad_ensemble("s6", eps, H, T, ic, w0)
+    e = _explicit(aw, eps, T, 256)
+    L, gic, geps = aw.ftle_grad(e, _to_dev(ic), _to_dev(w0), ckpt_every=100)
+    g = np.vstack([np_(gic), np_(geps)[None]])
+    chi = Lo / np.log(1 + T * H)
+    reg = chi < 1.5
+    assert reg.sum() > 100
+    print(f"L: max abs err {np.max(np.abs(np_(L)[reg] - Lo[reg])):.3e}", flush=True)
+    assert np.max(np.abs(np_(L)[reg] - Lo[reg])) < 1e-9
+    _per_orbit_close(g[:, reg], dLo[:, reg], 1e-8, "dL (regular)")
+
+
+@pytest.mark.parametrize("form", ["stdmap", "s2", "s4"])
+def test_ftle_gradient_other_forms(aw, form):
+    print_case("ftle grad form", form)
+    ic = oracle.ic_box([0.0] * 6, [2 * np.pi] * 6, 9, 64)
+    w0 = oracle.w0(4, 64)
+    T, eps = 200, 2e-2
+    Lo, dLo = oracle.ftle_grad_ensemble(form, eps, H, T, ic, w0)
+    L, gic, geps = aw.ftle_grad(_explicit(aw, eps, T, 64, form), _to_dev(ic), _to_dev(w0), ckpt_every=30)
+    g = np.vstack([np_(gic), np_(geps)[None]])
+    assert np.max(np.abs(np_(L) - Lo)) < 1e-10
+    reg = Lo / np.log(1 + T * H) < 1.5
+    assert reg.sum() > 16
+    _per_orbit_close(g[:, reg], dLo[:, reg], 1e-8, f"dL {form}")
+
+
+def test_ftle_gradient_against_gpu_differences(aw):
+    """Central differences (step 1e-6) of the GPU forward kernel's own L."""
+    import torch
+    print_case("ftle grad vs gpu fd")
+    ic = oracle.ic_box([0.0] * 6, [2 * np.pi] * 6, 13, 64)
+    T, eps, d = 400, 1e-2, 1e-6
+    e = _explicit(aw, eps, T, 64)
+    icd = _to_dev(ic)
+    L, gic, geps = aw.ftle_grad(e, icd)                   # seeded tangent start, as map_ensemble
+    g = np.vstack([np_(gic), np_(geps)[None]])
+
+    def Lf(x, ep):
+        ee = aw.Ensemble(eps=ep, n_steps=T, ic_kind="explicit", n_orbits=64, tangent=True)
+        return np_(aw.map_ensemble(ee, x, want_class=False).orbit_out[aw.OUT_L])
+
+    np.testing.assert_allclose(np_(L), Lf(icd, eps), rtol=0, atol=1e-13)
+    fd = np.empty((7, 64))
+    for c in range(6):
+        dp = icd.clone()
+        dp[c] += d
+        dm = icd.clone()
+        dm[c] -= d
+        fd[c] = (Lf(dp, eps) - Lf(dm, eps)) / (2 * d)
+    fd[6] = (Lf(icd, eps + d) - Lf(icd, eps - d)) / (2 * d)
+    reg = np_(L) / np.log(1 + T * H) < 1.5
+    assert reg.sum() > 16
+    _per_orbit_close(g[:, reg], fd[:, reg], 2e-6, "dL vs differences")
+    torch.cuda.synchronize()
+
+
+def test_ftle_gradient_independent_of_checkpoints(aw):
+    """Ragged horizon (T = 333, not a multiple of 8 or of the interval): the
+    result does not depend on the checkpoint interval, bit for bit."""
+    print_case("ftle grad checkpoints")
+    ic = _to_dev(oracle.ic_box([0.0] * 6, [2 * np.pi] * 6, 3, 300))
+    e = _explicit(aw, 3e-2, 333, 300)
+    ref = aw.ftle_grad(e, ic, ckpt_every=333)
+    for ck in (1, 7, 64, 1000):
+        got = aw.ftle_grad(e, ic, ckpt_every=ck)
+        for a, b in zip(got, ref):
+            np.testing.assert_array_equal(np_(a), np_(b))
+
+
+def test_ftle_gradient_edge_cases(aw):
+    """T = 1 (one step, no rescale), T = 8 (the last step is a rescale step),
+    one orbit, and an empty ensemble."""
+    import torch
+    print_case("ftle grad edges")
+    ic = oracle.ic_box([0.0] * 6, [2 * np.pi] * 6, 17, 5)
+    w0 = oracle.w0(0, 5)
+    for T in (1, 8, 9):
+        Lo, dLo = oracle.ftle_grad_ensemble("s6", 0.1, H, T, ic, w0)
+        L, gic, geps = aw.ftle_grad(_explicit(aw, 0.1, T, 5), _to_dev(ic), _to_dev(w0), ckpt_every=4)
+        _per_orbit_close(np.vstack([np_(gic), np_(geps)[None]]), dLo, 1e-12, f"T={T}")
+        np.testing.assert_allclose(np_(L), Lo, rtol=0, atol=1e-14)
+    one = aw.ftle_grad(_explicit(aw, 0.1, 20, 1), _to_dev(ic[:, :1]), _to_dev(w0[:, :1]))
+    Lo, dLo = oracle.ftle_grad_ensemble("s6", 0.1, H, 20, ic[:, :1], w0[:, :1])
+    _per_orbit_close(np.vstack([np_(one[1]), np_(one[2])[None]]), dLo, 1e-12, "one orbit")
+    empty = torch.empty((6, 0), dtype=torch.float64, device="cuda")
+    L0, g0, e0 = aw.ftle_grad(_explicit(aw, 0.1, 20, 0), empty, empty)
+    assert L0.shape == (0,) and g0.shape == (6, 0) and e0.shape == (0,)
+
+
+def test_ftle_autograd(aw):
+    """IndicatorL: the backward of sum(c * L) equals the adjoint with upstream
+    gradient c; the eps gradient is the sum of the per-orbit contributions."""
+    import torch
+    print_case("ftle autograd")
+    ic = _to_dev(oracle.ic_box([0.0] * 6, [2 * np.pi] * 6, 23, 128))
+    x = ic.t().contiguous().requires_grad_(True)
+    eps = torch.tensor(2e-2, dtype=torch.float64, requires_grad=True)
+    L = aw.IndicatorL.apply(x, eps, 300)
+    c = torch.linspace(-1.0, 2.0, 128, dtype=torch.float64, device="cuda")
+    (L * c).sum().backward()
+    e = _explicit(aw, 2e-2, 300, 128)
+    _, gic, geps = aw.ftle_grad(e, ic, grad_L=c)
+    np.testing.assert_allclose(np_(x.grad), np_(gic).T, rtol=1e-14, atol=1e-14)
+    assert abs(float(eps.grad) - float(geps.sum())) <= 1e-12 * max(1.0, abs(float(eps.grad)))
