@@ -21,8 +21,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "aw_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-STDMAP, S2, S4, S6 = 1, 2, 4, 6
-FORMS = {"stdmap": STDMAP, "s2": S2, "s4": S4, "s6": S6}
+STDMAP, S2, S4, S6, Y6 = 1, 2, 4, 6, 7
+FORMS = {"stdmap": STDMAP, "s2": S2, "s4": S4, "s6": S6, "y6": Y6}
 OUT_ROWS = ("L", "lambda", "chi", "Vx", "Vy", "Vz", "dP2", "J", "dE")
 REC_LEN = 21
 
@@ -80,6 +80,7 @@ def _load():
         "oracle_energy": (d, [_dp, d]),
         "oracle_hp_derivs": (None, [_dp, _dp, _dp, _dp]),
         "oracle_tj_constants": (None, [_dp]),
+        "oracle_y6_weights": (None, [_dp]),
         "oracle_max_threads": (i, []),
     }
     for name, (res, args) in sig.items():
@@ -361,6 +362,13 @@ def tj_constants():
     c = np.empty(4)
     _load().oracle_tj_constants(_ptr(c))
     return c
+
+
+def y6_weights():
+    """(w0, w1, w2, w3) of the 7-stage 6th-order composition, solved by the oracle."""
+    w = np.empty(4)
+    _load().oracle_y6_weights(_ptr(w))
+    return w
 
 
 def max_threads():

@@ -20,6 +20,9 @@
  *     d1 = 1/(2 - 2^(1/5)), d0 = 1 - 2 d1.  The first-order member kick-then-
  *     drift (STDMAP) is the coupled standard map the model section names.
  *     The composition is applied literally (no merging of adjacent drifts).
+ *     A second 6th-order member (Y6) composes seven S2 steps symmetrically,
+ *     S2(w3 t) S2(w2 t) S2(w1 t) S2(w0 t) S2(w1 t) S2(w2 t) S2(w3 t), with the
+ *     weights solved here from the order conditions (see y6_conditions).
  *   - Per-orbit observables: the finite-time mean velocity
  *     V = [X(t + dt) - X(t)] / dt on the unwrapped coordinates (section "Main
  *     results"), the momentum drift |P(t) - P(0)|^2 (model section), and a
@@ -51,6 +54,7 @@
 #define OR_S2 2
 #define OR_S4 4
 #define OR_S6 6
+#define OR_Y6 7
 
 /* Number of doubles in a resumable per-orbit record:
  * X[3] P[3] w[6] X0[3] P0[3] L Jsum steps. */
@@ -196,6 +200,103 @@ static void kick(orbit *o, double tau)
         o->s[3 + a] = o->s[3 + a] - tau * o->eps * g[a];
 }
 
+/* ------------------------------------------------------------------------ */
+/* Weights of the 7-stage symmetric composition of order 6.                 */
+/*                                                                          */
+/* With log S2(t) = t A + t^3 B + t^5 C + O(t^7) (S2 is symmetric, so only  */
+/* odd powers occur), the composition, built from the middle outwards by    */
+/* the symmetric Baker-Campbell-Hausdorff formula                           */
+/*   log(e^X e^Z e^X) = 2X + Z - [X,[X,Z]]/6 + [Z,[Z,X]]/6 + (degree 5),    */
+/* has log = a t A + b t^3 B + c t^5 C + d t^5 [A,[A,B]] + O(t^7) with      */
+/*   start (middle stage w0): a = w0, b = w0^3, c = w0^5, d = 0;            */
+/*   each outer pair w:       k = a w^3 - b w,  d += k (a + w) / 6,         */
+/*                            a += 2w, b += 2w^3, c += 2w^5                 */
+/* (degree-5 brackets of A alone vanish; those holding B are O(t^7)).       */
+/* Order 6 requires a = 1, b = c = d = 0.  With w0 = 1 - 2(w1 + w2 + w3)    */
+/* that is three equations in (w1, w2, w3); their real roots are found by   */
+/* Newton's method in long double from a grid of starts, and the root with  */
+/* the smallest |w0| + 2(|w1| + |w2| + |w3|) -- the least stepping back and */
+/* forth in time -- is used.                                                */
+/* ------------------------------------------------------------------------ */
+
+static void y6_conditions(const long double w[3], long double f[3])
+{
+    long double a = 1.0L - 2.0L * (w[0] + w[1] + w[2]);
+    long double b = a * a * a, c = b * a * a, d = 0.0L;
+    for (int i = 0; i < 3; i++) {
+        long double v = w[i];
+        long double k = a * v * v * v - b * v;
+        d = d + k * (a + v) / 6.0L;
+        a = a + 2.0L * v;
+        b = b + 2.0L * v * v * v;
+        c = c + 2.0L * v * v * v * v * v;
+    }
+    f[0] = b;
+    f[1] = c;
+    f[2] = d;
+}
+
+/* Newton's method with a central-difference Jacobian; returns 0 on
+ * convergence (|f| < 1e-18), -1 otherwise. */
+static int y6_newton(long double w[3])
+{
+    for (int it = 0; it < 200; it++) {
+        long double f[3], J[3][3];
+        y6_conditions(w, f);
+        long double nf = fabsl(f[0]) + fabsl(f[1]) + fabsl(f[2]);
+        if (!(nf < 1e6L)) return -1;
+        if (nf < 1e-18L) return 0;
+        for (int j = 0; j < 3; j++) {
+            long double wp[3] = {w[0], w[1], w[2]}, wm[3] = {w[0], w[1], w[2]}, fp[3], fm[3];
+            long double dj = 1e-7L * (1.0L + fabsl(w[j]));
+            wp[j] += dj;
+            wm[j] -= dj;
+            y6_conditions(wp, fp);
+            y6_conditions(wm, fm);
+            for (int i = 0; i < 3; i++) J[i][j] = (fp[i] - fm[i]) / (2.0L * dj);
+        }
+        /* solve J dx = -f by Cramer's rule */
+        long double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1])
+                        - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0])
+                        + J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        if (!(fabsl(det) > 1e-30L)) return -1;
+        long double dx[3];
+        for (int c = 0; c < 3; c++) {
+            long double M[3][3];
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++) M[i][j] = (j == c) ? -f[i] : J[i][j];
+            dx[c] = (M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1])
+                   - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0])
+                   + M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0])) / det;
+        }
+        for (int j = 0; j < 3; j++) w[j] = w[j] + dx[j];
+    }
+    return -1;
+}
+
+/* Y6W = (w0, w1, w2, w3), computed once when the library is loaded. */
+static double Y6W[4];
+
+__attribute__((constructor)) static void y6_init(void)
+{
+    long double best[3] = {0, 0, 0}, best_cost = 1e30L;
+    const long double grid[6] = {-2.5L, -1.5L, -0.5L, 0.5L, 1.5L, 2.5L};
+    for (int i = 0; i < 6; i++)
+        for (int j = 0; j < 6; j++)
+            for (int k = 0; k < 6; k++) {
+                long double w[3] = {grid[i], grid[j], grid[k]};
+                if (y6_newton(w)) continue;
+                long double w0 = 1.0L - 2.0L * (w[0] + w[1] + w[2]);
+                long double cost = fabsl(w0) + 2.0L * (fabsl(w[0]) + fabsl(w[1]) + fabsl(w[2]));
+                if (cost < best_cost) {
+                    best_cost = cost;
+                    for (int m = 0; m < 3; m++) best[m] = w[m];
+                }
+            }
+    Y6W[0] = (double)(1.0L - 2.0L * (best[0] + best[1] + best[2]));
+    for (int m = 0; m < 3; m++) Y6W[1 + m] = (double)best[m];
+}
+
 static double tj_g1(void) { return 1.0 / (2.0 - cbrt(2.0)); }
 static double tj_d1(void) { return 1.0 / (2.0 - pow(2.0, 1.0 / 5.0)); }
 
@@ -222,6 +323,12 @@ static void map_s6(orbit *o, double t)
     map_s4(o, d1 * t);
 }
 
+static void map_y6(orbit *o, double t)
+{
+    const int order[7] = {3, 2, 1, 0, 1, 2, 3};
+    for (int i = 0; i < 7; i++) map_s2(o, Y6W[order[i]] * t);
+}
+
 /* One application of the map of the chosen form with step h. */
 static int map_step(orbit *o, int form, double h)
 {
@@ -230,6 +337,7 @@ static int map_step(orbit *o, int form, double h)
     case OR_S2: map_s2(o, h); return 0;
     case OR_S4: map_s4(o, h); return 0;
     case OR_S6: map_s6(o, h); return 0;
+    case OR_Y6: map_y6(o, h); return 0;
     default: return -1;
     }
 }
@@ -312,7 +420,7 @@ int oracle_ensemble(int form, double eps, double h, long T, long N,
                     const double *ic, const double *w0, double *out, double *state,
                     int nthreads)
 {
-    if (form != OR_STDMAP && form != OR_S2 && form != OR_S4 && form != OR_S6) return -1;
+    if (form != OR_STDMAP && form != OR_S2 && form != OR_S4 && form != OR_S6 && form != OR_Y6) return -1;
     if (T < 1 || N < 0) return -1;
 #ifdef _OPENMP
     if (nthreads <= 0) nthreads = omp_get_max_threads();
@@ -522,7 +630,7 @@ static void map2_s6(orbit2 *o, double t)
 int oracle_ftle_grad(int form, double eps, double h, long T, const double s0[6], const double w0[6],
                      double *L, double dL[7], double *sT)
 {
-    if (form != OR_STDMAP && form != OR_S2 && form != OR_S4 && form != OR_S6) return -1;
+    if (form != OR_STDMAP && form != OR_S2 && form != OR_S4 && form != OR_S6 && form != OR_Y6) return -1;
     orbit2 o;
     o.eps = eps;
     double n0 = 0.0;
@@ -542,6 +650,11 @@ int oracle_ftle_grad(int form, double eps, double h, long T, const double s0[6],
         case OR_STDMAP: kick2(&o, h); drift2(&o, h); break;
         case OR_S2: map2_s2(&o, h); break;
         case OR_S4: map2_s4(&o, h); break;
+        case OR_Y6: {
+            const int order[7] = {3, 2, 1, 0, 1, 2, 3};
+            for (int i = 0; i < 7; i++) map2_s2(&o, Y6W[order[i]] * h);
+            break;
+        }
         default: map2_s6(&o, h); break;
         }
         double n2 = 0.0;
@@ -723,7 +836,7 @@ void oracle_ic_cloud(double E, double eps, const double cloud[4], const double x
 int oracle_window_velocities(int form, double eps, double h, long N, const double *ic, long n_windows,
                              long window_steps, double *V, int nthreads)
 {
-    if (form != OR_STDMAP && form != OR_S2 && form != OR_S4 && form != OR_S6) return -1;
+    if (form != OR_STDMAP && form != OR_S2 && form != OR_S4 && form != OR_S6 && form != OR_Y6) return -1;
     if (n_windows < 1 || window_steps < 1 || N < 0) return -1;
     double dt = (double)window_steps * h;
 #ifdef _OPENMP
@@ -766,7 +879,7 @@ int oracle_ensemble_window(int form, double eps, double h, long T, long N, const
                            const double *w0, const double win[4], double *out, uint8_t *left,
                            double *margin, int nthreads)
 {
-    if (form != OR_STDMAP && form != OR_S2 && form != OR_S4 && form != OR_S6) return -1;
+    if (form != OR_STDMAP && form != OR_S2 && form != OR_S4 && form != OR_S6 && form != OR_Y6) return -1;
     if (T < 1 || N < 0) return -1;
 #ifdef _OPENMP
     if (nthreads <= 0) nthreads = omp_get_max_threads();
@@ -869,6 +982,12 @@ void oracle_hp_derivs(const double X[3], double *hp, double g[3], double H6[6])
     H6[3] = Hs[0][1];
     H6[4] = Hs[0][2];
     H6[5] = Hs[1][2];
+}
+
+/* Weights (w0, w1, w2, w3) of the 7-stage composition, as solved here. */
+void oracle_y6_weights(double w[4])
+{
+    for (int i = 0; i < 4; i++) w[i] = Y6W[i];
 }
 
 /* Triple-jump constants as evaluated here: g1, g0, d1, d0. */

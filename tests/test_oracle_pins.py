@@ -73,6 +73,43 @@ def test_triple_jump_order_conditions(orc):
     assert abs(2 * d1 ** 5 + d0 ** 5) < 1e-14
 
 
+def test_y6_weights_give_order_six_on_a_free_lie_algebra(orc):
+    """The 7-stage weights, checked without the order conditions they were
+    solved from: with generic matrices A, B, C standing in for the terms of
+    log S2(t) = t A + t^3 B + t^5 C, the symmetric product of the seven
+    exponentials must equal exp((sum w) t A) up to O(t^7), so the remainder
+    over t^5 is O(t^2) (sum w is taken exactly, since the double-rounded
+    weights sum to 1 only within 1e-16).  The same weights in another order
+    keep sum w^3 = sum w^5 = 0 but not the [A,[A,B]] condition, and leave an
+    O(1) remainder, as does the 4th-order triple jump."""
+    w0, w1, w2, w3 = orc.y6_weights()
+    assert abs(w0 + 2 * (w1 + w2 + w3) - 1) < 1e-15
+    mpmath.mp.dps = 50
+    rng = np.random.default_rng(31)
+
+    def rnd():
+        return mpmath.matrix(rng.uniform(-1, 1, (4, 4)).tolist())
+
+    A, B, C = rnd(), rnd(), rnd()
+
+    def remainder(ws, t):
+        t = mpmath.mpf(t)
+        P = mpmath.eye(4)
+        total = mpmath.mpf(0)
+        for w in ws:
+            wt = mpmath.mpf(float(w)) * t
+            total += mpmath.mpf(float(w))
+            P = P * mpmath.expm(wt * A + wt ** 3 * B + wt ** 5 * C)
+        return mpmath.mnorm(mpmath.logm(P) - total * t * A, 1) / t ** 5
+
+    good = (w3, w2, w1, w0, w1, w2, w3)
+    r1, r2 = remainder(good, "2e-3"), remainder(good, "1e-3")
+    assert r1 < 1e-3 and 2.5 < r1 / r2 < 6, (r1, r2)          # O(t^2)
+    assert remainder((w1, w2, w3, w0, w3, w2, w1), "1e-3") > 1.0
+    g1, g0, _, _ = orc.tj_constants()
+    assert remainder((g1, g0, g1), "1e-3") > 1.0
+
+
 # ---------------------------------------------------------------- eq. 2 derivatives
 def test_hp_derivatives_against_mpmath(orc):
     rng = np.random.default_rng(11)
@@ -132,7 +169,7 @@ def test_hp_fourier_form_and_bound(orc):
 
 
 # ---------------------------------------------------------------- eps = 0
-@pytest.mark.parametrize("form", ["stdmap", "s2", "s4", "s6"])
+@pytest.mark.parametrize("form", ["stdmap", "s2", "s4", "s6", "y6"])
 def test_integrable_limit(orc, form):
     """eps = 0: P constant, X(t) = X(0) + P t, and the tangent grows by the
     linear shear: L_T = 1/2 ln(|dX0 + T h dP0|^2 + |dP0|^2)."""
@@ -163,7 +200,8 @@ def test_s6_tracks_hamiltonian_flow(orc):
         assert np.max(np.abs(got - ref)) < 1e-10
 
 
-@pytest.mark.parametrize("form,order,h", [("stdmap", 1, 0.02), ("s2", 2, 0.05), ("s4", 4, 0.1), ("s6", 6, 0.2)])
+@pytest.mark.parametrize("form,order,h", [("stdmap", 1, 0.02), ("s2", 2, 0.05), ("s4", 4, 0.1), ("s6", 6, 0.2),
+                                          ("y6", 6, 0.2)])
 def test_convergence_order(orc, form, order, h):
     """Error against the exact flow falls by 2^order per halving of h."""
     s0 = np.array([0.3, 1.1, 0.7, 0.9, -0.4, 0.6])
@@ -178,7 +216,7 @@ def test_convergence_order(orc, form, order, h):
 
 
 # ---------------------------------------------------------------- symplecticity, reversibility
-@pytest.mark.parametrize("form", ["stdmap", "s6"])
+@pytest.mark.parametrize("form", ["stdmap", "s6", "y6"])
 def test_symplectic_jacobian(orc, form):
     Om = np.block([[np.zeros((3, 3)), np.eye(3)], [-np.eye(3), np.zeros((3, 3))]])
     s0 = np.array([0.4, 2.0, 1.3, 0.7, 0.2, -0.5])
@@ -200,7 +238,7 @@ def test_jacobian_against_finite_differences(orc, form):
     assert np.max(np.abs(M - fd)) < 1e-7
 
 
-@pytest.mark.parametrize("form", ["s2", "s4", "s6"])
+@pytest.mark.parametrize("form", ["s2", "s4", "s6", "y6"])
 def test_time_reversibility(orc, form):
     """Symmetric compositions: S(-h) S(h) = id and R S R S = id, R(X, P) = (X, -P)."""
     s0 = np.array([0.4, 2.0, 1.3, 0.7, 0.2, -0.5])
@@ -318,7 +356,8 @@ def test_J_gradient_symmetry_on_invariant_plane(orc):
     assert dJ[2] == 0.0 and dJ[5] == 0.0
 
 
-@pytest.mark.parametrize("form,eps,T", [("s6", 5e-2, 60), ("s6", 1.0, 40), ("stdmap", 0.3, 80), ("s2", 0.1, 50)])
+@pytest.mark.parametrize("form,eps,T", [("s6", 5e-2, 60), ("s6", 1.0, 40), ("stdmap", 0.3, 80), ("s2", 0.1, 50),
+                                        ("y6", 0.2, 40)])
 def test_ftle_gradient_against_finite_differences(orc, form, eps, T):
     """Forward-over-forward dL/d(x0..pz0, eps) against central differences of
     the plain one-tangent oracle's L (a separate code path: no third
