@@ -24,7 +24,9 @@ Other workloads (measurement records, not the default line):
   nsweep  map-steps/s against the ensemble size N = 1e3 .. 1e7 at T = 1e4
       (the c5 distribution): where the device fills;
   peak    the achievable FP64 rate of independent FMA chains and the shader
-      clock the SIMDs sustain under that load (the probe library).
+      clock the SIMDs sustain under that load (the probe library);
+  forms   the integrators side by side on one slice (eps = 1e-2, 512 x 512,
+      pz0 = 1, T = 1e4): map-steps/s and the energy error |dE| at h and 2h.
 
 Prints ONE JSON line.  Single GPU only.
 """
@@ -490,6 +492,39 @@ def run_peak(args, aw, wl, torch):
     return rec, None
 
 
+def run_forms(args, aw, wl, torch):
+    """Integrators compared on the eps = 1e-2, 512 x 512 (px, py) slice with
+    pz0 = 1, T = 1e4: throughput, and the energy error |dE| (median and 99th
+    percentile over the slice) at the paper's h and at 2h, with T halved at 2h
+    so that both cover the same time."""
+    import numpy as np
+    rows = []
+    for form in ("stdmap", "s2", "s4", "s6", "y6"):
+        for hs in (1.0, 2.0):
+            T = int(10_000 / hs)
+            e = dataclasses.replace(wl.slice_ensemble(1e-2, 512, T, map_form=form, pz0=1.0), h=aw.H_PAPER * hs)
+            aw.map_ensemble(dataclasses.replace(e, n_steps=10), want_class=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = aw.map_ensemble(e, want_class=False)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            dE = np.abs(r.orbit_out[aw.OUT_DE].cpu().numpy())
+            fma, mul, add = aw.step_op_counts(form, True)
+            rows.append({"form": form, "h_over_paper_h": hs, "n_steps": T, "map_steps_per_s": e.size * T / wall,
+                         "kicks_per_step": {"stdmap": 1, "s2": 1, "s4": 3, "s6": 9, "y6": 7}[form],
+                         "flop_per_step": 2 * fma + mul + add, "wall_s": wall,
+                         "dE_median": float(np.median(dE)), "dE_p99": float(np.quantile(dE, 0.99))})
+            log(f"{form} h x{hs:g}: {rows[-1]['map_steps_per_s']:.4g} steps/s, |dE| median "
+                f"{rows[-1]['dE_median']:.3e}, p99 {rows[-1]['dE_p99']:.3e}")
+    tot = sum(r["n_steps"] * 512 * 512 for r in rows)
+    rec = base_record(tot / sum(r["wall_s"] for r in rows), 1, 1, sum(r["wall_s"] for r in rows) * 1e3)
+    rec["config"] = {"workload": "integrator comparison: eps=1e-2, 512x512 (px,py) slice with pz0=1, "
+                                 "t = 1e4 h, tangent on, at h and 2h"}
+    rec["forms"] = rows
+    return rec, None
+
+
 def run_sweep(args, aw, wl, torch):
     """Chaotic fraction (chi > 2) against eps on the literal slice and on the
     pz0 = 1 companion (256 x 256, T = 3e4, 16 eps values), each slice as one
@@ -530,7 +565,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "fig2", "fig3", "fig4", "sweep",
-                                                             "nsweep", "peak"])
+                                                             "nsweep", "peak", "forms"])
     ap.add_argument("--windows", type=int, default=200, help="fig4: number of 50 T windows")
     ap.add_argument("--t-scale", type=float, default=1.0, help="c3/c5: scale the horizons")
     ap.add_argument("--n-orbits", type=int, default=10_000_000, help="c5: ensemble size")
@@ -569,7 +604,7 @@ def main():
         del src, dst
     runner = {"c1": run_slice, "c2": run_slice, "c3": run_batched, "c4": run_adjoint, "c5": run_large,
               "fig2": run_sphere, "fig3": run_sphere, "fig4": run_diffusion, "sweep": run_sweep,
-              "nsweep": run_nsweep, "peak": run_peak}
+              "nsweep": run_nsweep, "peak": run_peak, "forms": run_forms}
     rec, ens = runner[args.workload](args, aw, wl, torch)
     rec.setdefault("cpu_baseline", None)
     if ens is not None and not args.no_cpu_baseline and args.workload in ("c1", "c2", "c5"):

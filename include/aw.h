@@ -57,9 +57,12 @@ const char *aw_version(void);
 /* Frees the library's internal scratch on the current device (synchronises it). */
 aw_status aw_release(void);
 
-/* Map forms: the first-order coupled standard map and the symmetric
- * compositions of order 2, 4 and 6 (section "Computational method"). */
-typedef enum { AW_MAP_STDMAP = 1, AW_MAP_S2 = 2, AW_MAP_S4 = 4, AW_MAP_S6 = 6 } aw_map_form;
+/* Map forms (section "Computational method"): the first-order coupled
+ * standard map (kick then drift), and symmetric compositions of the
+ * drift-kick-drift step S2: order 2 (S2), 4 and 6 by triple jumps (S4, S6:
+ * 9 kicks per step), and the 7-stage symmetric composition of order 6 (Y6:
+ * 7 kicks per step, weights solved from the order conditions). */
+typedef enum { AW_MAP_STDMAP = 1, AW_MAP_S2 = 2, AW_MAP_S4 = 4, AW_MAP_S6 = 6, AW_MAP_Y6 = 7 } aw_map_form;
 
 /* Initial conditions of an ensemble (sections "Main results", Figs. 2-4).
  *  GRID2:    a 2-D slice: s = base; s[axis[0]] = lo[0] + i * ((hi[0]-lo[0])/nx),

@@ -19,11 +19,11 @@ import torch
 
 from . import _abi
 from ._abi import (AwError, F_TANGENT, F_WINDOW, IC_BOX, IC_EXPLICIT, IC_GRID2, IC_SPHERE, IMG_HIST_P0, IMG_HIST_VDIR,
-                   IMG_IC_GRID, MAP_S2, MAP_S4, MAP_S6, MAP_STDMAP, NCARRY, NOUT, OUT_CHI, OUT_DE,
+                   IMG_IC_GRID, MAP_S2, MAP_S4, MAP_S6, MAP_STDMAP, MAP_Y6, NCARRY, NOUT, OUT_CHI, OUT_DE,
                    OUT_DP2, OUT_J, OUT_L, OUT_LAMBDA, OUT_VX, OUT_VY, OUT_VZ)
 
 H_PAPER = 0.01 * 2.0 * math.pi  # h = 10^-2 T, T = 2 pi (section "Computational method")
-FORMS = {"stdmap": MAP_STDMAP, "s2": MAP_S2, "s4": MAP_S4, "s6": MAP_S6}
+FORMS = {"stdmap": MAP_STDMAP, "s2": MAP_S2, "s4": MAP_S4, "s6": MAP_S6, "y6": MAP_Y6}
 OUT_ROWS = ("L", "lambda", "chi", "Vx", "Vy", "Vz", "dP2", "J", "dE")
 
 __all__ = [

@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(HERE, "libaw.so")
 AW_OK, AW_EINVAL, AW_EUNSUPPORTED, AW_EDEVICE, AW_ENOMEM, AW_EWORKSPACE = range(6)
 STATUS_NAMES = {0: "AW_OK", 1: "AW_EINVAL", 2: "AW_EUNSUPPORTED", 3: "AW_EDEVICE", 4: "AW_ENOMEM",
                 5: "AW_EWORKSPACE"}
-MAP_STDMAP, MAP_S2, MAP_S4, MAP_S6 = 1, 2, 4, 6
+MAP_STDMAP, MAP_S2, MAP_S4, MAP_S6, MAP_Y6 = 1, 2, 4, 6, 7
 IC_GRID2, IC_BOX, IC_EXPLICIT, IC_SPHERE, IC_CLOUD = 0, 1, 2, 3, 4
 F_TANGENT = 1
 F_WINDOW = 2

@@ -187,6 +187,7 @@ hipError_t launch_adj_forward(const AdjDesc &d, int form, const Tuning &t, hipSt
   case 2: hipLaunchKernelGGL(k_adj_fwd<2>, dim3(blocks), dim3(t.block), 0, s, d); break;
   case 4: hipLaunchKernelGGL(k_adj_fwd<4>, dim3(blocks), dim3(t.block), 0, s, d); break;
   case 6: hipLaunchKernelGGL(k_adj_fwd<6>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  case 7: hipLaunchKernelGGL(k_adj_fwd<7>, dim3(blocks), dim3(t.block), 0, s, d); break;
   default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -200,6 +201,7 @@ hipError_t launch_adj_backward(const AdjDesc &d, int form, const Tuning &t, hipS
   case 2: hipLaunchKernelGGL(k_adj_bwd<2>, dim3(blocks), dim3(t.block), 0, s, d); break;
   case 4: hipLaunchKernelGGL(k_adj_bwd<4>, dim3(blocks), dim3(t.block), 0, s, d); break;
   case 6: hipLaunchKernelGGL(k_adj_bwd<6>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  case 7: hipLaunchKernelGGL(k_adj_bwd<7>, dim3(blocks), dim3(t.block), 0, s, d); break;
   default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -16,6 +16,7 @@
 
 #include "aw.h"
 #include "aw_internal.hpp"
+#include "aw_y6_coef.h"
 #include "aw_launch.hpp"
 
 using namespace aw;
@@ -141,6 +142,10 @@ Stages stages_of(int form) {
   } else if (form == AW_MAP_S6) {
     const double w[9] = {g1 * d1, g0 * d1, g1 * d1, g1 * d0, g0 * d0, g1 * d0, g1 * d1, g0 * d1, g1 * d1};
     from_kicks(w, 9);
+  } else if (form == AW_MAP_Y6) {
+    const double *y = AW_Y6_W;  // w0, w1, w2, w3
+    const double w[7] = {y[3], y[2], y[1], y[0], y[1], y[2], y[3]};
+    from_kicks(w, 7);
   }
   return s;
 }
@@ -156,6 +161,7 @@ Pattern pattern_of(int form) {
   case 1: return {FormPattern<1>::NK, FormPattern<1>::ND, FormPattern<1>::kick_idx, FormPattern<1>::drift_idx};
   case 2: return {FormPattern<2>::NK, FormPattern<2>::ND, FormPattern<2>::kick_idx, FormPattern<2>::drift_idx};
   case 4: return {FormPattern<4>::NK, FormPattern<4>::ND, FormPattern<4>::kick_idx, FormPattern<4>::drift_idx};
+  case 7: return {FormPattern<7>::NK, FormPattern<7>::ND, FormPattern<7>::kick_idx, FormPattern<7>::drift_idx};
   default: return {FormPattern<6>::NK, FormPattern<6>::ND, FormPattern<6>::kick_idx, FormPattern<6>::drift_idx};
   }
 }
@@ -217,7 +223,7 @@ aw_status check_ensemble(const aw_ensemble *e, const double *ic, int idx) {
   if (!e) return fail(AW_EINVAL, "ensemble %d: null descriptor", idx);
   if (e->M != 3) return fail(AW_EUNSUPPORTED, "ensemble %d: only M = 3 is defined (got %d)", idx, e->M);
   if (e->map_form != AW_MAP_STDMAP && e->map_form != AW_MAP_S2 && e->map_form != AW_MAP_S4 &&
-      e->map_form != AW_MAP_S6)
+      e->map_form != AW_MAP_S6 && e->map_form != AW_MAP_Y6)
     return fail(AW_EINVAL, "ensemble %d: unknown map_form %d", idx, e->map_form);
   if (!is_fin(e->eps)) return fail(AW_EINVAL, "ensemble %d: eps must be finite", idx);
   if (!is_fin(e->h) || e->h == 0.0) return fail(AW_EINVAL, "ensemble %d: h must be finite and non-zero", idx);
@@ -988,7 +994,9 @@ aw_status aw_timing_read(double *ms, int64_t *launches) {
 
 aw_status aw_step_op_counts(int32_t map_form, int32_t tangent, int64_t *fma, int64_t *mul, int64_t *add) {
   if (!fma || !mul || !add) return fail(AW_EINVAL, "null output");
-  if (map_form != 1 && map_form != 2 && map_form != 4 && map_form != 6) return fail(AW_EINVAL, "unknown map_form");
+  if (map_form != AW_MAP_STDMAP && map_form != AW_MAP_S2 && map_form != AW_MAP_S4 && map_form != AW_MAP_S6 &&
+      map_form != AW_MAP_Y6)
+    return fail(AW_EINVAL, "unknown map_form");
   step_op_counts(map_form, tangent != 0, fma, mul, add);
   return AW_OK;
 }

@@ -313,6 +313,7 @@ hipError_t launch_ftle_forward(const FtleDesc &d, int form, const Tuning &t, hip
   case 2: hipLaunchKernelGGL(k_ftle_fwd<2>, dim3(blocks), dim3(t.block), 0, s, d); break;
   case 4: hipLaunchKernelGGL(k_ftle_fwd<4>, dim3(blocks), dim3(t.block), 0, s, d); break;
   case 6: hipLaunchKernelGGL(k_ftle_fwd<6>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  case 7: hipLaunchKernelGGL(k_ftle_fwd<7>, dim3(blocks), dim3(t.block), 0, s, d); break;
   default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -326,6 +327,7 @@ hipError_t launch_ftle_backward(const FtleDesc &d, int form, const Tuning &t, hi
   case 2: hipLaunchKernelGGL(k_ftle_bwd<2>, dim3(blocks), dim3(t.block), 0, s, d); break;
   case 4: hipLaunchKernelGGL(k_ftle_bwd<4>, dim3(blocks), dim3(t.block), 0, s, d); break;
   case 6: hipLaunchKernelGGL(k_ftle_bwd<6>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  case 7: hipLaunchKernelGGL(k_ftle_bwd<7>, dim3(blocks), dim3(t.block), 0, s, d); break;
   default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -431,6 +431,7 @@ hipError_t launch_fwd(const FwdDesc &d, const Tuning &t, int form, bool tan, hip
   case 2: return tan ? fwd_dispatch_opl<2, true>(d, t, s) : fwd_dispatch_opl<2, false>(d, t, s);
   case 4: return tan ? fwd_dispatch_opl<4, true>(d, t, s) : fwd_dispatch_opl<4, false>(d, t, s);
   case 6: return tan ? fwd_dispatch_opl<6, true>(d, t, s) : fwd_dispatch_opl<6, false>(d, t, s);
+  case 7: return tan ? fwd_dispatch_opl<7, true>(d, t, s) : fwd_dispatch_opl<7, false>(d, t, s);
   default: return hipErrorInvalidValue;
   }
 }
@@ -457,6 +458,8 @@ hipError_t launch_fwd_batched(const FwdDesc *descs_dev, const WorkItem *items_de
                      : persist_dispatch<4, false>(descs_dev, items_dev, n_items, head_dev, t, n_wg, s);
   case 6: return tan ? persist_dispatch<6, true>(descs_dev, items_dev, n_items, head_dev, t, n_wg, s)
                      : persist_dispatch<6, false>(descs_dev, items_dev, n_items, head_dev, t, n_wg, s);
+  case 7: return tan ? persist_dispatch<7, true>(descs_dev, items_dev, n_items, head_dev, t, n_wg, s)
+                     : persist_dispatch<7, false>(descs_dev, items_dev, n_items, head_dev, t, n_wg, s);
   default: return hipErrorInvalidValue;
   }
 }
@@ -471,7 +474,7 @@ int persistent_blocks_per_cu(int form, bool tan, const Tuning &t) {
     else e = t.opl == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_persist<F, false, 1>, t.block, 0) \
                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_persist<F, false, 2>, t.block, 0); \
   }
-  AW_OCC(1) AW_OCC(2) AW_OCC(4) AW_OCC(6)
+  AW_OCC(1) AW_OCC(2) AW_OCC(4) AW_OCC(6) AW_OCC(7)
 #undef AW_OCC
   return (e == hipSuccess && nb > 0) ? nb : 1;
 }
@@ -498,6 +501,7 @@ void step_op_counts(int form, bool tan, int64_t *fma, int64_t *mul, int64_t *add
   case 2: nk = 1; nd = 2; break;
   case 4: nk = 3; nd = 4; break;
   case 6: nk = 9; nd = 10; break;
+  case 7: nk = 7; nd = 8; break;
   default: break;
   }
   const int kf = tan ? KickOps<true>::fma : KickOps<false>::fma;

@@ -40,6 +40,13 @@ template <> struct FormPattern<6> {
   static constexpr int kick_idx[9] = {0, 1, 0, 2, 3, 2, 0, 1, 0};
   static constexpr int drift_idx[10] = {0, 1, 1, 2, 3, 3, 2, 1, 1, 0};
 };
+// Y6: S2(w3) S2(w2) S2(w1) S2(w0) S2(w1) S2(w2) S2(w3).
+template <> struct FormPattern<7> {
+  static constexpr int NK = 7, ND = 8;
+  static constexpr bool LEAD = true;
+  static constexpr int kick_idx[7] = {0, 1, 2, 3, 2, 1, 0};
+  static constexpr int drift_idx[8] = {0, 1, 2, 3, 3, 2, 1, 0};
+};
 constexpr uint32_t BIN_DROP = 0xffffffffu;
 
 // Image epilogue selector of the propagation kernel.

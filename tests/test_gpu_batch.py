@@ -41,6 +41,18 @@ def test_batched_equals_separate(aw, tun):
         np.testing.assert_array_equal(np_(b.cls), np_(s.cls))
 
 
+def test_batched_equals_separate_y6(aw):
+    """The same for the 7-stage 6th-order composition (its own stage pattern)."""
+    import dataclasses
+    print_case("batched vs separate y6")
+    ens = [dataclasses.replace(e, map_form="y6") for e in _mixed(aw)]
+    batch = aw.map_ensembles(ens, want_state=True)
+    for e, b in zip(ens, batch):
+        s = aw.map_ensemble(e, want_state=True)
+        np.testing.assert_array_equal(np_(b.orbit_out), np_(s.orbit_out))
+        np.testing.assert_array_equal(np_(b.state), np_(s.state))
+
+
 def test_graph_replays_match_eager(aw):
     import torch
     print_case("graph replays")

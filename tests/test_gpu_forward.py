@@ -48,7 +48,7 @@ def test_initial_conditions_are_bitwise(aw):
     np.testing.assert_array_equal(np_(w0), oracle.w0(b.seed_tangent, 5000))
 
 
-@pytest.mark.parametrize("form", ["s6", "stdmap", "s2", "s4"])
+@pytest.mark.parametrize("form", ["s6", "stdmap", "s2", "s4", "y6"])
 def test_states_match_for_short_runs(aw, form):
     print_case("states T=50", form)
     e = slice_ens(aw, 1e-2, 64, 50, form)
@@ -65,7 +65,7 @@ def test_states_match_for_short_runs(aw, form):
     assert np.max(np.abs(out[8] - out_o[8])) < 1e-13
 
 
-@pytest.mark.parametrize("form,pz0", [("s6", 0.0), ("s6", 1.0), ("stdmap", 0.0)])
+@pytest.mark.parametrize("form,pz0", [("s6", 0.0), ("s6", 1.0), ("stdmap", 0.0), ("y6", 1.0)])
 def test_indicators_64x64_T1000(aw, form, pz0):
     """The 64 x 64 slice, eps = 1e-2, T = 1000 (and its p_z0 = 1 companion)."""
     print_case("indicators 64x64 T=1000", form, pz0)

@@ -69,7 +69,7 @@ def test_ftle_gradient_matches_oracle(aw, pz0):
     _per_orbit_close(g[:, reg], dLo[:, reg], 1e-8, "dL (regular)")
 
 
-@pytest.mark.parametrize("form", ["stdmap", "s2", "s4"])
+@pytest.mark.parametrize("form", ["stdmap", "s2", "s4", "y6"])
 def test_ftle_gradient_other_forms(aw, form):
     print_case("ftle grad form", form)
     ic = oracle.ic_box([0.0] * 6, [2 * np.pi] * 6, 9, 64)
