@@ -581,8 +581,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the ensemble path has no multi-GPU mode in this build "
-              "(orbits are independent; see the sharding notes).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the ensemble path has no multi-GPU mode (orbits are "
+              "independent, so ensembles shard by orbit ranges; nothing is run across GPUs here).", file=sys.stderr)
         sys.exit(2)
 
     import torch

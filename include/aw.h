@@ -44,7 +44,7 @@ extern "C" {
 typedef enum {
   AW_OK = 0,
   AW_EINVAL = 1,        /* an argument is out of range or inconsistent */
-  AW_EUNSUPPORTED = 2,  /* a well-formed request this build does not do (e.g. M != 3) */
+  AW_EUNSUPPORTED = 2,  /* a well-formed request the library does not do (e.g. M != 3) */
   AW_EDEVICE = 3,       /* a HIP call or kernel launch failed */
   AW_ENOMEM = 4,        /* internal scratch could not be allocated */
   AW_EWORKSPACE = 5     /* caller workspace too small */
