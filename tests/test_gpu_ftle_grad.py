@@ -162,3 +162,34 @@ def test_ftle_autograd(aw):
     _, gic, geps = aw.ftle_grad(e, ic, grad_L=c)
     np.testing.assert_allclose(np_(x.grad), np_(gic).T, rtol=1e-14, atol=1e-14)
     assert abs(float(eps.grad) - float(geps.sum())) <= 1e-12 * max(1.0, abs(float(eps.grad)))
+
+
+def test_ftle_gradient_full_size(aw):
+    """The gradient workload at full size, in the configuration the benchmark
+    times: the 512 x 512 slice, eps = 1e-2, T = 1e4, checkpoints every 100
+    steps, all 262144 orbits in one call.  64 regular orbits drawn with seed 3
+    against the oracle's forward-over-forward derivatives.  Bars: dL to 1e-6
+    of the orbit's largest derivative and L to 1e-7 -- at this horizon a
+    relative change of 1e-15 in the initial state alone moves the oracle's dL
+    by up to 6e-8 and L by 2.4e-9 on these orbits."""
+    print_case("ftle gradient 512x512 T=1e4")
+    from paper_1107_4107_amd import workloads as wl
+    s = wl.c4()
+    N, T = s.nx * s.ny, s.n_steps
+    ic_all, _ = aw.generate_ic(s)
+    e = _explicit(aw, s.eps, T, N)
+    L, gic, geps = aw.ftle_grad(e, ic_all, ckpt_every=wl.C4_CKPT)
+    rng = np.random.default_rng(3)
+    cand = np.sort(rng.choice(N, 160, replace=False))
+    ic = oracle.ic_grid2((3, 4), (0, 0), (2 * np.pi, 2 * np.pi), s.nx, s.ny, list(s.base), idx=cand)
+    w0 = oracle.w0(0, idx=cand)
+    Lo, dLo = oracle.ftle_grad_ensemble("s6", s.eps, H, T, ic, w0)
+    reg = Lo / np.log(1 + T * H) < 1.5
+    pick = np.flatnonzero(reg)[:64]
+    assert pick.size == 64
+    Lg = np_(L)[cand[pick]]
+    print(f"L: max abs err {np.max(np.abs(Lg - Lo[pick])):.3e}", flush=True)
+    assert np.max(np.abs(Lg - Lo[pick])) < 1e-7
+    g = np.vstack([np_(gic)[:, cand[pick]], np_(geps)[None, cand[pick]]])
+    _per_orbit_close(g, dLo[:, pick], 1e-6, "dL full size")
+    assert np.all(np.isfinite(np_(gic))) and np.all(np.isfinite(np_(geps)))
