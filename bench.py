@@ -45,6 +45,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
+# Best rate of independent v_fma_f64 chains measured on this GPU model with
+# `bench.py --workload peak` (8 waves per SIMD, 2.384 GHz sustained).
+FP64_ACHIEVABLE_TFLOPS = 76.92
+KICKS_PER_STEP = {"stdmap": 1, "s2": 1, "s4": 3, "s6": 9, "y6": 7}
 KERNEL_SOURCES = ["paper_1107_4107_amd/csrc/aw_fwd.hip", "paper_1107_4107_amd/csrc/aw_device.hpp",
                   "paper_1107_4107_amd/csrc/aw_sincos_coef.h", "paper_1107_4107_amd/csrc/aw_internal.hpp"]
 METRIC = "orbit map-steps/sec (with tangent map)"
@@ -75,6 +79,24 @@ def traffic_for(workload: str):
     if rec.get("kernel_source_hash") != kernel_hash():
         return None
     return rec.get("bytes_per_launch")
+
+
+def host_info() -> str:
+    """CPU model, logical CPUs and SMT state of the host the oracle runs on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    smt = "unknown"
+    try:
+        smt = "on" if open("/sys/devices/system/cpu/smt/active").read().strip() == "1" else "off"
+    except OSError:
+        pass
+    return f"{model}; {os.cpu_count()} logical CPUs; SMT {smt}"
 
 
 def host_threads() -> int:
@@ -119,7 +141,7 @@ def cpu_baseline(ens, target_s: float, threads: int):
     where = f"{ens.nx}x{ens.ny} slice" if ens.ic_kind == "grid2" else f"{N} orbits"
     return {"value": m * ens.n_steps / t, "unit": "map-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{m} orbits (evenly strided over the {where}) x {ens.n_steps} steps each, "
-                      f"{t:.1f} s on {threads} host threads"}
+                      f"{t:.1f} s on {threads} host threads", "host": host_info()}
 
 
 def roofline(aw, ens, kernel_ms, workload, steps_per_launch=None):
@@ -132,6 +154,8 @@ def roofline(aw, ens, kernel_ms, workload, steps_per_launch=None):
     achieved = flop * ens.size * steps / (kernel_ms * 1e-3) / 1e12
     return {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic_for(workload),
+            "frac_of_achievable_peak": achieved / FP64_ACHIEVABLE_TFLOPS,
+            "force_evals_per_s": KICKS_PER_STEP[ens.map_form] * ens.size * steps / (kernel_ms * 1e-3),
             "kernel": f"k_fwd<{ {'s6': 6, 's4': 4, 's2': 2, 'stdmap': 1}[ens.map_form]},"
                       f"{'true' if ens.tangent else 'false'}> (propagation)",
             "kernel_ms": kernel_ms, "flop_per_map_step": flop,
