@@ -355,6 +355,18 @@ def run_large(args, aw, wl, torch):
                                                                     max(1e-9, abs(out_o[6, k])))}
                                               for k in range(32)],
                                 "class_disagreements": int(np.sum((g[2] > 2) != (out_o[2] > 2)))}
+        # How well FP64 determines these indicators at this horizon: the oracle
+        # against itself with every initial momentum moved by one ulp.
+        ic_p = ic_o.copy()
+        ic_p[3:] = np.nextafter(ic_p[3:], np.inf)
+        out_p = oracle.ensemble("s6", e.eps, e.h, T, ic_p, oracle.w0(e.seed_tangent, idx=idx),
+                                nthreads=host_threads())
+        sL = np.abs(out_p[0] - out_o[0]) / np.maximum(1, np.abs(out_o[0]))
+        sP = np.abs(out_p[6] - out_o[6]) / np.maximum(1e-9, np.abs(out_o[6]))
+        rec["sample_parity"]["oracle_one_ulp_sensitivity"] = {
+            "perturbation": "initial momenta moved by one ulp (oracle vs oracle)",
+            "max_rel_L_regular": float(np.max(sL[reg])), "median_rel_L_regular": float(np.median(sL[reg])),
+            "max_rel_dP2": float(np.max(sP)), "median_rel_dP2": float(np.median(sP))}
     return rec, e
 
 
