@@ -50,7 +50,8 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
 FP64_ACHIEVABLE_TFLOPS = 76.92
 KICKS_PER_STEP = {"stdmap": 1, "s2": 1, "s4": 3, "s6": 9, "y6": 7}
 KERNEL_SOURCES = ["paper_1107_4107_amd/csrc/aw_fwd.hip", "paper_1107_4107_amd/csrc/aw_device.hpp",
-                  "paper_1107_4107_amd/csrc/aw_sincos_coef.h", "paper_1107_4107_amd/csrc/aw_internal.hpp"]
+                  "paper_1107_4107_amd/csrc/aw_sincos_coef.h", "paper_1107_4107_amd/csrc/aw_sincos_tab.h",
+                  "paper_1107_4107_amd/csrc/aw_internal.hpp"]
 METRIC = "orbit map-steps/sec (with tangent map)"
 
 
@@ -79,6 +80,19 @@ def traffic_for(workload: str):
     if rec.get("kernel_source_hash") != kernel_hash():
         return None
     return rec.get("bytes_per_launch")
+
+
+def valu_for(workload: str):
+    """VALU wave-instructions per map step from the committed counter record,
+    if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"valu_{workload}.json")
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    if rec.get("kernel_source_hash") != kernel_hash():
+        return None
+    return rec.get("valu_insts_per_map_step")
 
 
 def host_info() -> str:
@@ -159,7 +173,21 @@ def roofline(aw, ens, kernel_ms, workload, steps_per_launch=None):
             "kernel": f"k_fwd<{ {'s6': 6, 's4': 4, 's2': 2, 'stdmap': 1}[ens.map_form]},"
                       f"{'true' if ens.tangent else 'false'}> (propagation)",
             "kernel_ms": kernel_ms, "flop_per_map_step": flop,
-            "fp64_ops_per_map_step": {"fma": fma, "mul": mul, "add": add}}
+            "fp64_ops_per_map_step": {"fma": fma, "mul": mul, "add": add},
+            "valu_issue": valu_issue(ens, kernel_ms, workload, steps)}
+
+
+def valu_issue(ens, kernel_ms, workload, steps):
+    """The instruction-issue view of the same launch: every wave64 VALU
+    instruction occupies its SIMD for 4 cycles, so the chip issues at most
+    1024 SIMDs x 2.4 GHz / 4 wave-instructions per second."""
+    per_step = valu_for(workload)
+    if per_step is None:
+        return None
+    achieved = per_step / 64.0 * ens.size * steps / (kernel_ms * 1e-3)
+    peak = 1024 * 2.4e9 / 4
+    return {"valu_insts_per_map_step": per_step, "achieved": achieved, "peak": peak,
+            "unit": "wave-instructions/s", "frac": achieved / peak}
 
 
 def base_record(value, steps, warmup, ms_per_step, dtype="f64"):

@@ -13,6 +13,7 @@
 #include <stdint.h>
 
 #include "aw_sincos_coef.h"
+#include "aw_sincos_tab.h"
 
 namespace aw {
 
@@ -58,6 +59,53 @@ __device__ __forceinline__ double flip(double v, uint32_t sgn) {
 constexpr int SC_FMA = 1 + 2 + (AW_SIN_NC - 1) + 1 + (AW_COS_NC - 1) + 1;
 constexpr int SC_MUL = 2;  // r*r, r*u
 constexpr int SC_ADD = 1;  // t - magic
+
+// ---------------------------------------------------------------------------
+// Table-driven sin and cos of an unwrapped angle (the propagation kernels).
+// x = q pi/64 + r with q = nearest integer to 64 x/pi (magic-number rounding:
+// the low mantissa word of q + 1.5*2^52 holds q in two's complement), r by a
+// two-part Cody-Waite step, |r| <= pi/128.  With k = q mod 128 and
+// (S, C) = (sin, cos)(k pi/64) from a 128-entry table in LDS:
+//   sin x = S cos r + C sin r,  cos x = C cos r - S sin r,
+// sin r and cos r by polynomials of three coefficients in r^2.  The table
+// carries every quadrant's signs, so the results are the true sine and
+// cosine.  11 FMA, 4 MUL, 1 ADD and one 16-byte LDS read.
+// ---------------------------------------------------------------------------
+struct SinCosT {
+  double s, c;
+};
+
+__device__ __forceinline__ SinCosT sincos_tab(double x, const double2 *__restrict__ tab) {
+  const double t = __builtin_fma(x, AW_INV_PI64, AW_ROUND_MAGIC);
+  const double q = t - AW_ROUND_MAGIC;
+  double r = __builtin_fma(-q, AW_PI64_A, x);
+  r = __builtin_fma(-q, AW_PI64_B, r);
+  const uint32_t k = (uint32_t)__double2loint(t) & (AW_TAB_N - 1);
+  const double2 e = tab[k];
+  const double u = r * r;
+  double ps = __builtin_fma(AW_TSIN_C[2], u, AW_TSIN_C[1]);
+  ps = __builtin_fma(ps, u, AW_TSIN_C[0]);
+  const double sr = __builtin_fma(r * u, ps, r);
+  double pc = __builtin_fma(AW_TCOS_C[2], u, AW_TCOS_C[1]);
+  pc = __builtin_fma(pc, u, AW_TCOS_C[0]);
+  const double cr = __builtin_fma(u, pc, 1.0);
+  SinCosT o;
+  o.s = __builtin_fma(e.x, cr, e.y * sr);
+  o.c = __builtin_fma(e.y, cr, -(e.x * sr));
+  return o;
+}
+
+// FP64 operation counts of one sincos_tab.
+constexpr int SCT_FMA = 1 + 2 + 2 + 1 + 2 + 1 + 2;
+constexpr int SCT_MUL = 4;  // r*r, r*u, and one product per rotated output
+constexpr int SCT_ADD = 1;
+
+// Fill a block's LDS copy of the (sin, cos)(k pi/64) table; every thread of
+// the block must call this before any of them returns.
+__device__ __forceinline__ void load_sincos_table(double2 *tab) {
+  for (int i = threadIdx.x; i < AW_TAB_N; i += blockDim.x) tab[i] = make_double2(AW_TAB_SC[2 * i], AW_TAB_SC[2 * i + 1]);
+  __syncthreads();
+}
 
 // True signed cos/sin (used outside the hot loop).
 __device__ __forceinline__ void sincos_full(double x, double &s, double &c) {
@@ -125,6 +173,43 @@ __device__ __forceinline__ void kick(Orbit &o, double a2, double a4) {
   o.pz = __builtin_fma(e2, pcc, o.pz);   // -t eps dHp/dz
 }
 
+// The same kick with the table-driven sines and cosines (no sign folding:
+// they are the true values).  Same formulas, same order of operations.
+template <bool TAN>
+__device__ __forceinline__ void kick_tab(Orbit &o, double a2, double a4, const double2 *__restrict__ tab) {
+  const SinCosT X = sincos_tab(o.x, tab), Y = sincos_tab(o.y, tab), Z = sincos_tab(o.z, tab);
+  const double cx = X.c, sx = X.s;
+  const double cy = Y.c, sy = Y.s;
+  const double cz2 = Z.c * Z.c;
+  const double czsz = Z.c * Z.s;
+  const double e1 = a2 * cz2;
+  const double e2 = a4 * czsz;
+  const double psc = sx * cy, pcs = cx * sy, pcc = cx * cy;
+  if (TAN) {
+    const double c2z = __builtin_fma(-Z.s, Z.s, cz2);
+    const double e3 = a4 * c2z;
+    const double pss = sx * sy;
+    const double mxx = e1 * pcc;
+    const double nxy = e1 * pss;
+    const double nxz = e2 * psc;
+    const double nyz = e2 * pcs;
+    const double mzz = e3 * pcc;
+    const double dx = o.dx, dy = o.dy, dz = o.dz;
+    o.dpx = __builtin_fma(mxx, dx, o.dpx);
+    o.dpx = __builtin_fma(-nxy, dy, o.dpx);
+    o.dpx = __builtin_fma(-nxz, dz, o.dpx);
+    o.dpy = __builtin_fma(-nxy, dx, o.dpy);
+    o.dpy = __builtin_fma(mxx, dy, o.dpy);
+    o.dpy = __builtin_fma(-nyz, dz, o.dpy);
+    o.dpz = __builtin_fma(-nxz, dx, o.dpz);
+    o.dpz = __builtin_fma(-nyz, dy, o.dpz);
+    o.dpz = __builtin_fma(mzz, dz, o.dpz);
+  }
+  o.px = __builtin_fma(e1, psc, o.px);
+  o.py = __builtin_fma(e1, pcs, o.py);
+  o.pz = __builtin_fma(e2, pcc, o.pz);
+}
+
 template <bool TAN>
 __device__ __forceinline__ void drift(Orbit &o, double t) {
   o.x = __builtin_fma(t, o.px, o.x);
@@ -142,6 +227,11 @@ template <bool TAN> struct KickOps {
   static constexpr int fma = 3 * SC_FMA + 3 + (TAN ? 1 + 9 : 0);
   static constexpr int mul = 3 * SC_MUL + 7 + (TAN ? 7 : 0);
   static constexpr int add = 3 * SC_ADD;
+};
+template <bool TAN> struct KickTabOps {
+  static constexpr int fma = 3 * SCT_FMA + 3 + (TAN ? 1 + 9 : 0);
+  static constexpr int mul = 3 * SCT_MUL + 7 + (TAN ? 7 : 0);
+  static constexpr int add = 3 * SCT_ADD;
 };
 template <bool TAN> struct DriftOps {
   static constexpr int fma = TAN ? 6 : 3;

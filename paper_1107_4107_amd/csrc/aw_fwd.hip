@@ -90,10 +90,11 @@ __device__ __forceinline__ void gen_w0(uint64_t seed, int64_t n, double w[6]) {
 
 // ---------------------------------------------------------------------------
 // One map step: NK kicks, each preceded by a drift, and a closing drift
-// (symmetric compositions), or kick-then-drift (coupled standard map).
+// (symmetric compositions), or kick-then-drift (coupled standard map).  The
+// kicks take their sines and cosines from the block's LDS table `tab`.
 // ---------------------------------------------------------------------------
 template <int FORM, bool TAN, int OPL>
-__device__ __forceinline__ void map_step(Orbit (&o)[OPL], const FwdDesc &d) {
+__device__ __forceinline__ void map_step(Orbit (&o)[OPL], const FwdDesc &d, const double2 *__restrict__ tab) {
   using F = FormPattern<FORM>;
   constexpr int NK = F::NK;
   if constexpr (F::LEAD) {
@@ -102,13 +103,13 @@ __device__ __forceinline__ void map_step(Orbit (&o)[OPL], const FwdDesc &d) {
 #pragma unroll
       for (int j = 0; j < OPL; ++j) drift<TAN>(o[j], d.drift[F::drift_idx[i]]);
 #pragma unroll
-      for (int j = 0; j < OPL; ++j) kick<TAN>(o[j], d.ka2[F::kick_idx[i]], d.ka4[F::kick_idx[i]]);
+      for (int j = 0; j < OPL; ++j) kick_tab<TAN>(o[j], d.ka2[F::kick_idx[i]], d.ka4[F::kick_idx[i]], tab);
     }
 #pragma unroll
     for (int j = 0; j < OPL; ++j) drift<TAN>(o[j], d.drift[F::drift_idx[NK]]);
   } else {
 #pragma unroll
-    for (int j = 0; j < OPL; ++j) kick<TAN>(o[j], d.ka2[0], d.ka4[0]);
+    for (int j = 0; j < OPL; ++j) kick_tab<TAN>(o[j], d.ka2[0], d.ka4[0], tab);
 #pragma unroll
     for (int j = 0; j < OPL; ++j) drift<TAN>(o[j], d.drift[0]);
   }
@@ -171,10 +172,11 @@ __device__ __forceinline__ bool in_window(double px, double py, double pz, const
 
 // ---------------------------------------------------------------------------
 // Run the orbits first + j*blockDim.x + threadIdx.x (j < OPL) over global
-// steps [k_begin, k_end).  FILT: test the window after every step.
+// steps [k_begin, k_end).  FILT: test the window after every step.  `tab` is
+// the block's LDS copy of the sine/cosine table (filled by the caller).
 // ---------------------------------------------------------------------------
 template <int FORM, bool TAN, int OPL, int UNR, bool FILT = false, bool WINV = false>
-__device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first) {
+__device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first, const double2 *__restrict__ tab) {
   int64_t n[OPL];
   bool act[OPL];
 #pragma unroll
@@ -237,7 +239,7 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first) {
   const int64_t mask = d.renorm_mask;
 #pragma unroll UNR
   for (int64_t k = k0; k < k1; ++k) {
-    map_step<FORM, TAN, OPL>(o, d);
+    map_step<FORM, TAN, OPL>(o, d, tab);
 #pragma unroll
     for (int j = 0; j < OPL; ++j) accum_j(o[j]);
     if (FILT) {
@@ -358,8 +360,10 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first) {
 
 template <int FORM, bool TAN, int OPL, int UNR, bool FILT = false, bool WINV = false>
 __global__ __launch_bounds__(256) void k_fwd(FwdDesc d) {
+  __shared__ double2 s_tab[AW_TAB_N];
+  load_sincos_table(s_tab);
   const int64_t first = (int64_t)blockIdx.x * blockDim.x * OPL;
-  run_orbits<FORM, TAN, OPL, UNR, FILT, WINV>(d, first);
+  run_orbits<FORM, TAN, OPL, UNR, FILT, WINV>(d, first, s_tab);
 }
 
 // Persistent batched propagation: each workgroup takes (ensemble, tile)
@@ -369,6 +373,8 @@ __global__ __launch_bounds__(256) void k_fwd_persist(const FwdDesc *__restrict__
                                                      const WorkItem *__restrict__ items,
                                                      int32_t n_items, uint32_t *head) {
   __shared__ int32_t s_item;
+  __shared__ double2 s_tab[AW_TAB_N];
+  load_sincos_table(s_tab);
   for (;;) {
     if (threadIdx.x == 0) s_item = (int32_t)atomicAdd(head, 1u);
     __syncthreads();
@@ -377,7 +383,7 @@ __global__ __launch_bounds__(256) void k_fwd_persist(const FwdDesc *__restrict__
     if (it >= n_items) break;
     const int32_t e = __builtin_amdgcn_readfirstlane(items[it].ens);
     const int64_t first = items[it].first;
-    run_orbits<FORM, TAN, OPL, 1>(descs[e], first);
+    run_orbits<FORM, TAN, OPL, 1>(descs[e], first, s_tab);
   }
 }
 
@@ -504,9 +510,9 @@ void step_op_counts(int form, bool tan, int64_t *fma, int64_t *mul, int64_t *add
   case 7: nk = 7; nd = 8; break;
   default: break;
   }
-  const int kf = tan ? KickOps<true>::fma : KickOps<false>::fma;
-  const int km = tan ? KickOps<true>::mul : KickOps<false>::mul;
-  const int ka = tan ? KickOps<true>::add : KickOps<false>::add;
+  const int kf = tan ? KickTabOps<true>::fma : KickTabOps<false>::fma;
+  const int km = tan ? KickTabOps<true>::mul : KickTabOps<false>::mul;
+  const int ka = tan ? KickTabOps<true>::add : KickTabOps<false>::add;
   const int df = tan ? DriftOps<true>::fma : DriftOps<false>::fma;
   *fma = (int64_t)nk * kf + (int64_t)nd * df + 3;  // + 3 fma of the J accumulator
   *mul = (int64_t)nk * km;

@@ -150,17 +150,22 @@ def test_ftle_grad_workspace_and_validation():
 
 def test_step_op_counts_match_the_stage_structure():
     """Per map step: 9 kicks (3 sincos each) and 10 drifts for the 6th-order
-    map; the counts are those of the kernel's formulas (one sincos = 19 fma,
-    2 mul, 1 add)."""
+    triple jump, 7 and 8 for Y6; the counts are those of the kernel's formulas
+    (one table-driven sincos = 11 fma, 4 mul, 1 add; the rest of a kick 3 fma
+    and 7 mul, plus 10 fma and 7 mul for the tangent; a drift 3 fma, 6 with the
+    tangent; the J accumulator 3 fma and 3 subtractions)."""
     from paper_1107_4107_amd import step_op_counts
+    sc_f, sc_m, sc_a = 11, 4, 1
+    kick_t = (3 * sc_f + 3 + 10, 3 * sc_m + 7 + 7, 3 * sc_a)
+    kick_n = (3 * sc_f + 3, 3 * sc_m + 7, 3 * sc_a)
     f, m, a = step_op_counts("s6", True)
-    assert (f, m, a) == (9 * (57 + 3 + 10) + 10 * 6 + 3, 9 * (6 + 7 + 7), 9 * 3 + 3)
+    assert (f, m, a) == (9 * kick_t[0] + 10 * 6 + 3, 9 * kick_t[1], 9 * kick_t[2] + 3)
     f, m, a = step_op_counts("y6", True)   # 7 kicks, 8 drifts
-    assert (f, m, a) == (7 * (57 + 3 + 10) + 8 * 6 + 3, 7 * (6 + 7 + 7), 7 * 3 + 3)
+    assert (f, m, a) == (7 * kick_t[0] + 8 * 6 + 3, 7 * kick_t[1], 7 * kick_t[2] + 3)
     f1, m1, a1 = step_op_counts("stdmap", True)
-    assert (f1, m1, a1) == ((57 + 3 + 10) + 6 + 3, 6 + 7 + 7, 3 + 3)
+    assert (f1, m1, a1) == (kick_t[0] + 6 + 3, kick_t[1], kick_t[2] + 3)
     f0, m0, a0 = step_op_counts("s6", False)
-    assert (f0, m0, a0) == (9 * (57 + 3) + 10 * 3 + 3, 9 * (6 + 7), 9 * 3 + 3)
+    assert (f0, m0, a0) == (9 * kick_n[0] + 10 * 3 + 3, 9 * kick_n[1], 9 * kick_n[2] + 3)
 
 
 def test_y6_weights_agree_between_the_two_derivations():
