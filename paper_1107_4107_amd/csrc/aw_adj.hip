@@ -26,18 +26,18 @@
 namespace aw {
 
 template <int FORM>
-__device__ __forceinline__ void adj_step_fwd(Orbit &o, const AdjDesc &d) {
+__device__ __forceinline__ void adj_step_fwd(Orbit &o, const AdjDesc &d, const double2 *__restrict__ tab) {
   using F = FormPattern<FORM>;
   constexpr int NK = F::NK;
   if constexpr (F::LEAD) {
 #pragma unroll
     for (int i = 0; i < NK; ++i) {
       drift<false>(o, d.drift[F::drift_idx[i]]);
-      kick<false>(o, d.ka2[F::kick_idx[i]], d.ka4[F::kick_idx[i]]);
+      kick_tab<false>(o, d.ka2[F::kick_idx[i]], d.ka4[F::kick_idx[i]], tab);
     }
     drift<false>(o, d.drift[F::drift_idx[NK]]);
   } else {
-    kick<false>(o, d.ka2[0], d.ka4[0]);
+    kick_tab<false>(o, d.ka2[0], d.ka4[0], tab);
     drift<false>(o, d.drift[0]);
   }
 }
@@ -57,12 +57,12 @@ __device__ __forceinline__ void rev_drift(Orbit &o, Adjoint &a, double t) {
 }
 
 // Undo K(t) on the state and apply its transpose to the adjoint.
-// a2 = 2 t eps, a4 = 4 t eps, w2 = 2 t, w4 = 4 t.
+// a2 = 2 t eps, a4 = 4 t eps, w2 = 2 t, w4 = 4 t.  Sines and cosines from the
+// same table as the forward kick, so the undone kick matches it.
 __device__ __forceinline__ void rev_kick(Orbit &o, Adjoint &a, double a2, double a4, double w2,
-                                         double w4) {
-  const SinCos X = sincos_red(o.x), Y = sincos_red(o.y), Z = sincos_red(o.z);
-  const uint32_t sg = (X.par ^ Y.par) << 31;
-  const double cx = flip(X.c, sg), sx = flip(X.s, sg);
+                                         double w4, const double2 *__restrict__ tab) {
+  const SinCosT X = sincos_tab(o.x, tab), Y = sincos_tab(o.y, tab), Z = sincos_tab(o.z, tab);
+  const double cx = X.c, sx = X.s;
   const double cy = Y.c, sy = Y.s;
   const double cz2 = Z.c * Z.c;
   const double czsz = Z.c * Z.s;
@@ -92,7 +92,7 @@ __device__ __forceinline__ void rev_kick(Orbit &o, Adjoint &a, double a2, double
 }
 
 template <int FORM>
-__device__ __forceinline__ void adj_step_rev(Orbit &o, Adjoint &a, const AdjDesc &d) {
+__device__ __forceinline__ void adj_step_rev(Orbit &o, Adjoint &a, const AdjDesc &d, const double2 *__restrict__ tab) {
   using F = FormPattern<FORM>;
   constexpr int NK = F::NK;
   if constexpr (F::LEAD) {
@@ -100,12 +100,12 @@ __device__ __forceinline__ void adj_step_rev(Orbit &o, Adjoint &a, const AdjDesc
 #pragma unroll
     for (int i = NK - 1; i >= 0; --i) {
       const int u = F::kick_idx[i];
-      rev_kick(o, a, d.ka2[u], d.ka4[u], d.kw2[u], d.kw4[u]);
+      rev_kick(o, a, d.ka2[u], d.ka4[u], d.kw2[u], d.kw4[u], tab);
       rev_drift(o, a, d.drift[F::drift_idx[i]]);
     }
   } else {
     rev_drift(o, a, d.drift[0]);
-    rev_kick(o, a, d.ka2[0], d.ka4[0], d.kw2[0], d.kw4[0]);
+    rev_kick(o, a, d.ka2[0], d.ka4[0], d.kw2[0], d.kw4[0], tab);
   }
 }
 
@@ -121,6 +121,8 @@ __device__ __forceinline__ void store6(double *p, int64_t N, int64_t n, const Or
 
 template <int FORM>
 __global__ __launch_bounds__(256) void k_adj_fwd(AdjDesc d) {
+  __shared__ double2 s_tab[AW_TAB_N];
+  load_sincos_table(s_tab);
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= d.N) return;
   Orbit o;
@@ -132,7 +134,7 @@ __global__ __launch_bounds__(256) void k_adj_fwd(AdjDesc d) {
     const int64_t g0 = s * d.ckpt;
     const int64_t g1 = g0 + d.ckpt < d.T ? g0 + d.ckpt : d.T;
     for (int64_t g = g0; g < g1; ++g) {
-      adj_step_fwd<FORM>(o, d);
+      adj_step_fwd<FORM>(o, d, s_tab);
       accum_j(o);
     }
   }
@@ -141,6 +143,8 @@ __global__ __launch_bounds__(256) void k_adj_fwd(AdjDesc d) {
 
 template <int FORM>
 __global__ __launch_bounds__(256) void k_adj_bwd(AdjDesc d) {
+  __shared__ double2 s_tab[AW_TAB_N];
+  load_sincos_table(s_tab);
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= d.N) return;
   const int64_t N = d.N;
@@ -157,7 +161,7 @@ __global__ __launch_bounds__(256) void k_adj_bwd(AdjDesc d) {
     const int64_t g1 = g0 + d.ckpt < d.T ? g0 + d.ckpt : d.T;
     load6(d.ckpts + s * 6 * N, N, n, o);
     for (int64_t g = g0; g < g1; ++g) {
-      adj_step_fwd<FORM>(o, d);
+      adj_step_fwd<FORM>(o, d, s_tab);
       store6(d.steps + (g - g0) * 6 * N, N, n, o);
     }
     for (int64_t g = g1 - 1; g >= g0; --g) {
@@ -167,7 +171,7 @@ __global__ __launch_bounds__(256) void k_adj_bwd(AdjDesc d) {
       a.pyb = __builtin_fma(c, ey, a.pyb);
       a.pzb = __builtin_fma(c, ez, a.pzb);
       sx += ex; sy += ey; sz += ez;
-      adj_step_rev<FORM>(o, a, d);
+      adj_step_rev<FORM>(o, a, d, s_tab);
     }
   }
   d.gic[0 * N + n] = a.xb;

@@ -44,18 +44,18 @@ constexpr double LN2_D = 0.693147180559945309417232121458176568;
 constexpr int64_t RESCALE_MASK = 7;  // rescale after steps k with (k + 1) % 8 == 0
 
 template <int FORM>
-__device__ __forceinline__ void tan_step(Orbit &o, const AdjDesc &d) {
+__device__ __forceinline__ void tan_step(Orbit &o, const AdjDesc &d, const double2 *__restrict__ tab) {
   using F = FormPattern<FORM>;
   constexpr int NK = F::NK;
   if constexpr (F::LEAD) {
 #pragma unroll
     for (int i = 0; i < NK; ++i) {
       drift<true>(o, d.drift[F::drift_idx[i]]);
-      kick<true>(o, d.ka2[F::kick_idx[i]], d.ka4[F::kick_idx[i]]);
+      kick_tab<true>(o, d.ka2[F::kick_idx[i]], d.ka4[F::kick_idx[i]], tab);
     }
     drift<true>(o, d.drift[F::drift_idx[NK]]);
   } else {
-    kick<true>(o, d.ka2[0], d.ka4[0]);
+    kick_tab<true>(o, d.ka2[0], d.ka4[0], tab);
     drift<true>(o, d.drift[0]);
   }
 }
@@ -83,18 +83,15 @@ __device__ __forceinline__ void rev_drift2(Orbit &o, Adjoint2 &a, double t) {
 }
 
 // Undo K(t) and apply its transpose.  a2 = 2 t eps, a4 = 4 t eps, w2 = 2 t,
-// w4 = 4 t.  Signs as in the forward kick: with sigma = (-1)^(qx+qy) folded
-// into the x factors, every first, second and third derivative of Hp
-// carries exactly one x factor and one y factor and even powers of the z
-// factors, so the reduced-angle sines and cosines serve directly.
+// w4 = 4 t.  Sines and cosines from the same table as the forward kick.
 //   t eps Hp_xxx = t eps Hp_xyy = e1 sx cy     t eps Hp_xxy = t eps Hp_yyy = e1 cx sy
 //   t eps Hp_xxz = t eps Hp_yyz = e2 cx cy     t eps Hp_xyz = -e2 sx sy
 //   t eps Hp_xzz = e3 sx cy   t eps Hp_yzz = e3 cx sy   t eps Hp_zzz = 4 e2 cx cy
 // with e1 = 2 t eps cz^2, e2 = 4 t eps cz sz, e3 = 4 t eps (cz^2 - sz^2).
-__device__ __forceinline__ void rev_kick2(Orbit &o, Adjoint2 &a, double a2, double a4, double w2, double w4) {
-  const SinCos X = sincos_red(o.x), Y = sincos_red(o.y), Z = sincos_red(o.z);
-  const uint32_t sg = (X.par ^ Y.par) << 31;
-  const double cx = flip(X.c, sg), sx = flip(X.s, sg);
+__device__ __forceinline__ void rev_kick2(Orbit &o, Adjoint2 &a, double a2, double a4, double w2, double w4,
+                                          const double2 *__restrict__ tab) {
+  const SinCosT X = sincos_tab(o.x, tab), Y = sincos_tab(o.y, tab), Z = sincos_tab(o.z, tab);
+  const double cx = X.c, sx = X.s;
   const double cy = Y.c, sy = Y.s;
   const double cz2 = Z.c * Z.c;
   const double czsz = Z.c * Z.s;
@@ -175,7 +172,7 @@ __device__ __forceinline__ void rev_kick2(Orbit &o, Adjoint2 &a, double a2, doub
 }
 
 template <int FORM>
-__device__ __forceinline__ void rev_tan_step(Orbit &o, Adjoint2 &a, const AdjDesc &d) {
+__device__ __forceinline__ void rev_tan_step(Orbit &o, Adjoint2 &a, const AdjDesc &d, const double2 *__restrict__ tab) {
   using F = FormPattern<FORM>;
   constexpr int NK = F::NK;
   if constexpr (F::LEAD) {
@@ -183,12 +180,12 @@ __device__ __forceinline__ void rev_tan_step(Orbit &o, Adjoint2 &a, const AdjDes
 #pragma unroll
     for (int i = NK - 1; i >= 0; --i) {
       const int u = F::kick_idx[i];
-      rev_kick2(o, a, d.ka2[u], d.ka4[u], d.kw2[u], d.kw4[u]);
+      rev_kick2(o, a, d.ka2[u], d.ka4[u], d.kw2[u], d.kw4[u], tab);
       rev_drift2(o, a, d.drift[F::drift_idx[i]]);
     }
   } else {
     rev_drift2(o, a, d.drift[0]);
-    rev_kick2(o, a, d.ka2[0], d.ka4[0], d.kw2[0], d.kw4[0]);
+    rev_kick2(o, a, d.ka2[0], d.ka4[0], d.kw2[0], d.kw4[0], tab);
   }
 }
 
@@ -226,6 +223,8 @@ __device__ __forceinline__ int rescale_exponent(const Orbit &o) {
 
 template <int FORM>
 __global__ __launch_bounds__(256) void k_ftle_fwd(FtleDesc d) {
+  __shared__ double2 s_tab[AW_TAB_N];
+  load_sincos_table(s_tab);
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= d.N) return;
   const int64_t N = d.N;
@@ -243,7 +242,7 @@ __global__ __launch_bounds__(256) void k_ftle_fwd(FtleDesc d) {
     const int64_t g0 = s * d.ckpt;
     const int64_t g1 = g0 + d.ckpt < d.T ? g0 + d.ckpt : d.T;
     for (int64_t g = g0; g < g1; ++g) {
-      tan_step<FORM>(o, d);
+      tan_step<FORM>(o, d, s_tab);
       if (((g + 1) & RESCALE_MASK) == 0) renorm(o);
     }
   }
@@ -257,6 +256,8 @@ __global__ __launch_bounds__(256) void k_ftle_fwd(FtleDesc d) {
 
 template <int FORM>
 __global__ __launch_bounds__(256) void k_ftle_bwd(FtleDesc d) {
+  __shared__ double2 s_tab[AW_TAB_N];
+  load_sincos_table(s_tab);
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= d.N) return;
   const int64_t N = d.N;
@@ -271,7 +272,7 @@ __global__ __launch_bounds__(256) void k_ftle_bwd(FtleDesc d) {
     const int64_t g1 = g0 + d.ckpt < d.T ? g0 + d.ckpt : d.T;
     load12(d.ckpts + s * 12 * N, N, n, o);
     for (int64_t g = g0; g < g1; ++g) {
-      tan_step<FORM>(o, d);
+      tan_step<FORM>(o, d, s_tab);
       store12(d.steps + (g - g0) * 12 * N, N, n, o);
       if (((g + 1) & RESCALE_MASK) == 0) renorm(o);
     }
@@ -291,7 +292,7 @@ __global__ __launch_bounds__(256) void k_ftle_bwd(FtleDesc d) {
         a.dpyb = __builtin_amdgcn_ldexp(a.dpyb, -k);
         a.dpzb = __builtin_amdgcn_ldexp(a.dpzb, -k);
       }
-      rev_tan_step<FORM>(o, a, d);
+      rev_tan_step<FORM>(o, a, d, s_tab);
     }
   }
   d.gic[0 * N + n] = a.xb;
