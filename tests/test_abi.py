@@ -188,3 +188,14 @@ def test_ensemble_size():
     assert lib.aw_ensemble_size(ctypes.byref(_ens(nx=7, ny=5))) == 35
     assert lib.aw_ensemble_size(ctypes.byref(_ens(ic_kind="box", n_orbits=123))) == 123
     assert lib.aw_ensemble_size(ctypes.byref(_ens(nx=0))) == -1
+
+
+@pytest.mark.parametrize("gen,header", [("gen_sincos.py", "aw_sincos_coef.h"), ("gen_sincos_tab.py", "aw_sincos_tab.h")])
+def test_generated_headers_are_current(gen, header):
+    """The committed constant headers of the device sine/cosine are exactly
+    what their generators write (the generators also replay the device
+    arithmetic against mpmath and record the error in the header)."""
+    csrc = os.path.join(ROOT, "paper_1107_4107_amd", "csrc")
+    out = subprocess.run(["python3", os.path.join(csrc, gen)], capture_output=True, text=True, timeout=300,
+                         cwd=csrc, check=True).stdout
+    assert out == open(os.path.join(csrc, header)).read()
