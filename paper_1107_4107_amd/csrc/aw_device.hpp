@@ -133,48 +133,14 @@ struct Orbit {
   int kexp;                            // tangent scale exponent (|w| true = |w| 2^kexp)
 };
 
-// Kick with weight a2 = 2 t eps, a4 = 4 t eps.  With sigma = (-1)^(qx+qy)
-// folded into the x factors, every force and Hessian term of eq. 2 carries
-// exactly one x factor and one y factor, and the z factors enter squared, so
-// the reduced-angle sines and cosines can be used directly.
-template <bool TAN>
-__device__ __forceinline__ void kick(Orbit &o, double a2, double a4) {
-  const SinCos X = sincos_red(o.x), Y = sincos_red(o.y), Z = sincos_red(o.z);
-  const uint32_t sg = (X.par ^ Y.par) << 31;
-  const double cx = flip(X.c, sg), sx = flip(X.s, sg);
-  const double cy = Y.c, sy = Y.s;
-  const double cz2 = Z.c * Z.c;
-  const double czsz = Z.c * Z.s;
-  const double e1 = a2 * cz2;      // 2 t eps cz^2
-  const double e2 = a4 * czsz;     // 4 t eps cz sz
-  const double psc = sx * cy, pcs = cx * sy, pcc = cx * cy;
-  if (TAN) {
-    const double c2z = __builtin_fma(-Z.s, Z.s, cz2);   // cz^2 - sz^2
-    const double e3 = a4 * c2z;
-    const double pss = sx * sy;
-    const double mxx = e1 * pcc;    // -t eps Hxx = -t eps Hyy
-    const double nxy = e1 * pss;    //  t eps Hxy
-    const double nxz = e2 * psc;    //  t eps Hxz
-    const double nyz = e2 * pcs;    //  t eps Hyz
-    const double mzz = e3 * pcc;    // -t eps Hzz
-    const double dx = o.dx, dy = o.dy, dz = o.dz;
-    o.dpx = __builtin_fma(mxx, dx, o.dpx);
-    o.dpx = __builtin_fma(-nxy, dy, o.dpx);
-    o.dpx = __builtin_fma(-nxz, dz, o.dpx);
-    o.dpy = __builtin_fma(-nxy, dx, o.dpy);
-    o.dpy = __builtin_fma(mxx, dy, o.dpy);
-    o.dpy = __builtin_fma(-nyz, dz, o.dpy);
-    o.dpz = __builtin_fma(-nxz, dx, o.dpz);
-    o.dpz = __builtin_fma(-nyz, dy, o.dpz);
-    o.dpz = __builtin_fma(mzz, dz, o.dpz);
-  }
-  o.px = __builtin_fma(e1, psc, o.px);   // -t eps dHp/dx
-  o.py = __builtin_fma(e1, pcs, o.py);   // -t eps dHp/dy
-  o.pz = __builtin_fma(e2, pcc, o.pz);   // -t eps dHp/dz
-}
-
-// The same kick with the table-driven sines and cosines (no sign folding:
-// they are the true values).  Same formulas, same order of operations.
+// Kick with weight a2 = 2 t eps, a4 = 4 t eps, sines and cosines from the
+// block's LDS table (true values: no sign folding).  Every force and Hessian
+// term of eq. 2 is a product of one x factor, one y factor and z factors:
+//   e1 = 2 t eps cz^2, e2 = 4 t eps cz sz, e3 = 4 t eps (cz^2 - sz^2),
+//   P  += (e1 sx cy, e1 cx sy, e2 cx cy)                 (= -t eps grad Hp)
+//   dP += M dX, M = [[e1 cx cy, -e1 sx sy, -e2 sx cy],
+//                    [-e1 sx sy, e1 cx cy, -e2 cx sy],
+//                    [-e2 sx cy, -e2 cx sy, e3 cx cy]]     (= -t eps Hess Hp)
 template <bool TAN>
 __device__ __forceinline__ void kick_tab(Orbit &o, double a2, double a4, const double2 *__restrict__ tab) {
   const SinCosT X = sincos_tab(o.x, tab), Y = sincos_tab(o.y, tab), Z = sincos_tab(o.z, tab);
@@ -223,11 +189,6 @@ __device__ __forceinline__ void drift(Orbit &o, double t) {
 }
 
 // Op counts of kick/drift (roofline accounting).
-template <bool TAN> struct KickOps {
-  static constexpr int fma = 3 * SC_FMA + 3 + (TAN ? 1 + 9 : 0);
-  static constexpr int mul = 3 * SC_MUL + 7 + (TAN ? 7 : 0);
-  static constexpr int add = 3 * SC_ADD;
-};
 template <bool TAN> struct KickTabOps {
   static constexpr int fma = 3 * SCT_FMA + 3 + (TAN ? 1 + 9 : 0);
   static constexpr int mul = 3 * SCT_MUL + 7 + (TAN ? 7 : 0);
