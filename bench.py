@@ -186,8 +186,17 @@ def valu_issue(ens, kernel_ms, workload, steps):
         return None
     achieved = per_step / 64.0 * ens.size * steps / (kernel_ms * 1e-3)
     peak = 1024 * 2.4e9 / 4
+    flop = sum(k * v for k, v in zip((2, 1, 1), _ops(ens)))
     return {"valu_insts_per_map_step": per_step, "achieved": achieved, "peak": peak,
-            "unit": "wave-instructions/s", "frac": achieved / peak}
+            "unit": "wave-instructions/s", "frac": achieved / peak,
+            "note": f"the kernel is bound by VALU issue: {per_step:.0f} wave-instructions per map step carry "
+                    f"{flop} FP64 flops ({flop / per_step:.2f} per instruction), which caps the FP64 fraction "
+                    f"at {flop / per_step / 2:.0%} of the FMA peak even at full issue"}
+
+
+def _ops(ens):
+    import paper_1107_4107_amd as aw
+    return aw.step_op_counts(ens.map_form, ens.tangent)
 
 
 def base_record(value, steps, warmup, ms_per_step, dtype="f64"):
