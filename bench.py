@@ -307,7 +307,9 @@ def run_adjoint(args, aw, wl, torch):
     t_fwd = timed(lambda: aw.map_ensemble(fwd, ic, want_class=False))
     t_fwd_tan = timed(lambda: aw.map_ensemble(fwd_t, ic, want_class=False))
     t_grad = timed(lambda: aw.indicator_grad(fwd, ic, ckpt_every=wl.C4_CKPT, workspace=ws))
-    log(f"forward {t_fwd:.3f} s, forward+tangent {t_fwd_tan:.3f} s, gradient {t_grad:.3f} s")
+    t_grad_rev = timed(lambda: aw.indicator_grad(fwd, ic, ckpt_every=wl.C4_CKPT, workspace=ws, reversible=True))
+    log(f"forward {t_fwd:.3f} s, forward+tangent {t_fwd_tan:.3f} s, gradient {t_grad:.3f} s, "
+        f"reversible gradient {t_grad_rev:.3f} s")
     del ws
     # Gradient of the tangent growth L (second-order adjoint) on the same slice.
     _, w0 = aw.generate_ic(fwd_t, ic)
@@ -324,6 +326,8 @@ def run_adjoint(args, aw, wl, torch):
     rec["gradient_s"] = t_grad
     rec["gradient_over_forward"] = t_grad / t_fwd
     rec["gradient_over_forward_tangent"] = t_grad / t_fwd_tan
+    rec["reversible_gradient_s"] = t_grad_rev
+    rec["reversible_gradient_over_forward"] = t_grad_rev / t_fwd
     rec["ftle_gradient_s"] = t_fgrad
     rec["ftle_gradient_over_forward_tangent"] = t_fgrad / t_fwd_tan
     return rec, None

@@ -270,12 +270,29 @@ aw_status aw_vdir_keys(int64_t N, const double *V_dev, double *phi_dev, double *
  *   grad_J_dev [N]: upstream dL/dJ_n (NULL = all ones)
  *   J_out_dev [N] or NULL; grad_ic_dev [6][N]: dL/d(initial x..pz);
  *   grad_eps_dev [N]: per-orbit dL/deps contributions (sum them for the scalar).
- * Requires a caller workspace of aw_indicator_grad_workspace() bytes. */
+ * Requires a caller workspace of aw_indicator_grad_workspace() bytes: the
+ * n_seg = ceil(T / ckpt_every) checkpoints, the final state and the step
+ * states of one segment, 6 doubles per orbit each. */
 aw_status aw_indicator_grad_workspace(const aw_ensemble *ens, int64_t ckpt_every, size_t *bytes);
 aw_status aw_indicator_grad(const aw_ensemble *ens, const double *ic_dev, const double *grad_J_dev,
                             int64_t ckpt_every, double *J_out_dev, double *grad_ic_dev,
                             double *grad_eps_dev, void *workspace_dev, size_t ws_bytes,
                             const aw_tuning *tuning, void *stream);
+
+/* The same gradient by a reversible sweep: the forward pass is the same, but
+ * the backward pass neither recomputes the segments nor stores step states.
+ * It sweeps each segment back from the exact state at its end (the next
+ * checkpoint, or the final state), undoing the steps one after the other by
+ * inverting their stages.  This relies on the map being a composition of
+ * invertible stages; the reconstructed states carry the rounding of the
+ * inversion, which restarts from an exact state at every checkpoint.  The
+ * result agrees with aw_indicator_grad to rounding, not bitwise.  Same
+ * arguments and workspace query; only the checkpoints and the final state
+ * are used. */
+aw_status aw_indicator_grad_reversible(const aw_ensemble *ens, const double *ic_dev, const double *grad_J_dev,
+                                       int64_t ckpt_every, double *J_out_dev, double *grad_ic_dev,
+                                       double *grad_eps_dev, void *workspace_dev, size_t ws_bytes,
+                                       const aw_tuning *tuning, void *stream);
 
 /* Gradient of the tangent-growth indicator L = ln(|w_T| / |w_0|) -- the
  * finite-time Lyapunov exponent that the conclusions name as the indicator to

@@ -315,8 +315,10 @@ def grad_workspace_bytes(ens: Ensemble, ckpt_every: int) -> int:
 
 def indicator_grad(ens: Ensemble, ic: torch.Tensor, grad_J: Optional[torch.Tensor] = None,
                    ckpt_every: int = 100, tuning: Optional[Tuning] = None,
-                   workspace: Optional[torch.Tensor] = None):
-    """Adjoint gradient of J.  Returns (J[N], grad_ic[6, N], grad_eps[N])."""
+                   workspace: Optional[torch.Tensor] = None, reversible: bool = False):
+    """Adjoint gradient of J.  Returns (J[N], grad_ic[6, N], grad_eps[N]).
+    reversible=True sweeps each segment back by inverting the steps instead
+    of recomputing and storing them (aw_indicator_grad_reversible)."""
     if ens.ic_kind != "explicit":
         raise ValueError("indicator_grad needs an explicit ensemble")
     N = ens.size
@@ -329,10 +331,9 @@ def indicator_grad(ens: Ensemble, ic: torch.Tensor, grad_J: Optional[torch.Tenso
     J = torch.empty((N,), dtype=torch.float64, device=ic.device)
     gic = torch.empty((6, N), dtype=torch.float64, device=ic.device)
     geps = torch.empty((N,), dtype=torch.float64, device=ic.device)
-    _abi.check(_lib().aw_indicator_grad(ctypes.byref(ens.to_c()), _p(ic), _p(grad_J), int(ckpt_every),
-                                        _p(J), _p(gic), _p(geps), _p(workspace),
-                                        workspace.numel() * workspace.element_size(), _tuning_ptr(tuning),
-                                        _stream()))
+    fn = _lib().aw_indicator_grad_reversible if reversible else _lib().aw_indicator_grad
+    _abi.check(fn(ctypes.byref(ens.to_c()), _p(ic), _p(grad_J), int(ckpt_every), _p(J), _p(gic), _p(geps),
+                  _p(workspace), workspace.numel() * workspace.element_size(), _tuning_ptr(tuning), _stream()))
     return J, gic, geps
 
 

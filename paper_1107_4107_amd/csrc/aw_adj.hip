@@ -17,6 +17,13 @@
 // -(2 gJ / T) sum_k (P_k - P_0) to the initial-momentum gradient.
 // Each lane only reads back what it wrote itself, so no synchronisation
 // between lanes is needed.
+//
+// Reversible sweep (k_adj_bwd_rev): the same reverse pass without the
+// recompute and without storing step states.  Each segment is swept back from
+// the exact state at its end (the next checkpoint; the final state for the
+// last segment), undoing the steps one after the other by inverting their
+// stages.  The reconstructed states carry the rounding of the inversion,
+// which restarts from an exact state at every checkpoint.
 #include <hip/hip_runtime.h>
 
 #include "aw_device.hpp"
@@ -138,7 +145,46 @@ __global__ __launch_bounds__(256) void k_adj_fwd(AdjDesc d) {
       accum_j(o);
     }
   }
+  store6(d.ckpts + d.n_seg * 6 * d.N, d.N, n, o);   // the final state
   if (d.J) d.J[n] = o.jsum / (double)d.T;
+}
+
+template <int FORM>
+__global__ __launch_bounds__(256) void k_adj_bwd_rev(AdjDesc d) {
+  __shared__ double2 s_tab[AW_TAB_N];
+  load_sincos_table(s_tab);
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= d.N) return;
+  const int64_t N = d.N;
+  const double p0x = d.ic[3 * N + n], p0y = d.ic[4 * N + n], p0z = d.ic[5 * N + n];
+  const double c = 2.0 * (d.gJ ? d.gJ[n] : 1.0) / (double)d.T;
+  Adjoint a{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double sx = 0.0, sy = 0.0, sz = 0.0;  // sum_k (P_k - P_0)
+  Orbit o;
+  o.p0x = p0x; o.p0y = p0y; o.p0z = p0z;
+  o.jsum = 0.0;
+  o.kexp = 0;
+  o.dx = o.dy = o.dz = o.dpx = o.dpy = o.dpz = 0.0;
+  for (int64_t s = d.n_seg - 1; s >= 0; --s) {
+    const int64_t g0 = s * d.ckpt;
+    const int64_t g1 = g0 + d.ckpt < d.T ? g0 + d.ckpt : d.T;
+    load6(d.ckpts + (s + 1) * 6 * N, N, n, o);        // exact state after step g1 - 1
+    for (int64_t g = g1 - 1; g >= g0; --g) {
+      const double ex = o.px - p0x, ey = o.py - p0y, ez = o.pz - p0z;
+      a.pxb = __builtin_fma(c, ex, a.pxb);
+      a.pyb = __builtin_fma(c, ey, a.pyb);
+      a.pzb = __builtin_fma(c, ez, a.pzb);
+      sx += ex; sy += ey; sz += ez;
+      adj_step_rev<FORM>(o, a, d, s_tab);              // state now at the start of step g
+    }
+  }
+  d.gic[0 * N + n] = a.xb;
+  d.gic[1 * N + n] = a.yb;
+  d.gic[2 * N + n] = a.zb;
+  d.gic[3 * N + n] = __builtin_fma(-c, sx, a.pxb);
+  d.gic[4 * N + n] = __builtin_fma(-c, sy, a.pyb);
+  d.gic[5 * N + n] = __builtin_fma(-c, sz, a.pzb);
+  d.geps[n] = a.eb;
 }
 
 template <int FORM>
@@ -192,6 +238,20 @@ hipError_t launch_adj_forward(const AdjDesc &d, int form, const Tuning &t, hipSt
   case 4: hipLaunchKernelGGL(k_adj_fwd<4>, dim3(blocks), dim3(t.block), 0, s, d); break;
   case 6: hipLaunchKernelGGL(k_adj_fwd<6>, dim3(blocks), dim3(t.block), 0, s, d); break;
   case 7: hipLaunchKernelGGL(k_adj_fwd<7>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_backward_reversible(const AdjDesc &d, int form, const Tuning &t, hipStream_t s) {
+  if (d.N <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((d.N + t.block - 1) / t.block);
+  switch (form) {
+  case 1: hipLaunchKernelGGL(k_adj_bwd_rev<1>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  case 2: hipLaunchKernelGGL(k_adj_bwd_rev<2>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  case 4: hipLaunchKernelGGL(k_adj_bwd_rev<4>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  case 6: hipLaunchKernelGGL(k_adj_bwd_rev<6>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  case 7: hipLaunchKernelGGL(k_adj_bwd_rev<7>, dim3(blocks), dim3(t.block), 0, s, d); break;
   default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -771,17 +771,18 @@ aw_status aw_indicator_grad_workspace(const aw_ensemble *ens, int64_t ckpt_every
   if (N < 0) return fail(AW_EINVAL, "bad ensemble size");
   const int64_t ck = std::min(ckpt_every, ens->n_steps);
   const int64_t n_seg = (ens->n_steps + ck - 1) / ck;
-  *bytes = sizeof(double) * 6 * (size_t)N * (size_t)(n_seg + ck);
+  // n_seg checkpoints, the final state, and the step states of one segment
+  *bytes = sizeof(double) * 6 * (size_t)N * (size_t)(n_seg + 1 + ck);
   return AW_OK;
 }
 
-aw_status aw_indicator_grad(const aw_ensemble *ens, const double *ic_dev, const double *grad_J_dev,
-                            int64_t ckpt_every, double *J_out_dev, double *grad_ic_dev, double *grad_eps_dev,
-                            void *workspace_dev, size_t ws_bytes, const aw_tuning *tuning, void *stream) {
+// Validation and descriptor of the adjoint of J (both sweeps).
+static aw_status adj_setup(const aw_ensemble *ens, const double *ic_dev, const double *grad_J_dev, int64_t ckpt_every,
+                    double *J_out_dev, double *grad_ic_dev, double *grad_eps_dev, void *workspace_dev,
+                    size_t ws_bytes, const aw_tuning *tuning, const char *who, AdjDesc &d, Tuning &t) {
   aw_status st = check_ensemble(ens, ic_dev, 0);
   if (st != AW_OK) return st;
-  if (ens->ic_kind != AW_IC_EXPLICIT) return fail(AW_EINVAL, "aw_indicator_grad needs an EXPLICIT ensemble");
-  Tuning t;
+  if (ens->ic_kind != AW_IC_EXPLICIT) return fail(AW_EINVAL, "%s needs an EXPLICIT ensemble", who);
   if ((st = check_tuning(tuning, t)) != AW_OK) return st;
   size_t need = 0;
   if ((st = aw_indicator_grad_workspace(ens, ckpt_every, &need)) != AW_OK) return st;
@@ -789,7 +790,6 @@ aw_status aw_indicator_grad(const aw_ensemble *ens, const double *ic_dev, const 
   if (N > 0 && (!grad_ic_dev || !grad_eps_dev)) return fail(AW_EINVAL, "null gradient outputs");
   if (ws_bytes < need || (N > 0 && !workspace_dev))
     return fail(AW_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
-  AdjDesc d;
   std::memset(&d, 0, sizeof d);
   double tau[MAX_UNIQUE];
   (void)unique_weights(ens->map_form, ens->h, tau, d.drift);
@@ -810,12 +810,40 @@ aw_status aw_indicator_grad(const aw_ensemble *ens, const double *ic_dev, const 
   d.gic = grad_ic_dev;
   d.geps = grad_eps_dev;
   d.ckpts = (double *)workspace_dev;
-  d.steps = d.ckpts + (size_t)d.n_seg * 6 * (size_t)N;
+  d.steps = d.ckpts + (size_t)(d.n_seg + 1) * 6 * (size_t)N;
+  return AW_OK;
+}
+
+aw_status aw_indicator_grad(const aw_ensemble *ens, const double *ic_dev, const double *grad_J_dev,
+                            int64_t ckpt_every, double *J_out_dev, double *grad_ic_dev, double *grad_eps_dev,
+                            void *workspace_dev, size_t ws_bytes, const aw_tuning *tuning, void *stream) {
+  AdjDesc d;
+  Tuning t;
+  aw_status st = adj_setup(ens, ic_dev, grad_J_dev, ckpt_every, J_out_dev, grad_ic_dev, grad_eps_dev, workspace_dev,
+                           ws_bytes, tuning, "aw_indicator_grad", d, t);
+  if (st != AW_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = launch_adj_forward(d, ens->map_form, t, s);
   if (e != hipSuccess) return hip_fail(e, "adjoint forward launch");
   e = launch_adj_backward(d, ens->map_form, t, s);
   if (e != hipSuccess) return hip_fail(e, "adjoint backward launch");
+  return AW_OK;
+}
+
+aw_status aw_indicator_grad_reversible(const aw_ensemble *ens, const double *ic_dev, const double *grad_J_dev,
+                                       int64_t ckpt_every, double *J_out_dev, double *grad_ic_dev,
+                                       double *grad_eps_dev, void *workspace_dev, size_t ws_bytes,
+                                       const aw_tuning *tuning, void *stream) {
+  AdjDesc d;
+  Tuning t;
+  aw_status st = adj_setup(ens, ic_dev, grad_J_dev, ckpt_every, J_out_dev, grad_ic_dev, grad_eps_dev, workspace_dev,
+                           ws_bytes, tuning, "aw_indicator_grad_reversible", d, t);
+  if (st != AW_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_adj_forward(d, ens->map_form, t, s);
+  if (e != hipSuccess) return hip_fail(e, "adjoint forward launch");
+  e = launch_adj_backward_reversible(d, ens->map_form, t, s);
+  if (e != hipSuccess) return hip_fail(e, "adjoint reversible backward launch");
   return AW_OK;
 }
 

@@ -136,7 +136,7 @@ struct AdjDesc {
   double *J;              // [N] or null
   double *gic;            // [6][N]
   double *geps;           // [N]
-  double *ckpts;          // [n_seg][6][N]
+  double *ckpts;          // [n_seg + 1][6][N] (the last slot: the final state)
   double *steps;          // [ckpt][6][N] (per-segment step states)
 };
 

@@ -54,6 +54,7 @@ hipError_t launch_hist_reduce(int64_t N, const uint32_t *bins, const double *val
 // Adjoint.
 hipError_t launch_adj_forward(const AdjDesc &d, int form, const Tuning &t, hipStream_t s);
 hipError_t launch_adj_backward(const AdjDesc &d, int form, const Tuning &t, hipStream_t s);
+hipError_t launch_adj_backward_reversible(const AdjDesc &d, int form, const Tuning &t, hipStream_t s);
 
 // Gradient of the tangent-growth indicator L: the adjoint descriptor, whose
 // checkpoint and step buffers then hold 12 rows (state and tangent) per

@@ -116,8 +116,8 @@ def test_grad_workspace_size():
     e = _ens(ic_kind="explicit", n_orbits=1000, n_steps=10_000)
     nb = ctypes.c_size_t()
     assert lib.aw_indicator_grad_workspace(ctypes.byref(e), 100, ctypes.byref(nb)) == 0
-    # 100 checkpoints + 100 step states, 6 doubles per orbit each.
-    assert nb.value == 8 * 6 * 1000 * (100 + 100)
+    # 100 checkpoints + the final state + 100 step states, 6 doubles per orbit each.
+    assert nb.value == 8 * 6 * 1000 * (100 + 1 + 100)
     assert lib.aw_indicator_grad_workspace(ctypes.byref(e), 0, ctypes.byref(nb)) == _abi.AW_EINVAL
 
 

@@ -145,3 +145,44 @@ def test_gradient_slice_full_size(aw):
     assert_close(np_(J)[pick], Jo, 1e-9, floor=1e-300, what="J")
     g = np.vstack([np_(gic)[:, pick], np_(geps)[None, pick]])
     _grad_rel(g, dJo, 1e-9)
+
+
+@pytest.mark.parametrize("form,T,ck", [("s6", 500, 50), ("s6", 537, 100), ("stdmap", 800, 64), ("y6", 400, 37),
+                                       ("s6", 300, 1)])
+def test_reversible_adjoint_matches_forward_mode(aw, form, T, ck):
+    """The store-free sweep (segments swept back from the next checkpoint by
+    inverting the steps) against the oracle's forward mode, at the same 1e-9
+    bar, and against the recompute-and-store sweep to rounding."""
+    print_case("reversible adjoint", form, T, ck)
+    eps = 1e-2
+    ic = _regular_ics(64, 1, eps, T)
+    e = aw.Ensemble(eps=eps, n_steps=T, map_form=form, ic_kind="explicit", n_orbits=64, tangent=False)
+    J, gic, geps = aw.indicator_grad(e, tensor(ic), ckpt_every=ck, reversible=True)
+    Jo, dJo = oracle.J_grad_ensemble(form, eps, H, T, ic)
+    assert_close(np_(J), Jo, 1e-11, floor=1e-300, what="J")
+    g = np.vstack([np_(gic), np_(geps)[None, :]])
+    _grad_rel(g, dJo, 1e-9)
+    _, gic_s, geps_s = aw.indicator_grad(e, tensor(ic), ckpt_every=ck)
+    _grad_rel(g, np.vstack([np_(gic_s), np_(geps_s)[None, :]]), 1e-11)
+
+
+def test_reversible_gradient_slice_full_size(aw):
+    """The 512 x 512 slice, eps = 1e-2, T = 1e4, checkpoints every 100 steps,
+    store-free sweep: 64 regular orbits (seed 3) against the oracle (1e-9)."""
+    print_case("reversible gradient 512x512 T=1e4")
+    from paper_1107_4107_amd import workloads as wl
+    s = wl.c4()
+    N, T = s.nx * s.ny, s.n_steps
+    ic_all, _ = aw.generate_ic(s)
+    e = aw.Ensemble(eps=s.eps, n_steps=T, ic_kind="explicit", n_orbits=N, tangent=False)
+    J, gic, geps = aw.indicator_grad(e, ic_all, ckpt_every=wl.C4_CKPT, reversible=True)
+    rng = np.random.default_rng(3)
+    cand = np.sort(rng.choice(N, 160, replace=False))
+    ic_c = oracle.ic_grid2((3, 4), (0, 0), (2 * np.pi, 2 * np.pi), s.nx, s.ny, list(s.base), idx=cand)
+    out_c = oracle.ensemble("s6", s.eps, H, T, ic_c, oracle.w0(0, idx=cand))
+    pick = cand[out_c[2] < 1.5][:64]
+    ic = ic_c[:, out_c[2] < 1.5][:, :64]
+    Jo, dJo = oracle.J_grad_ensemble("s6", s.eps, H, T, ic)
+    assert_close(np_(J)[pick], Jo, 1e-9, floor=1e-300, what="J")
+    g = np.vstack([np_(gic)[:, pick], np_(geps)[None, pick]])
+    _grad_rel(g, dJo, 1e-9)
