@@ -315,7 +315,8 @@ def run_adjoint(args, aw, wl, torch):
     _, w0 = aw.generate_ic(fwd_t, ic)
     ws2 = torch.empty((aw.ftle_grad_workspace_bytes(fwd_t, wl.C4_CKPT),), dtype=torch.uint8, device="cuda")
     t_fgrad = timed(lambda: aw.ftle_grad(fwd_t, ic, w0, ckpt_every=wl.C4_CKPT, workspace=ws2))
-    log(f"FTLE gradient {t_fgrad:.3f} s")
+    t_fgrad_rev = timed(lambda: aw.ftle_grad(fwd_t, ic, w0, ckpt_every=wl.C4_CKPT, workspace=ws2, reversible=True))
+    log(f"FTLE gradient {t_fgrad:.3f} s, reversible {t_fgrad_rev:.3f} s")
     del ws2
     rec = base_record(N * T / t_grad, 3, 1, t_grad * 1e3)
     rec["metric"] = "orbit map-steps/sec through the adjoint (forward + checkpoints + reverse)"
@@ -330,6 +331,8 @@ def run_adjoint(args, aw, wl, torch):
     rec["reversible_gradient_over_forward"] = t_grad_rev / t_fwd
     rec["ftle_gradient_s"] = t_fgrad
     rec["ftle_gradient_over_forward_tangent"] = t_fgrad / t_fwd_tan
+    rec["reversible_ftle_gradient_s"] = t_fgrad_rev
+    rec["reversible_ftle_gradient_over_forward_tangent"] = t_fgrad_rev / t_fwd_tan
     return rec, None
 
 

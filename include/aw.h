@@ -311,13 +311,27 @@ aw_status aw_indicator_grad_reversible(const aw_ensemble *ens, const double *ic_
  * lambda = L/(T h) and chi = L/ln(1 + T h) scale the same gradients.  On
  * chaotic orbits the derivative grows like exp(lambda T h) and is only
  * meaningful where the trajectory is. Requires a caller workspace of
- * aw_ftle_grad_workspace() bytes (12 doubles per orbit per checkpoint and per
- * step of a segment). */
+ * aw_ftle_grad_workspace() bytes: 12 doubles per orbit per checkpoint, for
+ * the final state and per step of a segment, then one 16-bit rescale exponent
+ * per orbit per 8 steps. */
 aw_status aw_ftle_grad_workspace(const aw_ensemble *ens, int64_t ckpt_every, size_t *bytes);
 aw_status aw_ftle_grad(const aw_ensemble *ens, const double *ic_dev, const double *w0_dev,
                        const double *grad_L_dev, int64_t ckpt_every, double *L_out_dev,
                        double *grad_ic_dev, double *grad_eps_dev, void *workspace_dev, size_t ws_bytes,
                        const aw_tuning *tuning, void *stream);
+
+/* The same gradient by a reversible sweep: no segment recompute and no stored
+ * step states.  Each segment is swept back from the exact state at its end,
+ * inverting the stages of state and tangent step after step, and undoing
+ * every tangent rescale with the exponent the forward pass recorded.  The
+ * result agrees with aw_ftle_grad to rounding, not bitwise: the reconstructed
+ * states carry the inversion's rounding, and on chaotic orbits the tangent's
+ * reconstruction error grows like exp(2 lambda h ckpt_every) within a
+ * segment.  Same arguments and workspace query. */
+aw_status aw_ftle_grad_reversible(const aw_ensemble *ens, const double *ic_dev, const double *w0_dev,
+                                  const double *grad_L_dev, int64_t ckpt_every, double *L_out_dev,
+                                  double *grad_ic_dev, double *grad_eps_dev, void *workspace_dev, size_t ws_bytes,
+                                  const aw_tuning *tuning, void *stream);
 
 /* A captured HIP graph of aw_indicator_image over n_ens ensembles (one
  * persistent launch plus the reductions).  Buffers are bound at creation;

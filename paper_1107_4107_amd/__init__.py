@@ -374,10 +374,11 @@ def ftle_grad_workspace_bytes(ens: Ensemble, ckpt_every: int) -> int:
 
 def ftle_grad(ens: Ensemble, ic: torch.Tensor, w0: Optional[torch.Tensor] = None,
               grad_L: Optional[torch.Tensor] = None, ckpt_every: int = 100, tuning: Optional[Tuning] = None,
-              workspace: Optional[torch.Tensor] = None):
+              workspace: Optional[torch.Tensor] = None, reversible: bool = False):
     """Second-order adjoint gradient of the tangent growth L = ln(|w_T|/|w_0|).
     w0 defaults to the ensemble's seeded tangent start (the one map_ensemble
-    uses).  Returns (L[N], grad_ic[6, N], grad_eps[N])."""
+    uses).  reversible=True sweeps each segment back by inverting the steps
+    (aw_ftle_grad_reversible).  Returns (L[N], grad_ic[6, N], grad_eps[N])."""
     if ens.ic_kind != "explicit":
         raise ValueError("ftle_grad needs an explicit ensemble")
     N = ens.size
@@ -393,9 +394,9 @@ def ftle_grad(ens: Ensemble, ic: torch.Tensor, w0: Optional[torch.Tensor] = None
     L = torch.empty((N,), dtype=torch.float64, device=ic.device)
     gic = torch.empty((6, N), dtype=torch.float64, device=ic.device)
     geps = torch.empty((N,), dtype=torch.float64, device=ic.device)
-    _abi.check(_lib().aw_ftle_grad(ctypes.byref(ens.to_c()), _p(ic), _p(w0), _p(grad_L), int(ckpt_every), _p(L),
-                                   _p(gic), _p(geps), _p(workspace), workspace.numel() * workspace.element_size(),
-                                   _tuning_ptr(tuning), _stream()))
+    fn = _lib().aw_ftle_grad_reversible if reversible else _lib().aw_ftle_grad
+    _abi.check(fn(ctypes.byref(ens.to_c()), _p(ic), _p(w0), _p(grad_L), int(ckpt_every), _p(L), _p(gic), _p(geps),
+                  _p(workspace), workspace.numel() * workspace.element_size(), _tuning_ptr(tuning), _stream()))
     return L, gic, geps
 
 

@@ -856,17 +856,21 @@ aw_status aw_ftle_grad_workspace(const aw_ensemble *ens, int64_t ckpt_every, siz
   if (N < 0) return fail(AW_EINVAL, "bad ensemble size");
   const int64_t ck = std::min(ckpt_every, ens->n_steps);
   const int64_t n_seg = (ens->n_steps + ck - 1) / ck;
-  *bytes = sizeof(double) * 12 * (size_t)N * (size_t)(n_seg + ck);
+  // checkpoints, the final state and one segment's step states (12 doubles
+  // per orbit each), then one 16-bit rescale exponent per orbit per 8 steps
+  *bytes = sizeof(double) * 12 * (size_t)N * (size_t)(n_seg + 1 + ck) +
+           sizeof(int16_t) * (size_t)N * (size_t)(ens->n_steps / 8);
   return AW_OK;
 }
 
-aw_status aw_ftle_grad(const aw_ensemble *ens, const double *ic_dev, const double *w0_dev, const double *grad_L_dev,
-                       int64_t ckpt_every, double *L_out_dev, double *grad_ic_dev, double *grad_eps_dev,
-                       void *workspace_dev, size_t ws_bytes, const aw_tuning *tuning, void *stream) {
+// Validation and descriptor of the adjoint of L (both sweeps).
+static aw_status ftle_setup(const aw_ensemble *ens, const double *ic_dev, const double *w0_dev,
+                            const double *grad_L_dev, int64_t ckpt_every, double *L_out_dev, double *grad_ic_dev,
+                            double *grad_eps_dev, void *workspace_dev, size_t ws_bytes, const aw_tuning *tuning,
+                            const char *who, FtleDesc &d, Tuning &t) {
   aw_status st = check_ensemble(ens, ic_dev, 0);
   if (st != AW_OK) return st;
-  if (ens->ic_kind != AW_IC_EXPLICIT) return fail(AW_EINVAL, "aw_ftle_grad needs an EXPLICIT ensemble");
-  Tuning t;
+  if (ens->ic_kind != AW_IC_EXPLICIT) return fail(AW_EINVAL, "%s needs an EXPLICIT ensemble", who);
   if ((st = check_tuning(tuning, t)) != AW_OK) return st;
   size_t need = 0;
   if ((st = aw_ftle_grad_workspace(ens, ckpt_every, &need)) != AW_OK) return st;
@@ -875,7 +879,6 @@ aw_status aw_ftle_grad(const aw_ensemble *ens, const double *ic_dev, const doubl
   if (N > 0 && (!grad_ic_dev || !grad_eps_dev)) return fail(AW_EINVAL, "null gradient outputs");
   if (ws_bytes < need || (N > 0 && !workspace_dev))
     return fail(AW_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
-  FtleDesc d;
   std::memset(&d, 0, sizeof d);
   double tau[MAX_UNIQUE];
   (void)unique_weights(ens->map_form, ens->h, tau, d.drift);
@@ -897,12 +900,41 @@ aw_status aw_ftle_grad(const aw_ensemble *ens, const double *ic_dev, const doubl
   d.gic = grad_ic_dev;
   d.geps = grad_eps_dev;
   d.ckpts = (double *)workspace_dev;
-  d.steps = d.ckpts + (size_t)d.n_seg * 12 * (size_t)N;
+  d.steps = d.ckpts + (size_t)(d.n_seg + 1) * 12 * (size_t)N;
+  d.exps = (int16_t *)(d.steps + (size_t)d.ckpt * 12 * (size_t)N);
+  return AW_OK;
+}
+
+aw_status aw_ftle_grad(const aw_ensemble *ens, const double *ic_dev, const double *w0_dev, const double *grad_L_dev,
+                       int64_t ckpt_every, double *L_out_dev, double *grad_ic_dev, double *grad_eps_dev,
+                       void *workspace_dev, size_t ws_bytes, const aw_tuning *tuning, void *stream) {
+  FtleDesc d;
+  Tuning t;
+  aw_status st = ftle_setup(ens, ic_dev, w0_dev, grad_L_dev, ckpt_every, L_out_dev, grad_ic_dev, grad_eps_dev,
+                            workspace_dev, ws_bytes, tuning, "aw_ftle_grad", d, t);
+  if (st != AW_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = launch_ftle_forward(d, ens->map_form, t, s);
   if (e != hipSuccess) return hip_fail(e, "FTLE-gradient forward launch");
   e = launch_ftle_backward(d, ens->map_form, t, s);
   if (e != hipSuccess) return hip_fail(e, "FTLE-gradient backward launch");
+  return AW_OK;
+}
+
+aw_status aw_ftle_grad_reversible(const aw_ensemble *ens, const double *ic_dev, const double *w0_dev,
+                                  const double *grad_L_dev, int64_t ckpt_every, double *L_out_dev,
+                                  double *grad_ic_dev, double *grad_eps_dev, void *workspace_dev, size_t ws_bytes,
+                                  const aw_tuning *tuning, void *stream) {
+  FtleDesc d;
+  Tuning t;
+  aw_status st = ftle_setup(ens, ic_dev, w0_dev, grad_L_dev, ckpt_every, L_out_dev, grad_ic_dev, grad_eps_dev,
+                            workspace_dev, ws_bytes, tuning, "aw_ftle_grad_reversible", d, t);
+  if (st != AW_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_ftle_forward(d, ens->map_form, t, s);
+  if (e != hipSuccess) return hip_fail(e, "FTLE-gradient forward launch");
+  e = launch_ftle_backward_reversible(d, ens->map_form, t, s);
+  if (e != hipSuccess) return hip_fail(e, "FTLE-gradient reversible backward launch");
   return AW_OK;
 }
 

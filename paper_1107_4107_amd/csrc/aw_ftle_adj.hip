@@ -30,6 +30,14 @@
 // undoing each stage by its exact inverse (drift: X -= t P, dX -= t dP;
 // kick: P -= the kick's increment, dP -= M dX) while the adjoint above is
 // propagated.  Each lane only reads back what it wrote itself.
+//
+// Reversible sweep (k_ftle_bwd_rev): no recompute and no stored step states.
+// Each segment is swept back from the exact state at its end (the next
+// checkpoint; the final state for the last segment), inverting the stages of
+// state and tangent step after step.  The exponent of every rescale cannot be
+// recovered from the rescaled tangent, so the forward pass records it (one
+// 16-bit integer per orbit per 8 steps) and the sweep applies it to the tangent and,
+// inversely, to its adjoint.
 #include <hip/hip_runtime.h>
 
 #include "aw_device.hpp"
@@ -243,9 +251,14 @@ __global__ __launch_bounds__(256) void k_ftle_fwd(FtleDesc d) {
     const int64_t g1 = g0 + d.ckpt < d.T ? g0 + d.ckpt : d.T;
     for (int64_t g = g0; g < g1; ++g) {
       tan_step<FORM>(o, d, s_tab);
-      if (((g + 1) & RESCALE_MASK) == 0) renorm(o);
+      if (((g + 1) & RESCALE_MASK) == 0) {
+        const int k0 = o.kexp;
+        renorm(o);
+        d.exps[((g + 1) / (RESCALE_MASK + 1) - 1) * N + n] = (int16_t)(o.kexp - k0);
+      }
     }
   }
+  store12(d.ckpts + d.n_seg * 12 * N, N, n, o);   // the final state (after any last rescale)
   if (d.L) {
     const double n2 = tan_norm2(o);
     const int e = __builtin_amdgcn_frexp_exp(n2);
@@ -304,7 +317,74 @@ __global__ __launch_bounds__(256) void k_ftle_bwd(FtleDesc d) {
   d.geps[n] = a.eb;
 }
 
+template <int FORM>
+__global__ __launch_bounds__(256) void k_ftle_bwd_rev(FtleDesc d) {
+  __shared__ double2 s_tab[AW_TAB_N];
+  load_sincos_table(s_tab);
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= d.N) return;
+  const int64_t N = d.N;
+  const double gl = d.gL ? d.gL[n] : 1.0;
+  Adjoint2 a{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  Orbit o;
+  o.p0x = o.p0y = o.p0z = 0.0;
+  o.jsum = 0.0;
+  o.kexp = 0;
+  for (int64_t s = d.n_seg - 1; s >= 0; --s) {
+    const int64_t g0 = s * d.ckpt;
+    const int64_t g1 = g0 + d.ckpt < d.T ? g0 + d.ckpt : d.T;
+    // Exact state at the end of step g1 - 1, after any rescale there.
+    load12(d.ckpts + (s + 1) * 12 * N, N, n, o);
+    for (int64_t g = g1 - 1; g >= g0; --g) {
+      // o: the state at the end of step g, after any rescale that followed it.
+      if (g == d.T - 1) {
+        const double c = gl / tan_norm2(o);
+        a.dxb = c * o.dx; a.dyb = c * o.dy; a.dzb = c * o.dz;
+        a.dpxb = c * o.dpx; a.dpyb = c * o.dpy; a.dpzb = c * o.dpz;
+      }
+      if (((g + 1) & RESCALE_MASK) == 0) {
+        // the forward set w_post = 2^-k w_pre: restore w_pre, and wbar_pre = 2^-k wbar_post
+        const int k = d.exps[((g + 1) / (RESCALE_MASK + 1) - 1) * N + n];
+        o.dx = __builtin_amdgcn_ldexp(o.dx, k);
+        o.dy = __builtin_amdgcn_ldexp(o.dy, k);
+        o.dz = __builtin_amdgcn_ldexp(o.dz, k);
+        o.dpx = __builtin_amdgcn_ldexp(o.dpx, k);
+        o.dpy = __builtin_amdgcn_ldexp(o.dpy, k);
+        o.dpz = __builtin_amdgcn_ldexp(o.dpz, k);
+        a.dxb = __builtin_amdgcn_ldexp(a.dxb, -k);
+        a.dyb = __builtin_amdgcn_ldexp(a.dyb, -k);
+        a.dzb = __builtin_amdgcn_ldexp(a.dzb, -k);
+        a.dpxb = __builtin_amdgcn_ldexp(a.dpxb, -k);
+        a.dpyb = __builtin_amdgcn_ldexp(a.dpyb, -k);
+        a.dpzb = __builtin_amdgcn_ldexp(a.dpzb, -k);
+      }
+      rev_tan_step<FORM>(o, a, d, s_tab);   // o: the state at the start of step g
+    }
+  }
+  d.gic[0 * N + n] = a.xb;
+  d.gic[1 * N + n] = a.yb;
+  d.gic[2 * N + n] = a.zb;
+  d.gic[3 * N + n] = a.pxb;
+  d.gic[4 * N + n] = a.pyb;
+  d.gic[5 * N + n] = a.pzb;
+  d.geps[n] = a.eb;
+}
+
 }  // namespace
+
+hipError_t launch_ftle_backward_reversible(const FtleDesc &d, int form, const Tuning &t, hipStream_t s) {
+  if (d.N <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((d.N + t.block - 1) / t.block);
+  switch (form) {
+  case 1: hipLaunchKernelGGL(k_ftle_bwd_rev<1>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  case 2: hipLaunchKernelGGL(k_ftle_bwd_rev<2>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  case 4: hipLaunchKernelGGL(k_ftle_bwd_rev<4>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  case 6: hipLaunchKernelGGL(k_ftle_bwd_rev<6>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  case 7: hipLaunchKernelGGL(k_ftle_bwd_rev<7>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_ftle_forward(const FtleDesc &d, int form, const Tuning &t, hipStream_t s) {
   if (d.N <= 0) return hipSuccess;

@@ -63,8 +63,10 @@ struct FtleDesc : AdjDesc {
   const double *w0;  // [6][N]
   const double *gL;  // [N] or null (ones)
   double *L;         // [N] or null
+  int16_t *exps;     // [floor(T/8)][N]: exponent of each tangent rescale
 };
 hipError_t launch_ftle_forward(const FtleDesc &d, int form, const Tuning &t, hipStream_t s);
 hipError_t launch_ftle_backward(const FtleDesc &d, int form, const Tuning &t, hipStream_t s);
+hipError_t launch_ftle_backward_reversible(const FtleDesc &d, int form, const Tuning &t, hipStream_t s);
 
 }  // namespace aw

@@ -129,7 +129,7 @@ def test_ftle_grad_workspace_and_validation():
     e = _ens(ic_kind="explicit", n_orbits=1000, n_steps=10_000)
     nb = ctypes.c_size_t()
     assert lib.aw_ftle_grad_workspace(ctypes.byref(e), 100, ctypes.byref(nb)) == 0
-    assert nb.value == 8 * 12 * 1000 * (100 + 100)
+    assert nb.value == 8 * 12 * 1000 * (100 + 1 + 100) + 2 * 1000 * (10_000 // 8)
     assert lib.aw_ftle_grad_workspace(ctypes.byref(e), 0, ctypes.byref(nb)) == _abi.AW_EINVAL
     fake = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation first
     # not EXPLICIT

@@ -210,3 +210,65 @@ def test_adjoints_do_not_depend_on_the_block_size(aw):
         got_j = aw.indicator_grad(ej, ic, ckpt_every=50, tuning=t)
         for a, r in zip(got_f + got_j, ref_f + ref_j):
             np.testing.assert_array_equal(np_(a), np_(r))
+
+
+@pytest.mark.parametrize("pz0", [0.0, 1.0])
+def test_reversible_ftle_gradient_matches_oracle(aw, pz0):
+    """The store-free sweep (each segment swept back from the next checkpoint,
+    rescales undone with the recorded exponents) at the bars of the
+    recompute-and-store sweep, and close to it."""
+    print_case("reversible ftle grad vs oracle", pz0)
+    rng = np.random.default_rng(5)
+    idx = np.sort(rng.choice(128 * 128, 256, replace=False))
+    ic = _slice_ic(128, pz0, idx)
+    w0 = oracle.w0(0, idx=idx)
+    T, eps = 1000, 1e-2
+    Lo, dLo = oracle.ftle_grad_ensemble("s6", eps, H, T, ic, w0)
+    e = _explicit(aw, eps, T, 256)
+    L, gic, geps = aw.ftle_grad(e, _to_dev(ic), _to_dev(w0), ckpt_every=100, reversible=True)
+    g = np.vstack([np_(gic), np_(geps)[None]])
+    reg = Lo / np.log(1 + T * H) < 1.5
+    assert np.max(np.abs(np_(L)[reg] - Lo[reg])) < 1e-9
+    _per_orbit_close(g[:, reg], dLo[:, reg], 1e-8, "reversible dL (regular)")
+    _, gs, es = aw.ftle_grad(e, _to_dev(ic), _to_dev(w0), ckpt_every=100)
+    _per_orbit_close(g[:, reg], np.vstack([np_(gs), np_(es)[None]])[:, reg], 1e-9, "reversible vs store")
+
+
+@pytest.mark.parametrize("form,T,ck", [("stdmap", 200, 30), ("y6", 200, 64), ("s6", 1, 4), ("s6", 8, 3), ("s6", 9, 9),
+                                       ("s6", 333, 1)])
+def test_reversible_ftle_gradient_forms_and_edges(aw, form, T, ck):
+    print_case("reversible ftle grad", form, T, ck)
+    ic = oracle.ic_box([0.0] * 6, [2 * np.pi] * 6, 9, 64)
+    w0 = oracle.w0(4, 64)
+    eps = 2e-2
+    Lo, dLo = oracle.ftle_grad_ensemble(form, eps, H, T, ic, w0)
+    L, gic, geps = aw.ftle_grad(_explicit(aw, eps, T, 64, form), _to_dev(ic), _to_dev(w0), ckpt_every=ck,
+                                reversible=True)
+    g = np.vstack([np_(gic), np_(geps)[None]])
+    reg = Lo / np.log(1 + T * H) < 1.5 if T > 50 else np.ones(64, dtype=bool)
+    assert reg.sum() > 16
+    _per_orbit_close(g[:, reg], dLo[:, reg], 1e-8, f"reversible dL {form} T={T}")
+
+
+def test_reversible_ftle_gradient_full_size(aw):
+    """Full size (512 x 512, eps = 1e-2, T = 1e4, checkpoints every 100
+    steps), store-free sweep: 64 regular orbits (seed 3) against the oracle at
+    the bars of the store sweep (dL 1e-6, L 1e-7)."""
+    print_case("reversible ftle gradient 512x512 T=1e4")
+    from paper_1107_4107_amd import workloads as wl
+    s = wl.c4()
+    N, T = s.nx * s.ny, s.n_steps
+    ic_all, _ = aw.generate_ic(s)
+    e = _explicit(aw, s.eps, T, N)
+    L, gic, geps = aw.ftle_grad(e, ic_all, ckpt_every=wl.C4_CKPT, reversible=True)
+    rng = np.random.default_rng(3)
+    cand = np.sort(rng.choice(N, 160, replace=False))
+    ic = oracle.ic_grid2((3, 4), (0, 0), (2 * np.pi, 2 * np.pi), s.nx, s.ny, list(s.base), idx=cand)
+    w0 = oracle.w0(0, idx=cand)
+    Lo, dLo = oracle.ftle_grad_ensemble("s6", s.eps, H, T, ic, w0)
+    reg = Lo / np.log(1 + T * H) < 1.5
+    pick = np.flatnonzero(reg)[:64]
+    assert pick.size == 64
+    assert np.max(np.abs(np_(L)[cand[pick]] - Lo[pick])) < 1e-7
+    g = np.vstack([np_(gic)[:, cand[pick]], np_(geps)[None, cand[pick]]])
+    _per_orbit_close(g, dLo[:, pick], 1e-6, "reversible dL full size")
