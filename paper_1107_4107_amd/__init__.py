@@ -340,10 +340,11 @@ def indicator_grad(ens: Ensemble, ic: torch.Tensor, grad_J: Optional[torch.Tenso
 class IndicatorJ(torch.autograd.Function):
     """J_n = (1/T) sum_k |P_k - P_0|^2 per orbit, differentiable in the initial
     state ic[N, 6] and in eps (a 0-d float64 tensor); the backward pass runs the
-    checkpointed adjoint kernels."""
+    checkpointed adjoint kernels (reversible=True: the store-free sweep)."""
 
     @staticmethod
-    def forward(ctx, ic, eps, n_steps: int, h: float = H_PAPER, map_form: str = "s6", ckpt_every: int = 100):
+    def forward(ctx, ic, eps, n_steps: int, h: float = H_PAPER, map_form: str = "s6", ckpt_every: int = 100,
+                reversible: bool = False):
         if ic.dim() != 2 or ic.shape[1] != 6:
             raise ValueError("ic must be [N, 6]")
         soa = ic.detach().t().contiguous()
@@ -353,17 +354,19 @@ class IndicatorJ(torch.autograd.Function):
         ctx.save_for_backward(soa)
         ctx.ens = e
         ctx.ckpt = ckpt_every
+        ctx.reversible = reversible
         ctx.eps_shape = eps.shape if isinstance(eps, torch.Tensor) else None
         return res.orbit_out[OUT_J].clone()
 
     @staticmethod
     def backward(ctx, gJ):
         (soa,) = ctx.saved_tensors
-        _, gic, geps = indicator_grad(ctx.ens, soa, gJ.contiguous().to(torch.float64), ctx.ckpt)
+        _, gic, geps = indicator_grad(ctx.ens, soa, gJ.contiguous().to(torch.float64), ctx.ckpt,
+                                      reversible=ctx.reversible)
         g_eps = geps.sum()
         if ctx.eps_shape is not None:
             g_eps = g_eps.reshape(ctx.eps_shape)
-        return gic.t().contiguous(), g_eps, None, None, None, None
+        return gic.t().contiguous(), g_eps, None, None, None, None, None
 
 
 def ftle_grad_workspace_bytes(ens: Ensemble, ckpt_every: int) -> int:
@@ -404,11 +407,12 @@ class IndicatorL(torch.autograd.Function):
     """L_n = ln(|w_T| / |w_0|) per orbit (the tangent growth behind the FTLE
     lambda = L/(T h) and chi = L/ln(1 + T h)), from the seeded tangent start,
     differentiable in the initial state ic[N, 6] and in eps (a 0-d float64
-    tensor); the backward pass runs the second-order adjoint kernels."""
+    tensor); the backward pass runs the second-order adjoint kernels
+    (reversible=True: the store-free sweep)."""
 
     @staticmethod
     def forward(ctx, ic, eps, n_steps: int, h: float = H_PAPER, map_form: str = "s6", ckpt_every: int = 100,
-                seed_tangent: int = 0):
+                seed_tangent: int = 0, reversible: bool = False):
         if ic.dim() != 2 or ic.shape[1] != 6:
             raise ValueError("ic must be [N, 6]")
         soa = ic.detach().t().contiguous()
@@ -418,17 +422,19 @@ class IndicatorL(torch.autograd.Function):
         ctx.save_for_backward(soa)
         ctx.ens = e
         ctx.ckpt = ckpt_every
+        ctx.reversible = reversible
         ctx.eps_shape = eps.shape if isinstance(eps, torch.Tensor) else None
         return res.orbit_out[OUT_L].clone()
 
     @staticmethod
     def backward(ctx, gL):
         (soa,) = ctx.saved_tensors
-        _, gic, geps = ftle_grad(ctx.ens, soa, grad_L=gL.contiguous().to(torch.float64), ckpt_every=ctx.ckpt)
+        _, gic, geps = ftle_grad(ctx.ens, soa, grad_L=gL.contiguous().to(torch.float64), ckpt_every=ctx.ckpt,
+                                 reversible=ctx.reversible)
         g_eps = geps.sum()
         if ctx.eps_shape is not None:
             g_eps = g_eps.reshape(ctx.eps_shape)
-        return gic.t().contiguous(), g_eps, None, None, None, None, None
+        return gic.t().contiguous(), g_eps, None, None, None, None, None, None
 
 
 class Graph:

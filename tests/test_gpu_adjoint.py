@@ -106,15 +106,16 @@ def test_symmetry_zeros_on_the_invariant_plane(aw):
     assert np.all(g[2] == 0.0) and np.all(g[5] == 0.0)
 
 
-def test_autograd_function(aw):
+@pytest.mark.parametrize("reversible", [False, True])
+def test_autograd_function(aw, reversible):
     import torch
-    print_case("autograd")
+    print_case("autograd", reversible)
     eps, T = 1e-2, 300
     ic = _regular_ics(8, 5, eps, T)
     x = tensor(ic.T.copy()).requires_grad_(True)
     ep = torch.tensor(eps, dtype=torch.float64, device="cuda", requires_grad=True)
     w = torch.arange(1, 9, dtype=torch.float64, device="cuda")
-    J = aw.IndicatorJ.apply(x, ep, T)
+    J = aw.IndicatorJ.apply(x, ep, T, H, "s6", 100, reversible)
     (J * w).sum().backward()
     _, dJo = oracle.J_grad_ensemble("s6", eps, H, T, ic)
     gx = np_(x.grad).T

@@ -147,19 +147,20 @@ def test_ftle_gradient_edge_cases(aw):
     assert L0.shape == (0,) and g0.shape == (6, 0) and e0.shape == (0,)
 
 
-def test_ftle_autograd(aw):
+@pytest.mark.parametrize("reversible", [False, True])
+def test_ftle_autograd(aw, reversible):
     """IndicatorL: the backward of sum(c * L) equals the adjoint with upstream
     gradient c; the eps gradient is the sum of the per-orbit contributions."""
     import torch
-    print_case("ftle autograd")
+    print_case("ftle autograd", reversible)
     ic = _to_dev(oracle.ic_box([0.0] * 6, [2 * np.pi] * 6, 23, 128))
     x = ic.t().contiguous().requires_grad_(True)
     eps = torch.tensor(2e-2, dtype=torch.float64, requires_grad=True)
-    L = aw.IndicatorL.apply(x, eps, 300)
+    L = aw.IndicatorL.apply(x, eps, 300, H, "s6", 100, 0, reversible)
     c = torch.linspace(-1.0, 2.0, 128, dtype=torch.float64, device="cuda")
     (L * c).sum().backward()
     e = _explicit(aw, 2e-2, 300, 128)
-    _, gic, geps = aw.ftle_grad(e, ic, grad_L=c)
+    _, gic, geps = aw.ftle_grad(e, ic, grad_L=c, reversible=reversible)
     np.testing.assert_allclose(np_(x.grad), np_(gic).T, rtol=1e-14, atol=1e-14)
     assert abs(float(eps.grad) - float(geps.sum())) <= 1e-12 * max(1.0, abs(float(eps.grad)))
 
