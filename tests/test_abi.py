@@ -199,3 +199,13 @@ def test_generated_headers_are_current(gen, header):
     out = subprocess.run(["python3", os.path.join(csrc, gen)], capture_output=True, text=True, timeout=300,
                          cwd=csrc, check=True).stdout
     assert out == open(os.path.join(csrc, header)).read()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it says so and exits non-zero
+    before touching a device."""
+    res = subprocess.run(["python3", os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, timeout=120)
+    assert res.returncode != 0
+    assert "one GPU" in res.stderr
+    assert res.stdout == ""
