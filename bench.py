@@ -653,7 +653,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-1core", action="store_true",
                     help="also time the oracle on one host thread (cpu_baseline_1core)")
-    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--block", type=int, default=512)
     ap.add_argument("--opl", type=int, default=1)
     ap.add_argument("--unroll", type=int, default=1)
     ap.add_argument("--copy-mib", type=int, default=0,

@@ -121,8 +121,8 @@ class Ensemble:
 
 @dataclass
 class Tuning:
-    """Launch shape (aw_tuning); zeros mean library defaults."""
-    block: int = 256
+    """Launch shape (aw_tuning); zeros mean library defaults (block 512)."""
+    block: int = 0
     orbits_per_lane: int = 1
     unroll: int = 1
     renorm_every: int = 8

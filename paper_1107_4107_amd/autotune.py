@@ -21,7 +21,7 @@ from . import Ensemble, Tuning, map_ensembles, timing_enable, timing_read
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "arnoldweb_tuning.json")
 CANDIDATES: Tuple[Tuple[int, int, int], ...] = tuple(
-    (b, o, u) for b in (64, 128, 256) for o in (1, 2) for u in (1, 2))
+    (b, o, u) for b in (64, 128, 256, 512) for o in (1, 2) for u in (1, 2))
 
 
 def _key(ens: Ensemble, n_total: int) -> str:

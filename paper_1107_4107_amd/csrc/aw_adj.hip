@@ -40,11 +40,11 @@ __device__ __forceinline__ void adj_step_fwd(Orbit &o, const AdjDesc &d, const d
 #pragma unroll
     for (int i = 0; i < NK; ++i) {
       drift<false>(o, d.drift[F::drift_idx[i]]);
-      kick_tab<false>(o, d.ka2[F::kick_idx[i]], d.ka4[F::kick_idx[i]], tab);
+      kick_tab<false, false>(o, d.ka2[F::kick_idx[i]], d.ka4[F::kick_idx[i]], tab);
     }
     drift<false>(o, d.drift[F::drift_idx[NK]]);
   } else {
-    kick_tab<false>(o, d.ka2[0], d.ka4[0], tab);
+    kick_tab<false, false>(o, d.ka2[0], d.ka4[0], tab);
     drift<false>(o, d.drift[0]);
   }
 }
@@ -231,13 +231,14 @@ __global__ __launch_bounds__(256) void k_adj_bwd(AdjDesc d) {
 
 hipError_t launch_adj_forward(const AdjDesc &d, int form, const Tuning &t, hipStream_t s) {
   if (d.N <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((d.N + t.block - 1) / t.block);
+  const int tb = block_256(t);
+  const unsigned blocks = (unsigned)((d.N + tb - 1) / tb);
   switch (form) {
-  case 1: hipLaunchKernelGGL(k_adj_fwd<1>, dim3(blocks), dim3(t.block), 0, s, d); break;
-  case 2: hipLaunchKernelGGL(k_adj_fwd<2>, dim3(blocks), dim3(t.block), 0, s, d); break;
-  case 4: hipLaunchKernelGGL(k_adj_fwd<4>, dim3(blocks), dim3(t.block), 0, s, d); break;
-  case 6: hipLaunchKernelGGL(k_adj_fwd<6>, dim3(blocks), dim3(t.block), 0, s, d); break;
-  case 7: hipLaunchKernelGGL(k_adj_fwd<7>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  case 1: hipLaunchKernelGGL(k_adj_fwd<1>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 2: hipLaunchKernelGGL(k_adj_fwd<2>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 4: hipLaunchKernelGGL(k_adj_fwd<4>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 6: hipLaunchKernelGGL(k_adj_fwd<6>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 7: hipLaunchKernelGGL(k_adj_fwd<7>, dim3(blocks), dim3(tb), 0, s, d); break;
   default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -245,13 +246,14 @@ hipError_t launch_adj_forward(const AdjDesc &d, int form, const Tuning &t, hipSt
 
 hipError_t launch_adj_backward_reversible(const AdjDesc &d, int form, const Tuning &t, hipStream_t s) {
   if (d.N <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((d.N + t.block - 1) / t.block);
+  const int tb = block_256(t);
+  const unsigned blocks = (unsigned)((d.N + tb - 1) / tb);
   switch (form) {
-  case 1: hipLaunchKernelGGL(k_adj_bwd_rev<1>, dim3(blocks), dim3(t.block), 0, s, d); break;
-  case 2: hipLaunchKernelGGL(k_adj_bwd_rev<2>, dim3(blocks), dim3(t.block), 0, s, d); break;
-  case 4: hipLaunchKernelGGL(k_adj_bwd_rev<4>, dim3(blocks), dim3(t.block), 0, s, d); break;
-  case 6: hipLaunchKernelGGL(k_adj_bwd_rev<6>, dim3(blocks), dim3(t.block), 0, s, d); break;
-  case 7: hipLaunchKernelGGL(k_adj_bwd_rev<7>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  case 1: hipLaunchKernelGGL(k_adj_bwd_rev<1>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 2: hipLaunchKernelGGL(k_adj_bwd_rev<2>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 4: hipLaunchKernelGGL(k_adj_bwd_rev<4>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 6: hipLaunchKernelGGL(k_adj_bwd_rev<6>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 7: hipLaunchKernelGGL(k_adj_bwd_rev<7>, dim3(blocks), dim3(tb), 0, s, d); break;
   default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -259,13 +261,14 @@ hipError_t launch_adj_backward_reversible(const AdjDesc &d, int form, const Tuni
 
 hipError_t launch_adj_backward(const AdjDesc &d, int form, const Tuning &t, hipStream_t s) {
   if (d.N <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((d.N + t.block - 1) / t.block);
+  const int tb = block_256(t);
+  const unsigned blocks = (unsigned)((d.N + tb - 1) / tb);
   switch (form) {
-  case 1: hipLaunchKernelGGL(k_adj_bwd<1>, dim3(blocks), dim3(t.block), 0, s, d); break;
-  case 2: hipLaunchKernelGGL(k_adj_bwd<2>, dim3(blocks), dim3(t.block), 0, s, d); break;
-  case 4: hipLaunchKernelGGL(k_adj_bwd<4>, dim3(blocks), dim3(t.block), 0, s, d); break;
-  case 6: hipLaunchKernelGGL(k_adj_bwd<6>, dim3(blocks), dim3(t.block), 0, s, d); break;
-  case 7: hipLaunchKernelGGL(k_adj_bwd<7>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  case 1: hipLaunchKernelGGL(k_adj_bwd<1>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 2: hipLaunchKernelGGL(k_adj_bwd<2>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 4: hipLaunchKernelGGL(k_adj_bwd<4>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 6: hipLaunchKernelGGL(k_adj_bwd<6>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 7: hipLaunchKernelGGL(k_adj_bwd<7>, dim3(blocks), dim3(tb), 0, s, d); break;
   default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -196,13 +196,13 @@ bool is_fin(double v) { return std::isfinite(v); }
 aw_status check_tuning(const aw_tuning *t, Tuning &out) {
   out = Tuning{};
   if (!t) return AW_OK;
-  out.block = t->block ? t->block : 256;
+  out.block = t->block ? t->block : 512;
   out.opl = t->orbits_per_lane ? t->orbits_per_lane : 1;
   out.unroll = t->unroll ? t->unroll : 1;
   out.renorm = t->renorm_every ? t->renorm_every : 8;
   out.pwgs = t->persistent_wgs;
-  if (out.block != 64 && out.block != 128 && out.block != 256)
-    return fail(AW_EINVAL, "tuning.block must be 64, 128 or 256 (got %d)", out.block);
+  if (out.block != 64 && out.block != 128 && out.block != 256 && out.block != 512)
+    return fail(AW_EINVAL, "tuning.block must be 64, 128, 256 or 512 (got %d)", out.block);
   if (out.opl != 1 && out.opl != 2) return fail(AW_EINVAL, "tuning.orbits_per_lane must be 1 or 2");
   if (out.unroll != 1 && out.unroll != 2) return fail(AW_EINVAL, "tuning.unroll must be 1 or 2");
   if (out.renorm < 1 || out.renorm > 16 || (out.renorm & (out.renorm - 1)))
@@ -363,7 +363,7 @@ struct BatchTables {
 
 BatchTables make_items(const std::vector<FwdDesc> &descs, const Tuning &t) {
   BatchTables b;
-  const int64_t per = (int64_t)t.block * t.opl;
+  const int64_t per = (int64_t)block_256(t) * t.opl;
   for (size_t e = 0; e < descs.size(); ++e)
     for (int64_t f = 0; f < descs[e].N; f += per) b.items.push_back(WorkItem{(int32_t)e, 0, f});
   // Longest processing time first: a tile's cost is its step count.

@@ -107,6 +107,54 @@ __device__ __forceinline__ void load_sincos_table(double2 *tab) {
   __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// The same with a 4096-entry table (the propagation kernels): x = q pi/2048 + r,
+// |r| <= pi/4096, k = q mod 4096, (S, C) = (sin, cos)(k pi/2048).  The small
+// |r| leaves one coefficient for sin r and two for cos r, and the table's byte
+// offset 16 k is the low word of t shifted left by 4 and cut to 16 bits, which
+// one SDWA shift does (dst_sel WORD_0 with zero padding), so the offset is
+// below 64 KB whatever t holds and the read stays inside the table.  Declared
+// as a kernel's first LDS object, the table sits at address 0 and the offset
+// is the address.  8 FMA, 4 MUL, 1 ADD, one integer instruction and one
+// 16-byte LDS read.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t ltab_offset(double t) {
+  uint32_t a;
+  asm("v_lshlrev_b32_sdwa %0, 4, %1 dst_sel:WORD_0 dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:DWORD"
+      : "=v"(a)
+      : "v"((uint32_t)__double2loint(t)));
+  return a;
+}
+
+__device__ __forceinline__ SinCosT sincos_ltab(double x, const double2 *__restrict__ tab) {
+  const double t = __builtin_fma(x, AW_INV_PI2K, AW_ROUND_MAGIC);
+  const double q = t - AW_ROUND_MAGIC;
+  double r = __builtin_fma(-q, AW_PI2K_A, x);
+  r = __builtin_fma(-q, AW_PI2K_B, r);
+  const double2 e = *(const double2 *)((const char *)tab + ltab_offset(t));
+  const double u = r * r;
+  const double sr = __builtin_fma(r * u, AW_LSIN_C0, r);
+  const double pc = __builtin_fma(AW_LCOS_C[1], u, AW_LCOS_C[0]);
+  const double cr = __builtin_fma(u, pc, 1.0);
+  SinCosT o;
+  o.s = __builtin_fma(e.x, cr, e.y * sr);
+  o.c = __builtin_fma(e.y, cr, -(e.x * sr));
+  return o;
+}
+
+// FP64 operation counts of one sincos_ltab.
+constexpr int SCL_FMA = 1 + 2 + 1 + 2 + 2;
+constexpr int SCL_MUL = 4;  // r*r, r*u, and one product per rotated output
+constexpr int SCL_ADD = 1;
+
+// Fill a block's LDS copy of the (sin, cos)(k pi/2048) table; every thread of
+// the block must call this before any of them returns.
+__device__ __forceinline__ void load_sincos_ltable(double2 *tab) {
+  for (int i = threadIdx.x; i < AW_LTAB_N; i += blockDim.x)
+    tab[i] = make_double2(AW_LTAB_SC[2 * i], AW_LTAB_SC[2 * i + 1]);
+  __syncthreads();
+}
+
 // True signed cos/sin (used outside the hot loop).
 __device__ __forceinline__ void sincos_full(double x, double &s, double &c) {
   SinCos a = sincos_red(x);
@@ -134,16 +182,22 @@ struct Orbit {
 };
 
 // Kick with weight a2 = 2 t eps, a4 = 4 t eps, sines and cosines from the
-// block's LDS table (true values: no sign folding).  Every force and Hessian
+// block's LDS table (true values: no sign folding): the 4096-entry table when
+// LTAB (the propagation kernels), else the 128-entry one (the adjoints).  Every force and Hessian
 // term of eq. 2 is a product of one x factor, one y factor and z factors:
 //   e1 = 2 t eps cz^2, e2 = 4 t eps cz sz, e3 = 4 t eps (cz^2 - sz^2),
 //   P  += (e1 sx cy, e1 cx sy, e2 cx cy)                 (= -t eps grad Hp)
 //   dP += M dX, M = [[e1 cx cy, -e1 sx sy, -e2 sx cy],
 //                    [-e1 sx sy, e1 cx cy, -e2 cx sy],
 //                    [-e2 sx cy, -e2 cx sy, e3 cx cy]]     (= -t eps Hess Hp)
-template <bool TAN>
+template <bool TAN, bool LTAB>
 __device__ __forceinline__ void kick_tab(Orbit &o, double a2, double a4, const double2 *__restrict__ tab) {
-  const SinCosT X = sincos_tab(o.x, tab), Y = sincos_tab(o.y, tab), Z = sincos_tab(o.z, tab);
+  SinCosT X, Y, Z;
+  if (LTAB) {
+    X = sincos_ltab(o.x, tab); Y = sincos_ltab(o.y, tab); Z = sincos_ltab(o.z, tab);
+  } else {
+    X = sincos_tab(o.x, tab); Y = sincos_tab(o.y, tab); Z = sincos_tab(o.z, tab);
+  }
   const double cx = X.c, sx = X.s;
   const double cy = Y.c, sy = Y.s;
   const double cz2 = Z.c * Z.c;
@@ -189,10 +243,10 @@ __device__ __forceinline__ void drift(Orbit &o, double t) {
 }
 
 // Op counts of kick/drift (roofline accounting).
-template <bool TAN> struct KickTabOps {
-  static constexpr int fma = 3 * SCT_FMA + 3 + (TAN ? 1 + 9 : 0);
-  static constexpr int mul = 3 * SCT_MUL + 7 + (TAN ? 7 : 0);
-  static constexpr int add = 3 * SCT_ADD;
+template <bool TAN, bool LTAB> struct KickTabOps {
+  static constexpr int fma = 3 * (LTAB ? SCL_FMA : SCT_FMA) + 3 + (TAN ? 1 + 9 : 0);
+  static constexpr int mul = 3 * (LTAB ? SCL_MUL : SCT_MUL) + 7 + (TAN ? 7 : 0);
+  static constexpr int add = 3 * (LTAB ? SCL_ADD : SCT_ADD);
 };
 template <bool TAN> struct DriftOps {
   static constexpr int fma = TAN ? 6 : 3;

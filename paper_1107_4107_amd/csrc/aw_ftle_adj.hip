@@ -59,11 +59,11 @@ __device__ __forceinline__ void tan_step(Orbit &o, const AdjDesc &d, const doubl
 #pragma unroll
     for (int i = 0; i < NK; ++i) {
       drift<true>(o, d.drift[F::drift_idx[i]]);
-      kick_tab<true>(o, d.ka2[F::kick_idx[i]], d.ka4[F::kick_idx[i]], tab);
+      kick_tab<true, false>(o, d.ka2[F::kick_idx[i]], d.ka4[F::kick_idx[i]], tab);
     }
     drift<true>(o, d.drift[F::drift_idx[NK]]);
   } else {
-    kick_tab<true>(o, d.ka2[0], d.ka4[0], tab);
+    kick_tab<true, false>(o, d.ka2[0], d.ka4[0], tab);
     drift<true>(o, d.drift[0]);
   }
 }
@@ -374,13 +374,14 @@ __global__ __launch_bounds__(256) void k_ftle_bwd_rev(FtleDesc d) {
 
 hipError_t launch_ftle_backward_reversible(const FtleDesc &d, int form, const Tuning &t, hipStream_t s) {
   if (d.N <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((d.N + t.block - 1) / t.block);
+  const int tb = block_256(t);
+  const unsigned blocks = (unsigned)((d.N + tb - 1) / tb);
   switch (form) {
-  case 1: hipLaunchKernelGGL(k_ftle_bwd_rev<1>, dim3(blocks), dim3(t.block), 0, s, d); break;
-  case 2: hipLaunchKernelGGL(k_ftle_bwd_rev<2>, dim3(blocks), dim3(t.block), 0, s, d); break;
-  case 4: hipLaunchKernelGGL(k_ftle_bwd_rev<4>, dim3(blocks), dim3(t.block), 0, s, d); break;
-  case 6: hipLaunchKernelGGL(k_ftle_bwd_rev<6>, dim3(blocks), dim3(t.block), 0, s, d); break;
-  case 7: hipLaunchKernelGGL(k_ftle_bwd_rev<7>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  case 1: hipLaunchKernelGGL(k_ftle_bwd_rev<1>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 2: hipLaunchKernelGGL(k_ftle_bwd_rev<2>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 4: hipLaunchKernelGGL(k_ftle_bwd_rev<4>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 6: hipLaunchKernelGGL(k_ftle_bwd_rev<6>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 7: hipLaunchKernelGGL(k_ftle_bwd_rev<7>, dim3(blocks), dim3(tb), 0, s, d); break;
   default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -388,13 +389,14 @@ hipError_t launch_ftle_backward_reversible(const FtleDesc &d, int form, const Tu
 
 hipError_t launch_ftle_forward(const FtleDesc &d, int form, const Tuning &t, hipStream_t s) {
   if (d.N <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((d.N + t.block - 1) / t.block);
+  const int tb = block_256(t);
+  const unsigned blocks = (unsigned)((d.N + tb - 1) / tb);
   switch (form) {
-  case 1: hipLaunchKernelGGL(k_ftle_fwd<1>, dim3(blocks), dim3(t.block), 0, s, d); break;
-  case 2: hipLaunchKernelGGL(k_ftle_fwd<2>, dim3(blocks), dim3(t.block), 0, s, d); break;
-  case 4: hipLaunchKernelGGL(k_ftle_fwd<4>, dim3(blocks), dim3(t.block), 0, s, d); break;
-  case 6: hipLaunchKernelGGL(k_ftle_fwd<6>, dim3(blocks), dim3(t.block), 0, s, d); break;
-  case 7: hipLaunchKernelGGL(k_ftle_fwd<7>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  case 1: hipLaunchKernelGGL(k_ftle_fwd<1>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 2: hipLaunchKernelGGL(k_ftle_fwd<2>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 4: hipLaunchKernelGGL(k_ftle_fwd<4>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 6: hipLaunchKernelGGL(k_ftle_fwd<6>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 7: hipLaunchKernelGGL(k_ftle_fwd<7>, dim3(blocks), dim3(tb), 0, s, d); break;
   default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -402,13 +404,14 @@ hipError_t launch_ftle_forward(const FtleDesc &d, int form, const Tuning &t, hip
 
 hipError_t launch_ftle_backward(const FtleDesc &d, int form, const Tuning &t, hipStream_t s) {
   if (d.N <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((d.N + t.block - 1) / t.block);
+  const int tb = block_256(t);
+  const unsigned blocks = (unsigned)((d.N + tb - 1) / tb);
   switch (form) {
-  case 1: hipLaunchKernelGGL(k_ftle_bwd<1>, dim3(blocks), dim3(t.block), 0, s, d); break;
-  case 2: hipLaunchKernelGGL(k_ftle_bwd<2>, dim3(blocks), dim3(t.block), 0, s, d); break;
-  case 4: hipLaunchKernelGGL(k_ftle_bwd<4>, dim3(blocks), dim3(t.block), 0, s, d); break;
-  case 6: hipLaunchKernelGGL(k_ftle_bwd<6>, dim3(blocks), dim3(t.block), 0, s, d); break;
-  case 7: hipLaunchKernelGGL(k_ftle_bwd<7>, dim3(blocks), dim3(t.block), 0, s, d); break;
+  case 1: hipLaunchKernelGGL(k_ftle_bwd<1>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 2: hipLaunchKernelGGL(k_ftle_bwd<2>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 4: hipLaunchKernelGGL(k_ftle_bwd<4>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 6: hipLaunchKernelGGL(k_ftle_bwd<6>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 7: hipLaunchKernelGGL(k_ftle_bwd<7>, dim3(blocks), dim3(tb), 0, s, d); break;
   default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

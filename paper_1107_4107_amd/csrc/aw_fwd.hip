@@ -103,24 +103,28 @@ __device__ __forceinline__ void map_step(Orbit (&o)[OPL], const FwdDesc &d, cons
 #pragma unroll
       for (int j = 0; j < OPL; ++j) drift<TAN>(o[j], d.drift[F::drift_idx[i]]);
 #pragma unroll
-      for (int j = 0; j < OPL; ++j) kick_tab<TAN>(o[j], d.ka2[F::kick_idx[i]], d.ka4[F::kick_idx[i]], tab);
+      for (int j = 0; j < OPL; ++j) kick_tab<TAN, true>(o[j], d.ka2[F::kick_idx[i]], d.ka4[F::kick_idx[i]], tab);
     }
 #pragma unroll
     for (int j = 0; j < OPL; ++j) drift<TAN>(o[j], d.drift[F::drift_idx[NK]]);
   } else {
 #pragma unroll
-    for (int j = 0; j < OPL; ++j) kick_tab<TAN>(o[j], d.ka2[0], d.ka4[0], tab);
+    for (int j = 0; j < OPL; ++j) kick_tab<TAN, true>(o[j], d.ka2[0], d.ka4[0], tab);
 #pragma unroll
     for (int j = 0; j < OPL; ++j) drift<TAN>(o[j], d.drift[0]);
   }
 }
 
-// Select row r of the nine per-orbit results without dynamic indexing.
-__device__ __forceinline__ double pick9(const double v[9], int r) {
-  double o = v[0];
+// Select row r of the nine per-orbit results by masking bit patterns.  A
+// chain of selects over the array's elements is folded by the optimizer into
+// one load at a selected offset, which keeps the array in memory (private
+// scratch, or LDS sized for the whole block); AND/OR of the bits leaves
+// nothing to fold.
+__device__ __forceinline__ double pick9(const double (&v)[9], int r) {
+  uint64_t o = 0;
 #pragma unroll
-  for (int k = 1; k < 9; ++k) o = (r == k) ? v[k] : o;
-  return o;
+  for (int k = 0; k < 9; ++k) o |= (uint64_t)__double_as_longlong(v[k]) & (0ull - (uint64_t)(r == k));
+  return __longlong_as_double((long long)o);
 }
 
 __device__ __forceinline__ uint32_t bin_of(double a, double b, double lo0, double hi0, double lo1,
@@ -235,10 +239,12 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first, cons
   }
 
   // Hot loop.  The trip count and the renormalisation test are uniform.
+  // UNR = 2 runs steps in pairs plus a one-step tail, written out: the table
+  // offset is inline assembly, which the compiler treats as convergent and
+  // will not unroll with a remainder.
   const int64_t k0 = d.k_begin, k1 = d.k_end;
   const int64_t mask = d.renorm_mask;
-#pragma unroll UNR
-  for (int64_t k = k0; k < k1; ++k) {
+  auto one_step = [&](int64_t k) {
     map_step<FORM, TAN, OPL>(o, d, tab);
 #pragma unroll
     for (int j = 0; j < OPL; ++j) accum_j(o[j]);
@@ -250,7 +256,17 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first, cons
 #pragma unroll
       for (int j = 0; j < OPL; ++j) renorm(o[j]);
     }
+  };
+  int64_t k = k0;
+  if (UNR == 2) {
+#pragma nounroll
+    for (; k + 1 < k1; k += 2) {
+      one_step(k);
+      one_step(k + 1);
+    }
   }
+#pragma nounroll
+  for (; k < k1; ++k) one_step(k);
 
   if (k1 < d.T || WINV) {
     // Intermediate launch (or a time window): store the resumable carry.
@@ -321,8 +337,10 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first, cons
     n_chaotic += (uint32_t)__popcll(__ballot(act[j] && chaotic));
     if (!act[j]) continue;
     if (d.out) {
-#pragma unroll
-      for (int r = 0; r < 9; ++r) d.out[r * N + m] = res[r];
+      double *out = d.out;
+      out[0 * N + m] = res[0]; out[1 * N + m] = res[1]; out[2 * N + m] = res[2];
+      out[3 * N + m] = res[3]; out[4 * N + m] = res[4]; out[5 * N + m] = res[5];
+      out[6 * N + m] = res[6]; out[7 * N + m] = res[7]; out[8 * N + m] = res[8];
     }
     if (d.state) {
       double *st = d.state;
@@ -358,10 +376,13 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first, cons
   }
 }
 
+// Blocks of up to 512 lanes: with the 64 KB table two blocks share a CU, and
+// at four waves per SIMD it takes blocks of 512 to fill it.  The window-test
+// and time-window variants hold about twice the registers and keep 256.
 template <int FORM, bool TAN, int OPL, int UNR, bool FILT = false, bool WINV = false>
-__global__ __launch_bounds__(256) void k_fwd(FwdDesc d) {
-  __shared__ double2 s_tab[AW_TAB_N];
-  load_sincos_table(s_tab);
+__global__ __launch_bounds__((FILT || WINV) ? 256 : 512) void k_fwd(FwdDesc d) {
+  __shared__ double2 s_tab[AW_LTAB_N];
+  load_sincos_ltable(s_tab);
   const int64_t first = (int64_t)blockIdx.x * blockDim.x * OPL;
   run_orbits<FORM, TAN, OPL, UNR, FILT, WINV>(d, first, s_tab);
 }
@@ -372,9 +393,9 @@ template <int FORM, bool TAN, int OPL>
 __global__ __launch_bounds__(256) void k_fwd_persist(const FwdDesc *__restrict__ descs,
                                                      const WorkItem *__restrict__ items,
                                                      int32_t n_items, uint32_t *head) {
+  __shared__ double2 s_tab[AW_LTAB_N];
   __shared__ int32_t s_item;
-  __shared__ double2 s_tab[AW_TAB_N];
-  load_sincos_table(s_tab);
+  load_sincos_ltable(s_tab);
   for (;;) {
     if (threadIdx.x == 0) s_item = (int32_t)atomicAdd(head, 1u);
     __syncthreads();
@@ -419,8 +440,10 @@ static hipError_t fwd_dispatch_opl(const FwdDesc &d, const Tuning &t, hipStream_
   dim3 grid((unsigned)blocks), block((unsigned)t.block);
   if (d.filter || d.window_v) {
     // The window test and the time-window velocity run with one orbit per
-    // lane and no unrolling.
-    const dim3 wgrid((unsigned)((d.N + t.block - 1) / t.block));
+    // lane, no unrolling and at most 256 lanes per block.
+    const int wb = block_256(t);
+    const dim3 wgrid((unsigned)((d.N + wb - 1) / wb));
+    block = dim3((unsigned)wb);
     if (d.filter && d.window_v) hipLaunchKernelGGL((k_fwd<FORM, TAN, 1, 1, true, true>), wgrid, block, 0, s, d);
     else if (d.filter) hipLaunchKernelGGL((k_fwd<FORM, TAN, 1, 1, true, false>), wgrid, block, 0, s, d);
     else hipLaunchKernelGGL((k_fwd<FORM, TAN, 1, 1, false, true>), wgrid, block, 0, s, d);
@@ -446,7 +469,7 @@ template <int FORM, bool TAN>
 static hipError_t persist_dispatch(const FwdDesc *descs, const WorkItem *items, int32_t n_items,
                                    uint32_t *head, const Tuning &t, int n_wg, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, head, 1);
-  dim3 grid((unsigned)n_wg), block((unsigned)t.block);
+  dim3 grid((unsigned)n_wg), block((unsigned)block_256(t));
   if (t.opl == 1) hipLaunchKernelGGL((k_fwd_persist<FORM, TAN, 1>), grid, block, 0, s, descs, items, n_items, head);
   else hipLaunchKernelGGL((k_fwd_persist<FORM, TAN, 2>), grid, block, 0, s, descs, items, n_items, head);
   return hipGetLastError();
@@ -475,10 +498,10 @@ int persistent_blocks_per_cu(int form, bool tan, const Tuning &t) {
   hipError_t e = hipErrorInvalidValue;
 #define AW_OCC(F)                                                                                 \
   if (form == F) {                                                                                \
-    if (tan) e = t.opl == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_persist<F, true, 1>, t.block, 0) \
-                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_persist<F, true, 2>, t.block, 0); \
-    else e = t.opl == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_persist<F, false, 1>, t.block, 0) \
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_persist<F, false, 2>, t.block, 0); \
+    if (tan) e = t.opl == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_persist<F, true, 1>, block_256(t), 0) \
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_persist<F, true, 2>, block_256(t), 0); \
+    else e = t.opl == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_persist<F, false, 1>, block_256(t), 0) \
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_persist<F, false, 2>, block_256(t), 0); \
   }
   AW_OCC(1) AW_OCC(2) AW_OCC(4) AW_OCC(6) AW_OCC(7)
 #undef AW_OCC
@@ -510,9 +533,9 @@ void step_op_counts(int form, bool tan, int64_t *fma, int64_t *mul, int64_t *add
   case 7: nk = 7; nd = 8; break;
   default: break;
   }
-  const int kf = tan ? KickTabOps<true>::fma : KickTabOps<false>::fma;
-  const int km = tan ? KickTabOps<true>::mul : KickTabOps<false>::mul;
-  const int ka = tan ? KickTabOps<true>::add : KickTabOps<false>::add;
+  const int kf = tan ? KickTabOps<true, true>::fma : KickTabOps<false, true>::fma;
+  const int km = tan ? KickTabOps<true, true>::mul : KickTabOps<false, true>::mul;
+  const int ka = tan ? KickTabOps<true, true>::add : KickTabOps<false, true>::add;
   const int df = tan ? DriftOps<true>::fma : DriftOps<false>::fma;
   *fma = (int64_t)nk * kf + (int64_t)nd * df + 3;  // + 3 fma of the J accumulator
   *mul = (int64_t)nk * km;

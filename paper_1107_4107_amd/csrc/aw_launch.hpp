@@ -10,12 +10,17 @@
 namespace aw {
 
 struct Tuning {
-  int block = 256;
+  int block = 512;
   int opl = 1;
   int unroll = 1;
   int renorm = 8;
   int pwgs = 0;
 };
+
+// Kernels bounded at 256 lanes per block (the window-test and time-window
+// propagation, the batched persistent kernel and the adjoints) run a larger
+// requested block as 256.  No result depends on the block.
+inline int block_256(const Tuning &t) { return t.block < 256 ? t.block : 256; }
 
 // Propagation.
 hipError_t launch_fwd(const FwdDesc &d, const Tuning &t, int form, bool tan, hipStream_t s);

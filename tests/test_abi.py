@@ -151,11 +151,11 @@ def test_ftle_grad_workspace_and_validation():
 def test_step_op_counts_match_the_stage_structure():
     """Per map step: 9 kicks (3 sincos each) and 10 drifts for the 6th-order
     triple jump, 7 and 8 for Y6; the counts are those of the kernel's formulas
-    (one table-driven sincos = 11 fma, 4 mul, 1 add; the rest of a kick 3 fma
+    (one sincos from the 4096-entry table = 8 fma, 4 mul, 1 add; the rest of a kick 3 fma
     and 7 mul, plus 10 fma and 7 mul for the tangent; a drift 3 fma, 6 with the
     tangent; the J accumulator 3 fma and 3 subtractions)."""
     from paper_1107_4107_amd import step_op_counts
-    sc_f, sc_m, sc_a = 11, 4, 1
+    sc_f, sc_m, sc_a = 8, 4, 1
     kick_t = (3 * sc_f + 3 + 10, 3 * sc_m + 7 + 7, 3 * sc_a)
     kick_n = (3 * sc_f + 3, 3 * sc_m + 7, 3 * sc_a)
     f, m, a = step_op_counts("s6", True)

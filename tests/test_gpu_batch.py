@@ -27,7 +27,7 @@ def _mixed(aw):
     return [wl.slice_ensemble(e, n, T) for e, n, T in spec]
 
 
-@pytest.mark.parametrize("tun", [None, (64, 1, 1, 8, 7), (128, 2, 1, 4, 0)])
+@pytest.mark.parametrize("tun", [None, (64, 1, 1, 8, 7), (128, 2, 1, 4, 0), (512, 1, 1, 8, 0)])
 def test_batched_equals_separate(aw, tun):
     print_case("batched vs separate", tun)
     ens = _mixed(aw)

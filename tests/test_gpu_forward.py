@@ -125,7 +125,8 @@ def test_chunked_run_is_bitwise_equal(aw):
     np.testing.assert_array_equal(np_(cls), np_(full.cls))
 
 
-@pytest.mark.parametrize("tun", [(64, 1, 1, 8), (128, 2, 1, 8), (256, 1, 2, 1), (256, 2, 2, 16), (64, 2, 1, 4)])
+@pytest.mark.parametrize("tun", [(64, 1, 1, 8), (128, 2, 1, 8), (256, 1, 2, 1), (256, 2, 2, 16), (64, 2, 1, 4),
+                                 (512, 1, 1, 8), (512, 1, 2, 4), (512, 2, 2, 8)])
 def test_results_do_not_depend_on_the_launch_shape(aw, tun):
     print_case("tuning", tun)
     e = slice_ens(aw, 2e-2, 50, 300, nx=50, ny=43)   # ragged against every block
