@@ -144,10 +144,10 @@ typedef struct {
 
 /* Launch shape.  NULL or zero fields = defaults (block 512, one orbit per
  * lane, step loop not unrolled, renormalisation every 8 steps).  block in
- * {64, 128, 256, 512}: the propagation kernels hold a 64 KB sine/cosine table
- * per block, so blocks of 512 lanes are needed for a full CU; the window-test
- * and time-window propagation, the batched persistent launch and the adjoints
- * run a block above 256 as 256.  orbits_per_lane in {1, 2}; unroll in {1, 2};
+ * {64, 128, 256, 512}: the kernels hold a 64 KB sine/cosine table per block,
+ * so blocks of 512 lanes are needed for a full CU; the window-test and
+ * time-window propagation and the batched persistent launch run a block above
+ * 256 as 256.  orbits_per_lane in {1, 2}; unroll in {1, 2};
  * renorm_every in {1, 2, 4, 8, 16}.  persistent_wgs: workgroups of the batched
  * persistent launch (0 = auto). */
 typedef struct {

@@ -40,11 +40,11 @@ __device__ __forceinline__ void adj_step_fwd(Orbit &o, const AdjDesc &d, const d
 #pragma unroll
     for (int i = 0; i < NK; ++i) {
       drift<false>(o, d.drift[F::drift_idx[i]]);
-      kick_tab<false, false>(o, d.ka2[F::kick_idx[i]], d.ka4[F::kick_idx[i]], tab);
+      kick_tab<false>(o, d.ka2[F::kick_idx[i]], d.ka4[F::kick_idx[i]], tab);
     }
     drift<false>(o, d.drift[F::drift_idx[NK]]);
   } else {
-    kick_tab<false, false>(o, d.ka2[0], d.ka4[0], tab);
+    kick_tab<false>(o, d.ka2[0], d.ka4[0], tab);
     drift<false>(o, d.drift[0]);
   }
 }
@@ -127,7 +127,7 @@ __device__ __forceinline__ void store6(double *p, int64_t N, int64_t n, const Or
 }
 
 template <int FORM>
-__global__ __launch_bounds__(256) void k_adj_fwd(AdjDesc d) {
+__global__ __launch_bounds__(512) void k_adj_fwd(AdjDesc d) {
   __shared__ double2 s_tab[AW_TAB_N];
   load_sincos_table(s_tab);
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256) void k_adj_fwd(AdjDesc d) {
 }
 
 template <int FORM>
-__global__ __launch_bounds__(256) void k_adj_bwd_rev(AdjDesc d) {
+__global__ __launch_bounds__(512) void k_adj_bwd_rev(AdjDesc d) {
   __shared__ double2 s_tab[AW_TAB_N];
   load_sincos_table(s_tab);
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -188,7 +188,7 @@ __global__ __launch_bounds__(256) void k_adj_bwd_rev(AdjDesc d) {
 }
 
 template <int FORM>
-__global__ __launch_bounds__(256) void k_adj_bwd(AdjDesc d) {
+__global__ __launch_bounds__(512) void k_adj_bwd(AdjDesc d) {
   __shared__ double2 s_tab[AW_TAB_N];
   load_sincos_table(s_tab);
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(256) void k_adj_bwd(AdjDesc d) {
 
 hipError_t launch_adj_forward(const AdjDesc &d, int form, const Tuning &t, hipStream_t s) {
   if (d.N <= 0) return hipSuccess;
-  const int tb = block_256(t);
+  const int tb = t.block;
   const unsigned blocks = (unsigned)((d.N + tb - 1) / tb);
   switch (form) {
   case 1: hipLaunchKernelGGL(k_adj_fwd<1>, dim3(blocks), dim3(tb), 0, s, d); break;
@@ -246,7 +246,7 @@ hipError_t launch_adj_forward(const AdjDesc &d, int form, const Tuning &t, hipSt
 
 hipError_t launch_adj_backward_reversible(const AdjDesc &d, int form, const Tuning &t, hipStream_t s) {
   if (d.N <= 0) return hipSuccess;
-  const int tb = block_256(t);
+  const int tb = t.block;
   const unsigned blocks = (unsigned)((d.N + tb - 1) / tb);
   switch (form) {
   case 1: hipLaunchKernelGGL(k_adj_bwd_rev<1>, dim3(blocks), dim3(tb), 0, s, d); break;
@@ -261,7 +261,7 @@ hipError_t launch_adj_backward_reversible(const AdjDesc &d, int form, const Tuni
 
 hipError_t launch_adj_backward(const AdjDesc &d, int form, const Tuning &t, hipStream_t s) {
   if (d.N <= 0) return hipSuccess;
-  const int tb = block_256(t);
+  const int tb = t.block;
   const unsigned blocks = (unsigned)((d.N + tb - 1) / tb);
   switch (form) {
   case 1: hipLaunchKernelGGL(k_adj_bwd<1>, dim3(blocks), dim3(tb), 0, s, d); break;

@@ -61,33 +61,43 @@ constexpr int SC_MUL = 2;  // r*r, r*u
 constexpr int SC_ADD = 1;  // t - magic
 
 // ---------------------------------------------------------------------------
-// Table-driven sin and cos of an unwrapped angle (the propagation kernels).
-// x = q pi/64 + r with q = nearest integer to 64 x/pi (magic-number rounding:
-// the low mantissa word of q + 1.5*2^52 holds q in two's complement), r by a
-// two-part Cody-Waite step, |r| <= pi/128.  With k = q mod 128 and
-// (S, C) = (sin, cos)(k pi/64) from a 128-entry table in LDS:
+// Table-driven sin and cos of an unwrapped angle (the propagation and adjoint
+// kernels).  x = q pi/2048 + r with q = nearest integer to 2048 x/pi
+// (magic-number rounding: the low mantissa word of q + 1.5*2^52 holds q in
+// two's complement), r by a two-part Cody-Waite step, |r| <= pi/4096.  With
+// k = q mod 4096 and (S, C) = (sin, cos)(k pi/2048) from a 4096-entry table in
+// LDS (64 KB):
 //   sin x = S cos r + C sin r,  cos x = C cos r - S sin r,
-// sin r and cos r by polynomials of three coefficients in r^2.  The table
-// carries every quadrant's signs, so the results are the true sine and
-// cosine.  11 FMA, 4 MUL, 1 ADD and one 16-byte LDS read.
+// sin r = r + r^3 c (one coefficient) and cos r = 1 + r^2 Q(r^2) (two).  The
+// table carries every quadrant's signs, so the results are the true sine and
+// cosine.  The table's byte offset 16 k is the low word of t shifted left by
+// 4 and cut to 16 bits, which one SDWA shift does (dst_sel WORD_0 with zero
+// padding), so the offset is below 64 KB whatever t holds and the read stays
+// inside the table.  Declared as a kernel's first LDS object, the table sits
+// at address 0 and the offset is the address.  8 FMA, 4 MUL, 1 ADD, one
+// integer instruction and one 16-byte LDS read.
 // ---------------------------------------------------------------------------
 struct SinCosT {
   double s, c;
 };
 
+__device__ __forceinline__ uint32_t tab_offset(double t) {
+  uint32_t a;
+  asm("v_lshlrev_b32_sdwa %0, 4, %1 dst_sel:WORD_0 dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:DWORD"
+      : "=v"(a)
+      : "v"((uint32_t)__double2loint(t)));
+  return a;
+}
+
 __device__ __forceinline__ SinCosT sincos_tab(double x, const double2 *__restrict__ tab) {
-  const double t = __builtin_fma(x, AW_INV_PI64, AW_ROUND_MAGIC);
+  const double t = __builtin_fma(x, AW_INV_PI2K, AW_ROUND_MAGIC);
   const double q = t - AW_ROUND_MAGIC;
-  double r = __builtin_fma(-q, AW_PI64_A, x);
-  r = __builtin_fma(-q, AW_PI64_B, r);
-  const uint32_t k = (uint32_t)__double2loint(t) & (AW_TAB_N - 1);
-  const double2 e = tab[k];
+  double r = __builtin_fma(-q, AW_PI2K_A, x);
+  r = __builtin_fma(-q, AW_PI2K_B, r);
+  const double2 e = *(const double2 *)((const char *)tab + tab_offset(t));
   const double u = r * r;
-  double ps = __builtin_fma(AW_TSIN_C[2], u, AW_TSIN_C[1]);
-  ps = __builtin_fma(ps, u, AW_TSIN_C[0]);
-  const double sr = __builtin_fma(r * u, ps, r);
-  double pc = __builtin_fma(AW_TCOS_C[2], u, AW_TCOS_C[1]);
-  pc = __builtin_fma(pc, u, AW_TCOS_C[0]);
+  const double sr = __builtin_fma(r * u, AW_TSIN_C0, r);
+  const double pc = __builtin_fma(AW_TCOS_C[1], u, AW_TCOS_C[0]);
   const double cr = __builtin_fma(u, pc, 1.0);
   SinCosT o;
   o.s = __builtin_fma(e.x, cr, e.y * sr);
@@ -96,62 +106,14 @@ __device__ __forceinline__ SinCosT sincos_tab(double x, const double2 *__restric
 }
 
 // FP64 operation counts of one sincos_tab.
-constexpr int SCT_FMA = 1 + 2 + 2 + 1 + 2 + 1 + 2;
+constexpr int SCT_FMA = 1 + 2 + 1 + 2 + 2;
 constexpr int SCT_MUL = 4;  // r*r, r*u, and one product per rotated output
 constexpr int SCT_ADD = 1;
 
-// Fill a block's LDS copy of the (sin, cos)(k pi/64) table; every thread of
+// Fill a block's LDS copy of the (sin, cos)(k pi/2048) table; every thread of
 // the block must call this before any of them returns.
 __device__ __forceinline__ void load_sincos_table(double2 *tab) {
   for (int i = threadIdx.x; i < AW_TAB_N; i += blockDim.x) tab[i] = make_double2(AW_TAB_SC[2 * i], AW_TAB_SC[2 * i + 1]);
-  __syncthreads();
-}
-
-// ---------------------------------------------------------------------------
-// The same with a 4096-entry table (the propagation kernels): x = q pi/2048 + r,
-// |r| <= pi/4096, k = q mod 4096, (S, C) = (sin, cos)(k pi/2048).  The small
-// |r| leaves one coefficient for sin r and two for cos r, and the table's byte
-// offset 16 k is the low word of t shifted left by 4 and cut to 16 bits, which
-// one SDWA shift does (dst_sel WORD_0 with zero padding), so the offset is
-// below 64 KB whatever t holds and the read stays inside the table.  Declared
-// as a kernel's first LDS object, the table sits at address 0 and the offset
-// is the address.  8 FMA, 4 MUL, 1 ADD, one integer instruction and one
-// 16-byte LDS read.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t ltab_offset(double t) {
-  uint32_t a;
-  asm("v_lshlrev_b32_sdwa %0, 4, %1 dst_sel:WORD_0 dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:DWORD"
-      : "=v"(a)
-      : "v"((uint32_t)__double2loint(t)));
-  return a;
-}
-
-__device__ __forceinline__ SinCosT sincos_ltab(double x, const double2 *__restrict__ tab) {
-  const double t = __builtin_fma(x, AW_INV_PI2K, AW_ROUND_MAGIC);
-  const double q = t - AW_ROUND_MAGIC;
-  double r = __builtin_fma(-q, AW_PI2K_A, x);
-  r = __builtin_fma(-q, AW_PI2K_B, r);
-  const double2 e = *(const double2 *)((const char *)tab + ltab_offset(t));
-  const double u = r * r;
-  const double sr = __builtin_fma(r * u, AW_LSIN_C0, r);
-  const double pc = __builtin_fma(AW_LCOS_C[1], u, AW_LCOS_C[0]);
-  const double cr = __builtin_fma(u, pc, 1.0);
-  SinCosT o;
-  o.s = __builtin_fma(e.x, cr, e.y * sr);
-  o.c = __builtin_fma(e.y, cr, -(e.x * sr));
-  return o;
-}
-
-// FP64 operation counts of one sincos_ltab.
-constexpr int SCL_FMA = 1 + 2 + 1 + 2 + 2;
-constexpr int SCL_MUL = 4;  // r*r, r*u, and one product per rotated output
-constexpr int SCL_ADD = 1;
-
-// Fill a block's LDS copy of the (sin, cos)(k pi/2048) table; every thread of
-// the block must call this before any of them returns.
-__device__ __forceinline__ void load_sincos_ltable(double2 *tab) {
-  for (int i = threadIdx.x; i < AW_LTAB_N; i += blockDim.x)
-    tab[i] = make_double2(AW_LTAB_SC[2 * i], AW_LTAB_SC[2 * i + 1]);
   __syncthreads();
 }
 
@@ -182,22 +144,16 @@ struct Orbit {
 };
 
 // Kick with weight a2 = 2 t eps, a4 = 4 t eps, sines and cosines from the
-// block's LDS table (true values: no sign folding): the 4096-entry table when
-// LTAB (the propagation kernels), else the 128-entry one (the adjoints).  Every force and Hessian
+// block's LDS table (true values: no sign folding).  Every force and Hessian
 // term of eq. 2 is a product of one x factor, one y factor and z factors:
 //   e1 = 2 t eps cz^2, e2 = 4 t eps cz sz, e3 = 4 t eps (cz^2 - sz^2),
 //   P  += (e1 sx cy, e1 cx sy, e2 cx cy)                 (= -t eps grad Hp)
 //   dP += M dX, M = [[e1 cx cy, -e1 sx sy, -e2 sx cy],
 //                    [-e1 sx sy, e1 cx cy, -e2 cx sy],
 //                    [-e2 sx cy, -e2 cx sy, e3 cx cy]]     (= -t eps Hess Hp)
-template <bool TAN, bool LTAB>
+template <bool TAN>
 __device__ __forceinline__ void kick_tab(Orbit &o, double a2, double a4, const double2 *__restrict__ tab) {
-  SinCosT X, Y, Z;
-  if (LTAB) {
-    X = sincos_ltab(o.x, tab); Y = sincos_ltab(o.y, tab); Z = sincos_ltab(o.z, tab);
-  } else {
-    X = sincos_tab(o.x, tab); Y = sincos_tab(o.y, tab); Z = sincos_tab(o.z, tab);
-  }
+  const SinCosT X = sincos_tab(o.x, tab), Y = sincos_tab(o.y, tab), Z = sincos_tab(o.z, tab);
   const double cx = X.c, sx = X.s;
   const double cy = Y.c, sy = Y.s;
   const double cz2 = Z.c * Z.c;
@@ -243,10 +199,10 @@ __device__ __forceinline__ void drift(Orbit &o, double t) {
 }
 
 // Op counts of kick/drift (roofline accounting).
-template <bool TAN, bool LTAB> struct KickTabOps {
-  static constexpr int fma = 3 * (LTAB ? SCL_FMA : SCT_FMA) + 3 + (TAN ? 1 + 9 : 0);
-  static constexpr int mul = 3 * (LTAB ? SCL_MUL : SCT_MUL) + 7 + (TAN ? 7 : 0);
-  static constexpr int add = 3 * (LTAB ? SCL_ADD : SCT_ADD);
+template <bool TAN> struct KickTabOps {
+  static constexpr int fma = 3 * SCT_FMA + 3 + (TAN ? 1 + 9 : 0);
+  static constexpr int mul = 3 * SCT_MUL + 7 + (TAN ? 7 : 0);
+  static constexpr int add = 3 * SCT_ADD;
 };
 template <bool TAN> struct DriftOps {
   static constexpr int fma = TAN ? 6 : 3;

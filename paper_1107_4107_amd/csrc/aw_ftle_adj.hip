@@ -59,11 +59,11 @@ __device__ __forceinline__ void tan_step(Orbit &o, const AdjDesc &d, const doubl
 #pragma unroll
     for (int i = 0; i < NK; ++i) {
       drift<true>(o, d.drift[F::drift_idx[i]]);
-      kick_tab<true, false>(o, d.ka2[F::kick_idx[i]], d.ka4[F::kick_idx[i]], tab);
+      kick_tab<true>(o, d.ka2[F::kick_idx[i]], d.ka4[F::kick_idx[i]], tab);
     }
     drift<true>(o, d.drift[F::drift_idx[NK]]);
   } else {
-    kick_tab<true, false>(o, d.ka2[0], d.ka4[0], tab);
+    kick_tab<true>(o, d.ka2[0], d.ka4[0], tab);
     drift<true>(o, d.drift[0]);
   }
 }
@@ -230,7 +230,7 @@ __device__ __forceinline__ int rescale_exponent(const Orbit &o) {
 }
 
 template <int FORM>
-__global__ __launch_bounds__(256) void k_ftle_fwd(FtleDesc d) {
+__global__ __launch_bounds__(512) void k_ftle_fwd(FtleDesc d) {
   __shared__ double2 s_tab[AW_TAB_N];
   load_sincos_table(s_tab);
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(256) void k_ftle_fwd(FtleDesc d) {
 }
 
 template <int FORM>
-__global__ __launch_bounds__(256) void k_ftle_bwd(FtleDesc d) {
+__global__ __launch_bounds__(512) void k_ftle_bwd(FtleDesc d) {
   __shared__ double2 s_tab[AW_TAB_N];
   load_sincos_table(s_tab);
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -318,7 +318,7 @@ __global__ __launch_bounds__(256) void k_ftle_bwd(FtleDesc d) {
 }
 
 template <int FORM>
-__global__ __launch_bounds__(256) void k_ftle_bwd_rev(FtleDesc d) {
+__global__ __launch_bounds__(512) void k_ftle_bwd_rev(FtleDesc d) {
   __shared__ double2 s_tab[AW_TAB_N];
   load_sincos_table(s_tab);
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -374,7 +374,7 @@ __global__ __launch_bounds__(256) void k_ftle_bwd_rev(FtleDesc d) {
 
 hipError_t launch_ftle_backward_reversible(const FtleDesc &d, int form, const Tuning &t, hipStream_t s) {
   if (d.N <= 0) return hipSuccess;
-  const int tb = block_256(t);
+  const int tb = t.block;
   const unsigned blocks = (unsigned)((d.N + tb - 1) / tb);
   switch (form) {
   case 1: hipLaunchKernelGGL(k_ftle_bwd_rev<1>, dim3(blocks), dim3(tb), 0, s, d); break;
@@ -389,7 +389,7 @@ hipError_t launch_ftle_backward_reversible(const FtleDesc &d, int form, const Tu
 
 hipError_t launch_ftle_forward(const FtleDesc &d, int form, const Tuning &t, hipStream_t s) {
   if (d.N <= 0) return hipSuccess;
-  const int tb = block_256(t);
+  const int tb = t.block;
   const unsigned blocks = (unsigned)((d.N + tb - 1) / tb);
   switch (form) {
   case 1: hipLaunchKernelGGL(k_ftle_fwd<1>, dim3(blocks), dim3(tb), 0, s, d); break;
@@ -404,7 +404,7 @@ hipError_t launch_ftle_forward(const FtleDesc &d, int form, const Tuning &t, hip
 
 hipError_t launch_ftle_backward(const FtleDesc &d, int form, const Tuning &t, hipStream_t s) {
   if (d.N <= 0) return hipSuccess;
-  const int tb = block_256(t);
+  const int tb = t.block;
   const unsigned blocks = (unsigned)((d.N + tb - 1) / tb);
   switch (form) {
   case 1: hipLaunchKernelGGL(k_ftle_bwd<1>, dim3(blocks), dim3(tb), 0, s, d); break;

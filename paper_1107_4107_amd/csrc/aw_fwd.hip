@@ -103,13 +103,13 @@ __device__ __forceinline__ void map_step(Orbit (&o)[OPL], const FwdDesc &d, cons
 #pragma unroll
       for (int j = 0; j < OPL; ++j) drift<TAN>(o[j], d.drift[F::drift_idx[i]]);
 #pragma unroll
-      for (int j = 0; j < OPL; ++j) kick_tab<TAN, true>(o[j], d.ka2[F::kick_idx[i]], d.ka4[F::kick_idx[i]], tab);
+      for (int j = 0; j < OPL; ++j) kick_tab<TAN>(o[j], d.ka2[F::kick_idx[i]], d.ka4[F::kick_idx[i]], tab);
     }
 #pragma unroll
     for (int j = 0; j < OPL; ++j) drift<TAN>(o[j], d.drift[F::drift_idx[NK]]);
   } else {
 #pragma unroll
-    for (int j = 0; j < OPL; ++j) kick_tab<TAN, true>(o[j], d.ka2[0], d.ka4[0], tab);
+    for (int j = 0; j < OPL; ++j) kick_tab<TAN>(o[j], d.ka2[0], d.ka4[0], tab);
 #pragma unroll
     for (int j = 0; j < OPL; ++j) drift<TAN>(o[j], d.drift[0]);
   }
@@ -381,8 +381,8 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first, cons
 // and time-window variants hold about twice the registers and keep 256.
 template <int FORM, bool TAN, int OPL, int UNR, bool FILT = false, bool WINV = false>
 __global__ __launch_bounds__((FILT || WINV) ? 256 : 512) void k_fwd(FwdDesc d) {
-  __shared__ double2 s_tab[AW_LTAB_N];
-  load_sincos_ltable(s_tab);
+  __shared__ double2 s_tab[AW_TAB_N];
+  load_sincos_table(s_tab);
   const int64_t first = (int64_t)blockIdx.x * blockDim.x * OPL;
   run_orbits<FORM, TAN, OPL, UNR, FILT, WINV>(d, first, s_tab);
 }
@@ -393,9 +393,9 @@ template <int FORM, bool TAN, int OPL>
 __global__ __launch_bounds__(256) void k_fwd_persist(const FwdDesc *__restrict__ descs,
                                                      const WorkItem *__restrict__ items,
                                                      int32_t n_items, uint32_t *head) {
-  __shared__ double2 s_tab[AW_LTAB_N];
+  __shared__ double2 s_tab[AW_TAB_N];
   __shared__ int32_t s_item;
-  load_sincos_ltable(s_tab);
+  load_sincos_table(s_tab);
   for (;;) {
     if (threadIdx.x == 0) s_item = (int32_t)atomicAdd(head, 1u);
     __syncthreads();
@@ -533,9 +533,9 @@ void step_op_counts(int form, bool tan, int64_t *fma, int64_t *mul, int64_t *add
   case 7: nk = 7; nd = 8; break;
   default: break;
   }
-  const int kf = tan ? KickTabOps<true, true>::fma : KickTabOps<false, true>::fma;
-  const int km = tan ? KickTabOps<true, true>::mul : KickTabOps<false, true>::mul;
-  const int ka = tan ? KickTabOps<true, true>::add : KickTabOps<false, true>::add;
+  const int kf = tan ? KickTabOps<true>::fma : KickTabOps<false>::fma;
+  const int km = tan ? KickTabOps<true>::mul : KickTabOps<false>::mul;
+  const int ka = tan ? KickTabOps<true>::add : KickTabOps<false>::add;
   const int df = tan ? DriftOps<true>::fma : DriftOps<false>::fma;
   *fma = (int64_t)nk * kf + (int64_t)nd * df + 3;  // + 3 fma of the J accumulator
   *mul = (int64_t)nk * km;

@@ -18,8 +18,9 @@ struct Tuning {
 };
 
 // Kernels bounded at 256 lanes per block (the window-test and time-window
-// propagation, the batched persistent kernel and the adjoints) run a larger
-// requested block as 256.  No result depends on the block.
+// propagation and the batched persistent kernel, whose register counts leave
+// room for no more) run a larger requested block as 256.  No result depends
+// on the block.
 inline int block_256(const Tuning &t) { return t.block < 256 ? t.block : 256; }
 
 // Propagation.
