@@ -236,7 +236,7 @@ def run_slice(args, aw, wl, torch):
     rec = base_record(N * T * args.steps / elapsed, args.steps, args.warmup, elapsed / args.steps * 1e3)
     rec["config"] = {"workload": f"{args.workload}: {desc}", "eps": ens.eps, "grid": [ens.nx, ens.ny],
                      "n_orbits": N, "n_steps": T, "h": ens.h, "map": ens.map_form, "tangent": True,
-                     "tuning": {"block": args.block, "orbits_per_lane": args.opl, "unroll": args.unroll}}
+                     "tuning": {"block": args.block or "auto", "orbits_per_lane": args.opl, "unroll": args.unroll}}
     rec["roofline"] = roofline(aw, ens, kern_ms / max(launches, 1), args.workload)
     rec["chaotic_fraction"] = n_chaotic / N
     return rec, ens
@@ -653,7 +653,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-1core", action="store_true",
                     help="also time the oracle on one host thread (cpu_baseline_1core)")
-    ap.add_argument("--block", type=int, default=512)
+    ap.add_argument("--block", type=int, default=0, help="lanes per block; 0 = the library's automatic choice")
     ap.add_argument("--opl", type=int, default=1)
     ap.add_argument("--unroll", type=int, default=1)
     ap.add_argument("--copy-mib", type=int, default=0,

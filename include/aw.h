@@ -142,12 +142,14 @@ typedef struct {
   double cloud[4];        /* CLOUD: centre (vx, vy) and standard deviations (sigma_x, sigma_y) */
 } aw_ensemble;
 
-/* Launch shape.  NULL or zero fields = defaults (block 512, one orbit per
- * lane, step loop not unrolled, renormalisation every 8 steps).  block in
- * {64, 128, 256, 512}: the kernels hold a 64 KB sine/cosine table per block,
- * so blocks of 512 lanes are needed for a full CU; the window-test and
- * time-window propagation and the batched persistent launch run a block above
- * 256 as 256.  orbits_per_lane in {1, 2}; unroll in {1, 2};
+/* Launch shape.  NULL or zero fields = defaults (automatic block, one orbit
+ * per lane, step loop not unrolled, renormalisation every 8 steps).  block in
+ * {0, 64, 128, 256, 512}: the kernels hold a 64 KB sine/cosine table per
+ * block, so blocks of 512 lanes are needed for a full CU; 0 picks 512 when
+ * the ensemble gives every CU at least one such block, else the largest of
+ * 256, 128 and 64 that still does.  The window-test and time-window
+ * propagation and the batched persistent launch run a block above 256 (or
+ * automatic) as 256.  orbits_per_lane in {1, 2}; unroll in {1, 2};
  * renorm_every in {1, 2, 4, 8, 16}.  persistent_wgs: workgroups of the batched
  * persistent launch (0 = auto). */
 typedef struct {

@@ -121,7 +121,8 @@ class Ensemble:
 
 @dataclass
 class Tuning:
-    """Launch shape (aw_tuning); zeros mean library defaults (block 512)."""
+    """Launch shape (aw_tuning); zeros mean library defaults (block 0: chosen
+    from the ensemble size, 512 for large ensembles)."""
     block: int = 0
     orbits_per_lane: int = 1
     unroll: int = 1

@@ -231,7 +231,7 @@ __global__ __launch_bounds__(512) void k_adj_bwd(AdjDesc d) {
 
 hipError_t launch_adj_forward(const AdjDesc &d, int form, const Tuning &t, hipStream_t s) {
   if (d.N <= 0) return hipSuccess;
-  const int tb = t.block;
+  const int tb = block_for(t, d.N);
   const unsigned blocks = (unsigned)((d.N + tb - 1) / tb);
   switch (form) {
   case 1: hipLaunchKernelGGL(k_adj_fwd<1>, dim3(blocks), dim3(tb), 0, s, d); break;
@@ -246,7 +246,7 @@ hipError_t launch_adj_forward(const AdjDesc &d, int form, const Tuning &t, hipSt
 
 hipError_t launch_adj_backward_reversible(const AdjDesc &d, int form, const Tuning &t, hipStream_t s) {
   if (d.N <= 0) return hipSuccess;
-  const int tb = t.block;
+  const int tb = block_for(t, d.N);
   const unsigned blocks = (unsigned)((d.N + tb - 1) / tb);
   switch (form) {
   case 1: hipLaunchKernelGGL(k_adj_bwd_rev<1>, dim3(blocks), dim3(tb), 0, s, d); break;
@@ -261,7 +261,7 @@ hipError_t launch_adj_backward_reversible(const AdjDesc &d, int form, const Tuni
 
 hipError_t launch_adj_backward(const AdjDesc &d, int form, const Tuning &t, hipStream_t s) {
   if (d.N <= 0) return hipSuccess;
-  const int tb = t.block;
+  const int tb = block_for(t, d.N);
   const unsigned blocks = (unsigned)((d.N + tb - 1) / tb);
   switch (form) {
   case 1: hipLaunchKernelGGL(k_adj_bwd<1>, dim3(blocks), dim3(tb), 0, s, d); break;

@@ -196,13 +196,13 @@ bool is_fin(double v) { return std::isfinite(v); }
 aw_status check_tuning(const aw_tuning *t, Tuning &out) {
   out = Tuning{};
   if (!t) return AW_OK;
-  out.block = t->block ? t->block : 512;
+  out.block = t->block;
   out.opl = t->orbits_per_lane ? t->orbits_per_lane : 1;
   out.unroll = t->unroll ? t->unroll : 1;
   out.renorm = t->renorm_every ? t->renorm_every : 8;
   out.pwgs = t->persistent_wgs;
-  if (out.block != 64 && out.block != 128 && out.block != 256 && out.block != 512)
-    return fail(AW_EINVAL, "tuning.block must be 64, 128, 256 or 512 (got %d)", out.block);
+  if (out.block != 0 && out.block != 64 && out.block != 128 && out.block != 256 && out.block != 512)
+    return fail(AW_EINVAL, "tuning.block must be 0 (automatic), 64, 128, 256 or 512 (got %d)", out.block);
   if (out.opl != 1 && out.opl != 2) return fail(AW_EINVAL, "tuning.orbits_per_lane must be 1 or 2");
   if (out.unroll != 1 && out.unroll != 2) return fail(AW_EINVAL, "tuning.unroll must be 1 or 2");
   if (out.renorm < 1 || out.renorm > 16 || (out.renorm & (out.renorm - 1)))

@@ -374,7 +374,7 @@ __global__ __launch_bounds__(512) void k_ftle_bwd_rev(FtleDesc d) {
 
 hipError_t launch_ftle_backward_reversible(const FtleDesc &d, int form, const Tuning &t, hipStream_t s) {
   if (d.N <= 0) return hipSuccess;
-  const int tb = t.block;
+  const int tb = block_for(t, d.N);
   const unsigned blocks = (unsigned)((d.N + tb - 1) / tb);
   switch (form) {
   case 1: hipLaunchKernelGGL(k_ftle_bwd_rev<1>, dim3(blocks), dim3(tb), 0, s, d); break;
@@ -389,7 +389,7 @@ hipError_t launch_ftle_backward_reversible(const FtleDesc &d, int form, const Tu
 
 hipError_t launch_ftle_forward(const FtleDesc &d, int form, const Tuning &t, hipStream_t s) {
   if (d.N <= 0) return hipSuccess;
-  const int tb = t.block;
+  const int tb = block_for(t, d.N);
   const unsigned blocks = (unsigned)((d.N + tb - 1) / tb);
   switch (form) {
   case 1: hipLaunchKernelGGL(k_ftle_fwd<1>, dim3(blocks), dim3(tb), 0, s, d); break;
@@ -404,7 +404,7 @@ hipError_t launch_ftle_forward(const FtleDesc &d, int form, const Tuning &t, hip
 
 hipError_t launch_ftle_backward(const FtleDesc &d, int form, const Tuning &t, hipStream_t s) {
   if (d.N <= 0) return hipSuccess;
-  const int tb = t.block;
+  const int tb = block_for(t, d.N);
   const unsigned blocks = (unsigned)((d.N + tb - 1) / tb);
   switch (form) {
   case 1: hipLaunchKernelGGL(k_ftle_bwd<1>, dim3(blocks), dim3(tb), 0, s, d); break;

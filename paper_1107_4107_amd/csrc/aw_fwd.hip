@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "aw_device.hpp"
 #include "aw_internal.hpp"
 #include "aw_launch.hpp"
@@ -432,16 +434,28 @@ __global__ void k_gen_ic(FwdDesc d, double *ic, double *w0) {
 // ---------------------------------------------------------------------------
 // Host-side launchers.
 // ---------------------------------------------------------------------------
+int block_for(const Tuning &t, int64_t n) {
+  if (t.block) return t.block;
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+    ncu = 256;
+  int b = 512;
+  while (b > 64 && (int64_t)b * ncu > n) b >>= 1;
+  return b;
+}
+
 template <int FORM, bool TAN>
 static hipError_t fwd_dispatch_opl(const FwdDesc &d, const Tuning &t, hipStream_t s) {
-  const int64_t per_block = (int64_t)t.block * t.opl;
+  const int lanes = block_for(t, (d.N + t.opl - 1) / t.opl);
+  const int64_t per_block = (int64_t)lanes * t.opl;
   const int64_t blocks = (d.N + per_block - 1) / per_block;
   if (blocks <= 0) return hipSuccess;
-  dim3 grid((unsigned)blocks), block((unsigned)t.block);
+  dim3 grid((unsigned)blocks), block((unsigned)lanes);
   if (d.filter || d.window_v) {
     // The window test and the time-window velocity run with one orbit per
     // lane, no unrolling and at most 256 lanes per block.
-    const int wb = block_256(t);
+    const int wb = std::min(block_for(t, d.N), 256);
     const dim3 wgrid((unsigned)((d.N + wb - 1) / wb));
     block = dim3((unsigned)wb);
     if (d.filter && d.window_v) hipLaunchKernelGGL((k_fwd<FORM, TAN, 1, 1, true, true>), wgrid, block, 0, s, d);

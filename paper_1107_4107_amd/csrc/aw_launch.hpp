@@ -10,18 +10,26 @@
 namespace aw {
 
 struct Tuning {
-  int block = 512;
+  int block = 0;  // 0: automatic (block_for)
   int opl = 1;
   int unroll = 1;
   int renorm = 8;
   int pwgs = 0;
 };
 
+// Lanes per block for a launch over n orbits (or lanes).  A block set in the
+// tuning is used as is.  Automatic: 512 when every CU gets at least one block
+// of 512 (a block holds the 64 KB sine/cosine table, so two blocks share a CU,
+// and it takes two of 512 lanes to fill it at four waves per SIMD); below
+// that the largest of 256, 128 and 64 that still gives every CU a block, so
+// that small ensembles spread over the whole chip.  No result depends on the
+// block.
+int block_for(const Tuning &t, int64_t n);
+
 // Kernels bounded at 256 lanes per block (the window-test and time-window
 // propagation and the batched persistent kernel, whose register counts leave
-// room for no more) run a larger requested block as 256.  No result depends
-// on the block.
-inline int block_256(const Tuning &t) { return t.block < 256 ? t.block : 256; }
+// room for no more) run a larger or automatic block as 256.
+inline int block_256(const Tuning &t) { return (t.block == 0 || t.block > 256) ? 256 : t.block; }
 
 // Propagation.
 hipError_t launch_fwd(const FwdDesc &d, const Tuning &t, int form, bool tan, hipStream_t s);
