@@ -95,8 +95,16 @@ __device__ __forceinline__ void gen_w0(uint64_t seed, int64_t n, double w[6]) {
 // (symmetric compositions), or kick-then-drift (coupled standard map).  The
 // kicks take their sines and cosines from the block's LDS table `tab`.
 // ---------------------------------------------------------------------------
+// The distinct stage weights of the form, copied from the descriptor before
+// the step loop.
+struct StepWeights {
+  double drift[MAX_UNIQUE];
+  double ka2[MAX_UNIQUE];
+  double ka4[MAX_UNIQUE];
+};
+
 template <int FORM, bool TAN, int OPL>
-__device__ __forceinline__ void map_step(Orbit (&o)[OPL], const FwdDesc &d, const double2 *__restrict__ tab) {
+__device__ __forceinline__ void map_step(Orbit (&o)[OPL], const StepWeights &d, const double2 *__restrict__ tab) {
   using F = FormPattern<FORM>;
   constexpr int NK = F::NK;
   if constexpr (F::LEAD) {
@@ -163,6 +171,7 @@ constexpr double LN2 = 0x1.62e42fefa39efp-1;
 // window of width w <= pi, phi is inside iff e0 x d >= 0 and d x e1 >= 0; for
 // w > pi, iff d is not strictly inside the complementary sector.
 __device__ __forceinline__ bool in_window(double px, double py, double pz, const FwdDesc &d) {
+#pragma clang fp contract(off)
   bool ok = true;
   if (d.win_phi != 0) {
     const double c0 = d.e0x * py - d.e0y * px;   // e0 x d
@@ -246,8 +255,28 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first, cons
   // will not unroll with a remainder.
   const int64_t k0 = d.k_begin, k1 = d.k_end;
   const int64_t mask = d.renorm_mask;
+  // Stage weights.  In the plain tangent kernel the kick weights move into
+  // VGPRs (an empty asm the compiler must treat as producing per-lane
+  // values): across the loop the descriptor fields of the epilogue hold most
+  // SGPRs, and kick weights left there are spilled to VGPR lanes and read back
+  // with v_readlane every step, 16 VALU instructions per S6 step and 32 per Y6
+  // step.  In VGPRs they cost 16 registers (111 -> 127, still four waves per
+  // SIMD) and no instruction.  The unrolled, two-orbit and window variants
+  // would lose occupancy and keep them in SGPRs.
+  constexpr bool kVregW = TAN && OPL == 1 && UNR == 1 && !FILT && !WINV;
+  StepWeights sw;
+#pragma unroll
+  for (int q = 0; q < MAX_UNIQUE; ++q) {
+    sw.drift[q] = d.drift[q];
+    sw.ka2[q] = d.ka2[q];
+    sw.ka4[q] = d.ka4[q];
+    if (kVregW) {
+      asm volatile("" : "+v"(sw.ka2[q]));
+      asm volatile("" : "+v"(sw.ka4[q]));
+    }
+  }
   auto one_step = [&](int64_t k) {
-    map_step<FORM, TAN, OPL>(o, d, tab);
+    map_step<FORM, TAN, OPL>(o, sw, tab);
 #pragma unroll
     for (int j = 0; j < OPL; ++j) accum_j(o[j]);
     if (FILT) {
@@ -298,10 +327,15 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first, cons
     return;
   }
 
-  // Final launch: per-orbit observables.
+  // Final launch: per-orbit observables.  Contraction is off so that every
+  // kernel variant rounds the sums of products below (L, dP^2, the energies)
+  // the same way: whether the compiler fuses a*b + c depends on the code
+  // around it, and the results are to be bitwise independent of the launch
+  // shape and of batching.
   uint32_t n_chaotic = 0;
 #pragma unroll
   for (int j = 0; j < OPL; ++j) {
+#pragma clang fp contract(off)
     const int64_t N = d.N, m = n[j];
     double s0[6];
     gen_ic(d, m, s0);
