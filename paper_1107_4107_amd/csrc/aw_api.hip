@@ -508,6 +508,7 @@ aw_status hist_scratch(DevScratch &sc, const HistPlan &p, int64_t n_items, bool 
   w.block_counts = (uint32_t *)sc.block_counts.p;
   w.block_dropped = (uint32_t *)sc.block_dropped.p;
   w.tile_start = (uint32_t *)sc.tile_start.p;
+  w.tile_total = w.tile_start + p.n_tiles + 1;
   w.sorted_local = (uint16_t *)sc.sorted_local.p;
   w.sorted_val = want_vals ? (double *)sc.sorted_val.p : nullptr;
   return AW_OK;

@@ -3,8 +3,9 @@
 // The W x H image (512 x 512 for the large ensemble: 3 MB of counts and
 // sums) does not fit in the 160 KB LDS of a CU, so the reduction is:
 //   1. count   : each block counts its items per image tile in LDS;
-//   2. scan    : one workgroup turns the (tile, block) counts, tile-major, into
-//                offsets, so every tile's items become one contiguous range;
+//   2. scan    : one workgroup per tile turns its row of per-block counts into
+//                offsets within the tile, and one more scans the tile totals,
+//                so every tile's items become one contiguous range;
 //   3. scatter : each block moves its items to their tile's range (LDS cursors);
 //   4. accumulate: one workgroup per tile adds its items into a TILE_W x TILE_H
 //                tile of counts (ds_add_u32) and sums (ds_add_f64) held in LDS
@@ -99,21 +100,60 @@ __global__ __launch_bounds__(HIST_BLOCK) void k_tile_count(int64_t N, const uint
   if (threadIdx.x == 0) block_dropped[blockIdx.x] = drop;
 }
 
-// 2. Exclusive scan of the tile-major counts (one workgroup of 1024 lanes).
-//    tile_start[t] = first sorted position of tile t; tile_start[n_tiles] = kept.
-__global__ __launch_bounds__(1024) void k_tile_scan(int64_t n_entries, uint32_t *__restrict__ counts,
-                                                    int32_t n_tiles, int32_t G,
-                                                    const uint32_t *__restrict__ block_dropped,
-                                                    uint32_t *__restrict__ tile_start,
-                                                    uint64_t *__restrict__ dropped_out) {
+// 2a. Exclusive scan of one tile's row of per-block counts, in place (one
+//     workgroup per tile; the row is read and written in coalesced chunks of
+//     SCAN_BLOCK entries, scanned by wave shuffles); the row total goes to
+//     tile_total[t].
+__global__ __launch_bounds__(SCAN_BLOCK) void k_tile_scan_rows(uint32_t *__restrict__ counts, int32_t G,
+                                                               uint32_t *__restrict__ tile_total) {
+  constexpr int NW = SCAN_BLOCK / 64;
+  __shared__ uint32_t wsum[NW];
+  uint32_t *row = counts + (int64_t)blockIdx.x * G;
+  const int lane = (int)__lane_id(), wv = (int)(threadIdx.x >> 6);
+  uint32_t carry = 0;
+  for (int32_t base = 0; base < G; base += SCAN_BLOCK) {
+    const int32_t e = base + (int32_t)threadIdx.x;
+    const uint32_t v = e < G ? row[e] : 0u;
+    uint32_t x = v;  // inclusive scan within the wave
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    uint32_t before = carry, total = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      before += k < wv ? wsum[k] : 0u;
+      total += wsum[k];
+    }
+    if (e < G) row[e] = before + x - v;
+    carry += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) tile_total[blockIdx.x] = carry;
+}
+
+// 2b. Exclusive scan of the tile totals and the count of dropped items (one
+//     workgroup of 1024 lanes): tile_start[t] = first sorted position of tile
+//     t; tile_start[n_tiles] = items kept.
+__global__ __launch_bounds__(1024) void k_tile_scan_tiles(const uint32_t *__restrict__ tile_total, int32_t n_tiles,
+                                                          const uint32_t *__restrict__ block_dropped, int32_t G,
+                                                          uint32_t *__restrict__ tile_start,
+                                                          uint64_t *__restrict__ dropped_out) {
   __shared__ uint32_t part[1024];
+  __shared__ uint64_t dsum[1024];
   const int tid = threadIdx.x;
-  const int64_t per = (n_entries + 1023) / 1024;
-  const int64_t beg = tid * per;
-  const int64_t end = beg + per < n_entries ? beg + per : n_entries;
+  const int per = (n_tiles + 1023) / 1024;
+  const int beg = tid * per;
+  const int end = beg + per < n_tiles ? beg + per : n_tiles;
   uint32_t s = 0;
-  for (int64_t e = beg; e < end; ++e) s += counts[e];
+  for (int t = beg; t < end; ++t) s += tile_total[t];
   part[tid] = s;
+  uint64_t d = 0;
+  for (int b = tid; b < G; b += 1024) d += block_dropped[b];
+  dsum[tid] = d;
   __syncthreads();
   // Hillis-Steele inclusive scan of the 1024 partial sums.
   for (int off = 1; off < 1024; off <<= 1) {
@@ -123,28 +163,29 @@ __global__ __launch_bounds__(1024) void k_tile_scan(int64_t n_entries, uint32_t 
     __syncthreads();
   }
   uint32_t run = tid > 0 ? part[tid - 1] : 0u;
-  for (int64_t e = beg; e < end; ++e) {
-    const uint32_t c = counts[e];
-    counts[e] = run;
-    if (e % G == 0) tile_start[e / G] = run;
-    run += c;
+  for (int t = beg; t < end; ++t) {
+    tile_start[t] = run;
+    run += tile_total[t];
   }
   if (tid == 1023) tile_start[n_tiles] = part[1023];
-  if (tid == 0 && dropped_out) {
-    uint64_t d = 0;
-    for (int b = 0; b < G; ++b) d += block_dropped[b];
-    *dropped_out = d;
+  // Tree sum of the dropped counts.
+  for (int off = 512; off > 0; off >>= 1) {
+    if (tid < off) dsum[tid] += dsum[tid + off];
+    __syncthreads();
   }
+  if (tid == 0 && dropped_out) *dropped_out = dsum[0];
 }
 
 // 3. Move each block's items to their tile ranges.
 __global__ __launch_bounds__(HIST_BLOCK) void k_tile_scatter(int64_t N, const uint32_t *__restrict__ bins,
                                                              const double *__restrict__ vals, TileGeom g,
                                                              int32_t G, const uint32_t *__restrict__ offsets,
+                                                             const uint32_t *__restrict__ tile_start,
                                                              uint16_t *__restrict__ sorted_local,
                                                              double *__restrict__ sorted_val) {
   __shared__ uint32_t cur[MAX_TILES];
-  for (int t = threadIdx.x; t < g.n_tiles; t += blockDim.x) cur[t] = offsets[(int64_t)t * G + blockIdx.x];
+  for (int t = threadIdx.x; t < g.n_tiles; t += blockDim.x)
+    cur[t] = tile_start[t] + offsets[(int64_t)t * G + blockIdx.x];
   __syncthreads();
   const int64_t beg = (int64_t)blockIdx.x * HIST_ITEMS_PER_BLOCK;
   const int64_t end = beg + HIST_ITEMS_PER_BLOCK < N ? beg + HIST_ITEMS_PER_BLOCK : N;
@@ -161,7 +202,8 @@ __global__ __launch_bounds__(HIST_BLOCK) void k_tile_scatter(int64_t N, const ui
 
 // 4. One workgroup per tile: LDS accumulation, then the tile is written out.
 //    mode 0: counts + sums; 1: counts + mean; 2: counts + density (count*norm).
-__global__ __launch_bounds__(HIST_BLOCK) void k_tile_accum(const uint32_t *__restrict__ tile_start,
+//    Each lane takes four items per pass so that four loads are in flight.
+__global__ __launch_bounds__(ACC_BLOCK) void k_tile_accum(const uint32_t *__restrict__ tile_start,
                                                            const uint16_t *__restrict__ sorted_local,
                                                            const double *__restrict__ sorted_val,
                                                            TileGeom g, int32_t mode, double norm, int32_t accumulate,
@@ -177,7 +219,24 @@ __global__ __launch_bounds__(HIST_BLOCK) void k_tile_accum(const uint32_t *__res
   __syncthreads();
   const uint32_t beg = tile_start[t], end = tile_start[t + 1];
   const bool have_vals = sorted_val != nullptr;
-  for (uint32_t p = beg + threadIdx.x; p < end; p += blockDim.x) {
+  const uint32_t bd = blockDim.x;
+  uint32_t p = beg + threadIdx.x;
+  for (; p + 3 * bd < end; p += 4 * bd) {
+    int loc[4];
+    double val[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) loc[k] = sorted_local[p + k * bd];
+    if (have_vals) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) val[k] = sorted_val[p + k * bd];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      atomicAdd(&c[loc[k]], 1u);
+      if (have_vals) atomicAdd(&s[loc[k]], val[k]);
+    }
+  }
+  for (; p < end; p += bd) {
     const int loc = sorted_local[p];
     atomicAdd(&c[loc], 1u);
     if (have_vals) atomicAdd(&s[loc], sorted_val[p]);
@@ -225,7 +284,7 @@ HistPlan hist_plan(int64_t N, int W, int H) {
   if (p.G < 1) p.G = 1;
   p.bytes_block_counts = sizeof(uint32_t) * (size_t)p.n_tiles * (size_t)p.G;
   p.bytes_block_dropped = sizeof(uint32_t) * (size_t)p.G;
-  p.bytes_tile_start = sizeof(uint32_t) * (size_t)(p.n_tiles + 1);
+  p.bytes_tile_start = sizeof(uint32_t) * (size_t)(2 * p.n_tiles + 1);  // tile_start, then tile_total
   p.bytes_sorted_local = sizeof(uint16_t) * (size_t)(N > 0 ? N : 1);
   p.bytes_sorted_val = sizeof(double) * (size_t)(N > 0 ? N : 1);
   return p;
@@ -244,12 +303,14 @@ hipError_t launch_hist_reduce(int64_t N, const uint32_t *bins, const double *val
     e = launch_zero_u32(w.block_dropped, p.G, s);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, (int64_t)p.n_tiles * p.G, w.block_counts,
-                     p.n_tiles, p.G, w.block_dropped, w.tile_start, dropped_out);
+  hipLaunchKernelGGL(k_tile_scan_rows, dim3((unsigned)p.n_tiles), dim3(SCAN_BLOCK), 0, s, w.block_counts, p.G,
+                     w.tile_total);
+  hipLaunchKernelGGL(k_tile_scan_tiles, dim3(1), dim3(1024), 0, s, w.tile_total, p.n_tiles, w.block_dropped, p.G,
+                     w.tile_start, dropped_out);
   if (N > 0)
     hipLaunchKernelGGL(k_tile_scatter, dim3((unsigned)p.G), dim3(HIST_BLOCK), 0, s, N, bins, vals, g, p.G,
-                       w.block_counts, w.sorted_local, vals ? w.sorted_val : nullptr);
-  hipLaunchKernelGGL(k_tile_accum, dim3((unsigned)p.n_tiles), dim3(HIST_BLOCK), 0, s, w.tile_start,
+                       w.block_counts, w.tile_start, w.sorted_local, vals ? w.sorted_val : nullptr);
+  hipLaunchKernelGGL(k_tile_accum, dim3((unsigned)p.n_tiles), dim3(ACC_BLOCK), 0, s, w.tile_start,
                      w.sorted_local, vals ? w.sorted_val : nullptr, g, mode, norm, accumulate, counts_out, f_out);
   return hipGetLastError();
 }

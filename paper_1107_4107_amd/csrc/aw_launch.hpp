@@ -51,7 +51,8 @@ struct HistPlan {
 struct HistScratch {
   uint32_t *block_counts = nullptr;
   uint32_t *block_dropped = nullptr;
-  uint32_t *tile_start = nullptr;
+  uint32_t *tile_start = nullptr;  // n_tiles + 1 entries
+  uint32_t *tile_total = nullptr;  // n_tiles entries (in the same buffer, after tile_start)
   uint16_t *sorted_local = nullptr;
   double *sorted_val = nullptr;
 };
