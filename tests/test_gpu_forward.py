@@ -137,6 +137,20 @@ def test_results_do_not_depend_on_the_launch_shape(aw, tun):
     np.testing.assert_array_equal(np_(got.state), np_(ref.state))
 
 
+@pytest.mark.parametrize("n", [1, 64, 65, 257])
+def test_automatic_block_on_tiny_ensembles(aw, n):
+    """The automatic block (64 lanes for ensembles this small) gives bitwise
+    the results of explicit blocks of 64 and 512, including a lone orbit and
+    a block with one active lane."""
+    print_case("automatic block", n)
+    e = slice_ens(aw, 2e-2, 0, 120, pz0=0.5, nx=n, ny=1)
+    ref = aw.map_ensemble(e, want_state=True)
+    for b in (64, 512):
+        got = aw.map_ensemble(e, want_state=True, tuning=aw.Tuning(block=b))
+        np.testing.assert_array_equal(np_(got.orbit_out), np_(ref.orbit_out))
+        np.testing.assert_array_equal(np_(got.state), np_(ref.state))
+
+
 def test_explicit_initial_conditions(aw):
     import torch
     print_case("explicit")
