@@ -200,6 +200,84 @@ __global__ __launch_bounds__(HIST_BLOCK) void k_tile_scatter(int64_t N, const ui
   }
 }
 
+// 3'. The same through LDS, for items with values and images of at most
+//     STAGE_MAX_TILES tiles (2-byte keys alone coalesce well enough): each
+//     round of STAGE_ITEMS items is counted and grouped by tile in LDS first,
+//     then every tile's run is written to consecutive positions, so that the
+//     stores fill whole lines instead of landing one item per line (written
+//     back as partial lines from several XCDs' L2s otherwise).
+__global__ __launch_bounds__(STAGE_BLOCK) void k_tile_scatter_staged(int64_t N, const uint32_t *__restrict__ bins,
+                                                                   const double *__restrict__ vals, TileGeom g,
+                                                                   int32_t G, const uint32_t *__restrict__ offsets,
+                                                                   const uint32_t *__restrict__ tile_start,
+                                                                   uint16_t *__restrict__ sorted_local,
+                                                                   double *__restrict__ sorted_val) {
+  constexpr int NW = STAGE_BLOCK / 64;
+  __shared__ double st_val[STAGE_ITEMS];
+  __shared__ uint32_t base[STAGE_MAX_TILES], lcnt[STAGE_MAX_TILES], lstart[STAGE_MAX_TILES];
+  __shared__ uint16_t st_local[STAGE_ITEMS], st_tile[STAGE_ITEMS];
+  __shared__ uint32_t wsum[NW];
+  const int nt = g.n_tiles;
+  const int tid = threadIdx.x, lane = (int)__lane_id(), wv = tid >> 6;
+  for (int t = tid; t < nt; t += blockDim.x) base[t] = tile_start[t] + offsets[(int64_t)t * G + blockIdx.x];
+  const int64_t beg = (int64_t)blockIdx.x * HIST_ITEMS_PER_BLOCK;
+  const int64_t end = beg + HIST_ITEMS_PER_BLOCK < N ? beg + HIST_ITEMS_PER_BLOCK : N;
+  for (int64_t r0 = beg; r0 < end; r0 += STAGE_ITEMS) {
+    const int64_t r1 = r0 + STAGE_ITEMS < end ? r0 + STAGE_ITEMS : end;
+    for (int t = tid; t < nt; t += blockDim.x) lcnt[t] = 0u;
+    __syncthreads();
+    for (int64_t n = r0 + tid; n < r1; n += blockDim.x) {
+      const uint32_t bin = bins[n];
+      if (bin == BIN_DROP) continue;
+      int tile, local;
+      tile_of(bin, g, tile, local);
+      atomicAdd(&lcnt[tile], 1u);
+    }
+    __syncthreads();
+    // Exclusive scan of the round's tile counts (nt <= STAGE_MAX_TILES = blockDim.x).
+    const uint32_t v = tid < nt ? lcnt[tid] : 0u;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    uint32_t before = 0, kept = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      before += k < wv ? wsum[k] : 0u;
+      kept += wsum[k];
+    }
+    if (tid < nt) {
+      lstart[tid] = before + x - v;
+      lcnt[tid] = 0u;  // reused as the round's cursor
+    }
+    __syncthreads();
+    for (int64_t n = r0 + tid; n < r1; n += blockDim.x) {
+      const uint32_t bin = bins[n];
+      if (bin == BIN_DROP) continue;
+      int tile, local;
+      tile_of(bin, g, tile, local);
+      const uint32_t slot = lstart[tile] + atomicAdd(&lcnt[tile], 1u);
+      st_local[slot] = (uint16_t)local;
+      st_tile[slot] = (uint16_t)tile;
+      if (vals) st_val[slot] = vals[n];
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < kept; i += blockDim.x) {
+      const int t = st_tile[i];
+      const uint32_t pos = base[t] + (i - lstart[t]);
+      sorted_local[pos] = st_local[i];
+      if (vals) sorted_val[pos] = st_val[i];
+    }
+    __syncthreads();
+    for (int t = tid; t < nt; t += blockDim.x) base[t] += lcnt[t];
+    __syncthreads();
+  }
+}
+
 // 4. One workgroup per tile: LDS accumulation, then the tile is written out.
 //    mode 0: counts + sums; 1: counts + mean; 2: counts + density (count*norm).
 //    Each lane takes four items per pass so that four loads are in flight.
@@ -307,7 +385,10 @@ hipError_t launch_hist_reduce(int64_t N, const uint32_t *bins, const double *val
                      w.tile_total);
   hipLaunchKernelGGL(k_tile_scan_tiles, dim3(1), dim3(1024), 0, s, w.tile_total, p.n_tiles, w.block_dropped, p.G,
                      w.tile_start, dropped_out);
-  if (N > 0)
+  if (N > 0 && vals && p.n_tiles <= STAGE_MAX_TILES)
+    hipLaunchKernelGGL(k_tile_scatter_staged, dim3((unsigned)p.G), dim3(STAGE_BLOCK), 0, s, N, bins, vals, g, p.G,
+                       w.block_counts, w.tile_start, w.sorted_local, vals ? w.sorted_val : nullptr);
+  else if (N > 0)
     hipLaunchKernelGGL(k_tile_scatter, dim3((unsigned)p.G), dim3(HIST_BLOCK), 0, s, N, bins, vals, g, p.G,
                        w.block_counts, w.tile_start, w.sorted_local, vals ? w.sorted_val : nullptr);
   hipLaunchKernelGGL(k_tile_accum, dim3((unsigned)p.n_tiles), dim3(ACC_BLOCK), 0, s, w.tile_start,

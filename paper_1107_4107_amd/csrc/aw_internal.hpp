@@ -120,6 +120,9 @@ constexpr int HIST_ITEMS_PER_BLOCK = 8192;  // items per block in count/scatter
 constexpr int ACC_BLOCK = 1024;             // lanes per tile in the accumulation
 constexpr int SCAN_BLOCK = 256;             // lanes per tile row in the scan
 constexpr int MAX_TILES = 8192;
+constexpr int STAGE_MAX_TILES = 1024;       // images up to this many tiles scatter through LDS
+constexpr int STAGE_ITEMS = 4096;           // items per LDS staging round
+constexpr int STAGE_BLOCK = 1024;
 
 // Adjoint descriptor.
 struct AdjDesc {
