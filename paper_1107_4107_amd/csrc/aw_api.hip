@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "aw.h"
+#include "aw_hist.hpp"
 #include "aw_internal.hpp"
 #include "aw_y6_coef.h"
 #include "aw_launch.hpp"

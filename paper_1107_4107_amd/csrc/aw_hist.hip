@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "aw_hist.hpp"
 #include "aw_internal.hpp"
 #include "aw_launch.hpp"
 
