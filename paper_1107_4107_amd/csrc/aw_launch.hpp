@@ -21,9 +21,9 @@ struct Tuning {
 // tuning is used as is.  Automatic: 512 when every CU gets at least one block
 // of 512 (a block holds the 64 KB sine/cosine table, so two blocks share a CU,
 // and it takes two of 512 lanes to fill it at four waves per SIMD); below
-// that the largest of 256, 128 and 64 that still gives every CU a block, so
-// that small ensembles spread over the whole chip.  No result depends on the
-// block.
+// that the largest of 256 and 128 that still gives every CU a block, else 64,
+// so that small ensembles spread over as much of the chip as they can.  No
+// result depends on the block.
 int block_for(const Tuning &t, int64_t n);
 
 // Kernels bounded at 256 lanes per block (the window-test and time-window
