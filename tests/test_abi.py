@@ -201,6 +201,23 @@ def test_generated_headers_are_current(gen, header):
     assert out == open(os.path.join(csrc, header)).read()
 
 
+def test_table_sincos_error_bound():
+    """The table-driven sine and cosine of the step loops, replayed by its
+    generator with exactly rounded FMAs over arguments up to 1e6 and around
+    the table's interval edges, stay within 1.2e-16 of the true values (half
+    an ulp of 1 plus the rotation's rounding); the polynomial form of the
+    initial conditions and the energy within 2.5e-16 on its reduced range."""
+    import re
+    csrc = os.path.join(ROOT, "paper_1107_4107_amd", "csrc")
+    tab = open(os.path.join(csrc, "aw_sincos_tab.h")).read()
+    m = re.search(r"max abs error sin ([0-9.e+-]+), cos ([0-9.e+-]+)", tab)
+    assert m and float(m.group(1)) <= 1.2e-16 and float(m.group(2)) <= 1.2e-16
+    assert "#define AW_TAB_N 4096" in tab
+    poly = open(os.path.join(csrc, "aw_sincos_coef.h")).read()
+    errs = [float(x) for x in re.findall(r"double Horner max abs error ([0-9.e+-]+)", poly)]
+    assert len(errs) == 2 and max(errs) <= 2.5e-16
+
+
 def test_bench_refuses_more_than_one_gpu():
     """bench.py measures one GPU; asked for more it says so and exits non-zero
     before touching a device."""
