@@ -1,7 +1,8 @@
-// Achievable FP64 vector rate and the sustained shader clock of the device.
+// Achievable FP64 vector rate and the sustained shader clock of the device,
+// and the device's own sine and cosine evaluated on given arguments.
 //
-// A measurement probe, built into its own library (libaw_probe.so) and used
-// only by the benchmark: every lane runs CHAINS independent chains of FP64
+// Probes built into their own library (libaw_probe.so), used by the benchmark
+// and the tests, never by the library.  The rate probe: every lane runs CHAINS independent chains of FP64
 // fused multiply-adds, so that the issue of v_fma_f64 is limited by the SIMD's
 // FP64 throughput and not by the latency of one chain.  Each wave also reads
 // the shader-clock counter and the constant-rate wall clock around its loop;
@@ -13,6 +14,8 @@
 
 #include <cstdint>
 #include <cstdio>
+
+#include "aw_device.hpp"
 
 namespace {
 
@@ -45,6 +48,26 @@ __global__ __launch_bounds__(BLOCK) void k_fma_chains(double m, double c, int64_
     const int wave = gid >> 6;
     clk[2 * wave] = t1 - t0;
     clk[2 * wave + 1] = w1 - w0;
+  }
+}
+
+// The table-driven sine and cosine of the propagation and adjoint kernels and
+// the polynomial form of the initial conditions, one argument per lane.
+__global__ __launch_bounds__(BLOCK) void k_sincos(const double* __restrict__ x, double* __restrict__ s,
+                                                  double* __restrict__ c, int64_t n, int32_t form) {
+  __shared__ double2 tab[AW_TAB_N];
+  aw::load_sincos_table(tab);  // before any lane returns: it ends in a barrier
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= n) return;
+  if (form == 0) {
+    const aw::SinCosT r = aw::sincos_tab(x[i], tab);
+    s[i] = r.s;
+    c[i] = r.c;
+  } else {
+    double sv, cv;
+    aw::sincos_full(x[i], sv, cv);
+    s[i] = sv;
+    c[i] = cv;
   }
 }
 
@@ -118,4 +141,22 @@ extern "C" int awp_fma_peak(int32_t waves_per_simd, int64_t trips, double* out) 
   (void)hipFree(sink);
   (void)hipFree(clk);
   return rc;
+}
+
+// Writes s_dev[i], c_dev[i] = sin, cos of x_dev[i] (device arrays of n
+// doubles) as the kernels compute them: form 0 = the table-driven routine of
+// the step loops, 1 = the polynomial routine of the initial conditions and
+// the energy.  Enqueued on `stream` (NULL = default).  Returns 0, 1 on a HIP
+// error (printed), 2 on bad arguments.
+extern "C" int awp_sincos(const double* x_dev, double* s_dev, double* c_dev, int64_t n, int32_t form,
+                          void* stream) {
+  if (n < 0 || (form != 0 && form != 1)) return 2;
+  if (n == 0) return 0;
+  if (!x_dev || !s_dev || !c_dev) return 2;
+  const int64_t blocks = (n + BLOCK - 1) / BLOCK;
+  if (blocks > INT32_MAX) return 2;
+  hipLaunchKernelGGL(k_sincos, dim3((unsigned)blocks), dim3(BLOCK), 0, (hipStream_t)stream, x_dev, s_dev, c_dev, n,
+                     form);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : fail(e, "sincos probe");
 }
