@@ -30,13 +30,22 @@ def test_library_exports_every_declared_function():
 
 
 def test_probe_library_loads():
-    """The FP64 peak/clock probe the benchmark uses is built beside libaw.so."""
+    """The probes (FP64 peak and clock for the benchmark; the device sine and
+    cosine for the tests) are built beside libaw.so and check their arguments
+    before touching a device."""
     lib = ctypes.CDLL(os.path.join(ROOT, "paper_1107_4107_amd", "libaw_probe.so"))
-    assert hasattr(lib, "awp_fma_peak")
+    assert hasattr(lib, "awp_fma_peak") and hasattr(lib, "awp_sincos")
     lib.awp_fma_peak.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
     out = (ctypes.c_double * 5)()
     assert lib.awp_fma_peak(0, 1000, out) == 2      # argument check, no device touched
     assert lib.awp_fma_peak(1, 1000, None) == 2
+    lib.awp_sincos.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                               ctypes.c_void_p]
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: every call below returns before any launch
+    assert lib.awp_sincos(fake, fake, fake, -1, 0, None) == 2
+    assert lib.awp_sincos(fake, fake, fake, 10, 2, None) == 2
+    assert lib.awp_sincos(None, fake, fake, 10, 0, None) == 2
+    assert lib.awp_sincos(None, None, None, 0, 1, None) == 0
 
 
 def test_struct_layouts_match_the_header(tmp_path):
