@@ -17,7 +17,9 @@ Other workloads (measurement records, not the default line):
       launch captured in a HIP graph against the sum of 64 separate launches;
   c4  gradient of J on the 512 x 512, T = 1e4 slice with checkpoints every
       100 steps: adjoint time against the forward pass; also the gradient of
-      the tangent growth L (second-order adjoint) on the same slice;
+      the tangent growth L (second-order adjoint) on the same slice, and both
+      in one segment (every step state stored by the forward pass) where HBM
+      holds them;
   c5  1e7 orbits uniform on [0, 2 pi)^6, eps = 5e-3, T = 1e6, run in chunks
       of 1e5 steps with the state carried in HBM, then the momentum-drift image
       and the direction density on the sphere (512 x 512 each);
@@ -317,7 +319,34 @@ def run_adjoint(args, aw, wl, torch):
     t_fgrad = timed(lambda: aw.ftle_grad(fwd_t, ic, w0, ckpt_every=wl.C4_CKPT, workspace=ws2))
     t_fgrad_rev = timed(lambda: aw.ftle_grad(fwd_t, ic, w0, ckpt_every=wl.C4_CKPT, workspace=ws2, reversible=True))
     log(f"FTLE gradient {t_fgrad:.3f} s, reversible {t_fgrad_rev:.3f} s")
+    g_ck = aw.ftle_grad(fwd_t, ic, w0, ckpt_every=wl.C4_CKPT, workspace=ws2)
     del ws2
+    # One segment: the forward pass stores every step state and the reverse
+    # sweep reads them back without recomputing, where HBM holds them
+    # (6 doubles per orbit-step for J, 12 for L: 126 GB and 252 GB here).
+    free = torch.cuda.mem_get_info()[0]
+    one = {}
+    for name, ens, nbytes, call in (
+            ("gradient", fwd, aw.grad_workspace_bytes(fwd, T),
+             lambda w: aw.indicator_grad(fwd, ic, ckpt_every=T, workspace=w)),
+            ("ftle_gradient", fwd_t, aw.ftle_grad_workspace_bytes(fwd_t, T),
+             lambda w: aw.ftle_grad(fwd_t, ic, w0, ckpt_every=T, workspace=w))):
+        if nbytes + (4 << 30) > free:
+            one[name] = None
+            log(f"{name} in one segment skipped: {nbytes / 1e9:.1f} GB of workspace, {free / 1e9:.1f} GB free")
+            continue
+        w = torch.empty((nbytes,), dtype=torch.uint8, device="cuda")
+        t1 = timed(lambda: call(w))
+        if name == "gradient":
+            same = all(torch.equal(a, b) for a, b in zip(call(w), aw.indicator_grad(fwd, ic, ckpt_every=wl.C4_CKPT)))
+        else:
+            same = all(torch.equal(a, b) for a, b in zip(call(w), g_ck))
+        del w
+        torch.cuda.empty_cache()
+        one[name] = (t1, nbytes, bool(same))
+        log(f"{name} in one segment {t1:.3f} s ({nbytes / 1e9:.1f} GB of workspace), equal to the checkpointed "
+            f"one bit for bit: {same}")
+    del g_ck
     rec = base_record(N * T / t_grad, 3, 1, t_grad * 1e3)
     rec["metric"] = "orbit map-steps/sec through the adjoint (forward + checkpoints + reverse)"
     rec["config"] = {"workload": "c4: eps=1e-2 512x512 (px,py) slice, T=1e4, checkpoint every 100 steps, "
@@ -333,6 +362,10 @@ def run_adjoint(args, aw, wl, torch):
     rec["ftle_gradient_over_forward_tangent"] = t_fgrad / t_fwd_tan
     rec["reversible_ftle_gradient_s"] = t_fgrad_rev
     rec["reversible_ftle_gradient_over_forward_tangent"] = t_fgrad_rev / t_fwd_tan
+    for name, base in (("gradient", t_fwd), ("ftle_gradient", t_fwd_tan)):
+        r = one[name]
+        rec[f"one_segment_{name}"] = None if r is None else {
+            "s": r[0], "over_forward": r[0] / base, "workspace_bytes": r[1], "equals_checkpointed_bitwise": r[2]}
     return rec, None
 
 

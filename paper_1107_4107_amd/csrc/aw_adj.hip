@@ -143,6 +143,7 @@ __global__ __launch_bounds__(512) void k_adj_fwd(AdjDesc d) {
     for (int64_t g = g0; g < g1; ++g) {
       adj_step_fwd<FORM>(o, d, s_tab);
       accum_j(o);
+      if (d.fwd_steps) store6(d.steps + g * 6 * d.N, d.N, n, o);  // one segment: g0 = 0
     }
   }
   store6(d.ckpts + d.n_seg * 6 * d.N, d.N, n, o);   // the final state
@@ -205,10 +206,12 @@ __global__ __launch_bounds__(512) void k_adj_bwd(AdjDesc d) {
   for (int64_t s = d.n_seg - 1; s >= 0; --s) {
     const int64_t g0 = s * d.ckpt;
     const int64_t g1 = g0 + d.ckpt < d.T ? g0 + d.ckpt : d.T;
-    load6(d.ckpts + s * 6 * N, N, n, o);
-    for (int64_t g = g0; g < g1; ++g) {
-      adj_step_fwd<FORM>(o, d, s_tab);
-      store6(d.steps + (g - g0) * 6 * N, N, n, o);
+    if (!d.fwd_steps) {  // else the forward pass has stored the steps already
+      load6(d.ckpts + s * 6 * N, N, n, o);
+      for (int64_t g = g0; g < g1; ++g) {
+        adj_step_fwd<FORM>(o, d, s_tab);
+        store6(d.steps + (g - g0) * 6 * N, N, n, o);
+      }
     }
     for (int64_t g = g1 - 1; g >= g0; --g) {
       load6(d.steps + (g - g0) * 6 * N, N, n, o);   // state after step g

@@ -824,6 +824,7 @@ aw_status aw_indicator_grad(const aw_ensemble *ens, const double *ic_dev, const 
   aw_status st = adj_setup(ens, ic_dev, grad_J_dev, ckpt_every, J_out_dev, grad_ic_dev, grad_eps_dev, workspace_dev,
                            ws_bytes, tuning, "aw_indicator_grad", d, t);
   if (st != AW_OK) return st;
+  d.fwd_steps = d.n_seg == 1 ? 1 : 0;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = launch_adj_forward(d, ens->map_form, t, s);
   if (e != hipSuccess) return hip_fail(e, "adjoint forward launch");
@@ -915,6 +916,7 @@ aw_status aw_ftle_grad(const aw_ensemble *ens, const double *ic_dev, const doubl
   aw_status st = ftle_setup(ens, ic_dev, w0_dev, grad_L_dev, ckpt_every, L_out_dev, grad_ic_dev, grad_eps_dev,
                             workspace_dev, ws_bytes, tuning, "aw_ftle_grad", d, t);
   if (st != AW_OK) return st;
+  d.fwd_steps = d.n_seg == 1 ? 1 : 0;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = launch_ftle_forward(d, ens->map_form, t, s);
   if (e != hipSuccess) return hip_fail(e, "FTLE-gradient forward launch");

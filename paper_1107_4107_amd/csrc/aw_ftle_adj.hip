@@ -251,6 +251,7 @@ __global__ __launch_bounds__(512) void k_ftle_fwd(FtleDesc d) {
     const int64_t g1 = g0 + d.ckpt < d.T ? g0 + d.ckpt : d.T;
     for (int64_t g = g0; g < g1; ++g) {
       tan_step<FORM>(o, d, s_tab);
+      if (d.fwd_steps) store12(d.steps + g * 12 * N, N, n, o);  // one segment: g0 = 0
       if (((g + 1) & RESCALE_MASK) == 0) {
         const int k0 = o.kexp;
         renorm(o);
@@ -283,11 +284,13 @@ __global__ __launch_bounds__(512) void k_ftle_bwd(FtleDesc d) {
   for (int64_t s = d.n_seg - 1; s >= 0; --s) {
     const int64_t g0 = s * d.ckpt;
     const int64_t g1 = g0 + d.ckpt < d.T ? g0 + d.ckpt : d.T;
-    load12(d.ckpts + s * 12 * N, N, n, o);
-    for (int64_t g = g0; g < g1; ++g) {
-      tan_step<FORM>(o, d, s_tab);
-      store12(d.steps + (g - g0) * 12 * N, N, n, o);
-      if (((g + 1) & RESCALE_MASK) == 0) renorm(o);
+    if (!d.fwd_steps) {  // else the forward pass has stored the steps already
+      load12(d.ckpts + s * 12 * N, N, n, o);
+      for (int64_t g = g0; g < g1; ++g) {
+        tan_step<FORM>(o, d, s_tab);
+        store12(d.steps + (g - g0) * 12 * N, N, n, o);
+        if (((g + 1) & RESCALE_MASK) == 0) renorm(o);
+      }
     }
     for (int64_t g = g1 - 1; g >= g0; --g) {
       load12(d.steps + (g - g0) * 12 * N, N, n, o);   // end of step g, before any rescale

@@ -129,6 +129,8 @@ struct AdjDesc {
   double *geps;           // [N]
   double *ckpts;          // [n_seg + 1][6][N] (the last slot: the final state)
   double *steps;          // [ckpt][6][N] (per-segment step states)
+  int32_t fwd_steps;      // 1: one segment, and the forward pass stores the step
+                          // states itself, so that the store sweep skips its recompute
 };
 
 }  // namespace aw

@@ -57,6 +57,21 @@ def test_adjoint_matches_forward_mode(aw, form, T, ck):
     _grad_rel(g, dJo, 1e-9)
 
 
+def test_adjoint_independent_of_checkpoints(aw):
+    """The gradient does not depend on the checkpoint interval, bit for bit,
+    including one segment (the forward pass then stores the step states
+    itself and the backward pass skips its recompute) and a ragged last
+    segment."""
+    print_case("adjoint checkpoints")
+    ic = tensor(oracle.ic_box([0.0] * 6, [2 * np.pi] * 6, 4, 200))
+    e = aw.Ensemble(eps=3e-2, n_steps=333, ic_kind="explicit", n_orbits=200, tangent=False)
+    ref = aw.indicator_grad(e, ic, ckpt_every=333)
+    for ck in (1, 7, 64, 1000):
+        got = aw.indicator_grad(e, ic, ckpt_every=ck)
+        for a, b in zip(got, ref):
+            np.testing.assert_array_equal(np_(a), np_(b))
+
+
 def test_adjoint_dot_product(aw):
     """<dL/dic, u> + dL/deps * v = sum_n gJ_n (dJ_n . (u_n, v)) for random gJ, u, v."""
     print_case("dot product")
