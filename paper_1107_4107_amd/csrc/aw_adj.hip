@@ -68,15 +68,13 @@ __device__ __forceinline__ void rev_drift(Orbit &o, Adjoint &a, double t) {
 // same table as the forward kick, so the undone kick matches it.
 __device__ __forceinline__ void rev_kick(Orbit &o, Adjoint &a, double a2, double a4, double w2,
                                          double w4, const double2 *__restrict__ tab) {
-  const SinCosT X = sincos_tab(o.x, tab), Y = sincos_tab(o.y, tab), Z = sincos_tab(o.z, tab);
+  const SinCosT X = sincos_tab(o.x, tab), Y = sincos_tab(o.y, tab);
+  const ZTerms Z = zterms_tab(o.z, tab);
   const double cx = X.c, sx = X.s;
   const double cy = Y.c, sy = Y.s;
-  const double cz2 = Z.c * Z.c;
-  const double czsz = Z.c * Z.s;
-  const double c2z = __builtin_fma(-Z.s, Z.s, cz2);
   const double psc = sx * cy, pcs = cx * sy, pcc = cx * cy, pss = sx * sy;
-  const double e1 = a2 * cz2, e2 = a4 * czsz, e3 = a4 * c2z;
-  const double f1 = w2 * cz2, f2 = w4 * czsz;
+  const double e1 = a2 * Z.cz2, e2 = a4 * Z.czsz, e3 = __builtin_fma(4.0, e1, -a4);
+  const double f1 = w2 * Z.cz2, f2 = w4 * Z.czsz;
   // d(P after kick)/d eps = -t grad Hp = (f1 psc, f1 pcs, f2 pcc).
   a.eb = __builtin_fma(f1, __builtin_fma(psc, a.pxb, pcs * a.pyb), a.eb);
   a.eb = __builtin_fma(f2 * pcc, a.pzb, a.eb);

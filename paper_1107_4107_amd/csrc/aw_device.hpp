@@ -110,6 +110,46 @@ constexpr int SCT_FMA = 1 + 2 + 1 + 2 + 2;
 constexpr int SCT_MUL = 4;  // r*r, r*u, and one product per rotated output
 constexpr int SCT_ADD = 1;
 
+// The z factors of eq. 2's force and Hessian, cos^2 z and cos z sin z, from
+// the same table at the doubled angle: cos^2 z = (1 + cos 2z)/2 and
+// cos z sin z = sin(2z)/2.  The reduction is sincos_tab's, x = q pi/2048 + r;
+// then 2z = 2q pi/2048 + 2r, whose node 2q mod 4096 sits at the low word of t
+// shifted by 5 (cut to 16 bits), and two short polynomials in u = r^2 give
+// sin(2r)/2 and cos(2r)/2.  9 FMA, 3 MUL, 1 ADD: as many as one sincos_tab,
+// in place of the sincos of z and its two products, and no reduction
+// constants beyond sincos_tab's.
+struct ZTerms {
+  double cz2, czsz;
+};
+
+__device__ __forceinline__ uint32_t tab_offset2(double t) {
+  uint32_t a;
+  asm("v_lshlrev_b32_sdwa %0, 5, %1 dst_sel:WORD_0 dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:DWORD"
+      : "=v"(a)
+      : "v"((uint32_t)__double2loint(t)));
+  return a;
+}
+
+__device__ __forceinline__ ZTerms zterms_tab(double z, const double2 *__restrict__ tab) {
+  const double t = __builtin_fma(z, AW_INV_PI2K, AW_ROUND_MAGIC);
+  const double q = t - AW_ROUND_MAGIC;
+  double r = __builtin_fma(-q, AW_PI2K_A, z);
+  r = __builtin_fma(-q, AW_PI2K_B, r);
+  const double2 e = *(const double2 *)((const char *)tab + tab_offset2(t));
+  const double u = r * r;
+  const double sh = __builtin_fma(r * u, AW_ZSIN_C0, r);                           // sin(2r)/2
+  const double ph = __builtin_fma(AW_ZCOS_C[1], u, AW_ZCOS_C[0]);
+  const double ch = __builtin_fma(u, ph, 0.5);                                     // cos(2r)/2
+  ZTerms o;
+  o.czsz = __builtin_fma(e.x, ch, e.y * sh);
+  o.cz2 = __builtin_fma(e.y, ch, __builtin_fma(-e.x, sh, 0.5));
+  return o;
+}
+
+constexpr int ZT_FMA = 1 + 2 + 1 + 2 + 3;
+constexpr int ZT_MUL = 3;  // r*r, r*u, C*sh
+constexpr int ZT_ADD = 1;
+
 // Fill a block's LDS copy of the (sin, cos)(k pi/2048) table; every thread of
 // the block must call this before any of them returns.
 __device__ __forceinline__ void load_sincos_table(double2 *tab) {
@@ -143,27 +183,26 @@ struct Orbit {
   int kexp;                            // tangent scale exponent (|w| true = |w| 2^kexp)
 };
 
-// Kick with weight a2 = 2 t eps, a4 = 4 t eps, sines and cosines from the
-// block's LDS table (true values: no sign folding).  Every force and Hessian
-// term of eq. 2 is a product of one x factor, one y factor and z factors:
-//   e1 = 2 t eps cz^2, e2 = 4 t eps cz sz, e3 = 4 t eps (cz^2 - sz^2),
+// Kick with weight a2 = 2 t eps, a4 = 4 t eps = 2 a2, sines and cosines from
+// the block's LDS table (true values: no sign folding).  Every force and
+// Hessian term of eq. 2 is a product of one x factor, one y factor and z
+// factors:
+//   e1 = 2 t eps cz^2, e2 = 4 t eps cz sz, e3 = 4 t eps (cz^2 - sz^2) = 4 e1 - a4,
 //   P  += (e1 sx cy, e1 cx sy, e2 cx cy)                 (= -t eps grad Hp)
 //   dP += M dX, M = [[e1 cx cy, -e1 sx sy, -e2 sx cy],
 //                    [-e1 sx sy, e1 cx cy, -e2 cx sy],
 //                    [-e2 sx cy, -e2 cx sy, e3 cx cy]]     (= -t eps Hess Hp)
 template <bool TAN>
 __device__ __forceinline__ void kick_tab(Orbit &o, double a2, double a4, const double2 *__restrict__ tab) {
-  const SinCosT X = sincos_tab(o.x, tab), Y = sincos_tab(o.y, tab), Z = sincos_tab(o.z, tab);
+  const SinCosT X = sincos_tab(o.x, tab), Y = sincos_tab(o.y, tab);
+  const ZTerms Z = zterms_tab(o.z, tab);
   const double cx = X.c, sx = X.s;
   const double cy = Y.c, sy = Y.s;
-  const double cz2 = Z.c * Z.c;
-  const double czsz = Z.c * Z.s;
-  const double e1 = a2 * cz2;
-  const double e2 = a4 * czsz;
+  const double e1 = a2 * Z.cz2;
+  const double e2 = a4 * Z.czsz;
   const double psc = sx * cy, pcs = cx * sy, pcc = cx * cy;
   if (TAN) {
-    const double c2z = __builtin_fma(-Z.s, Z.s, cz2);
-    const double e3 = a4 * c2z;
+    const double e3 = __builtin_fma(4.0, e1, -a4);
     const double pss = sx * sy;
     const double mxx = e1 * pcc;
     const double nxy = e1 * pss;
@@ -200,9 +239,9 @@ __device__ __forceinline__ void drift(Orbit &o, double t) {
 
 // Op counts of kick/drift (roofline accounting).
 template <bool TAN> struct KickTabOps {
-  static constexpr int fma = 3 * SCT_FMA + 3 + (TAN ? 1 + 9 : 0);
-  static constexpr int mul = 3 * SCT_MUL + 7 + (TAN ? 7 : 0);
-  static constexpr int add = 3 * SCT_ADD;
+  static constexpr int fma = 2 * SCT_FMA + ZT_FMA + 3 + (TAN ? 1 + 9 : 0);
+  static constexpr int mul = 2 * SCT_MUL + ZT_MUL + 5 + (TAN ? 6 : 0);
+  static constexpr int add = 2 * SCT_ADD + ZT_ADD;
 };
 template <bool TAN> struct DriftOps {
   static constexpr int fma = TAN ? 6 : 3;

@@ -98,18 +98,16 @@ __device__ __forceinline__ void rev_drift2(Orbit &o, Adjoint2 &a, double t) {
 // with e1 = 2 t eps cz^2, e2 = 4 t eps cz sz, e3 = 4 t eps (cz^2 - sz^2).
 __device__ __forceinline__ void rev_kick2(Orbit &o, Adjoint2 &a, double a2, double a4, double w2, double w4,
                                           const double2 *__restrict__ tab) {
-  const SinCosT X = sincos_tab(o.x, tab), Y = sincos_tab(o.y, tab), Z = sincos_tab(o.z, tab);
+  const SinCosT X = sincos_tab(o.x, tab), Y = sincos_tab(o.y, tab);
+  const ZTerms Z = zterms_tab(o.z, tab);
   const double cx = X.c, sx = X.s;
   const double cy = Y.c, sy = Y.s;
-  const double cz2 = Z.c * Z.c;
-  const double czsz = Z.c * Z.s;
-  const double c2z = __builtin_fma(-Z.s, Z.s, cz2);
   const double psc = sx * cy, pcs = cx * sy, pcc = cx * cy, pss = sx * sy;
-  const double e1 = a2 * cz2, e2 = a4 * czsz, e3 = a4 * c2z;
+  const double e1 = a2 * Z.cz2, e2 = a4 * Z.czsz, e3 = __builtin_fma(4.0, e1, -a4);
   // M = -t eps Hess: diagonal mxx (= myy), mzz; off-diagonal -nxy, -nxz, -nyz.
   const double mxx = e1 * pcc, nxy = e1 * pss, nxz = e2 * psc, nyz = e2 * pcs, mzz = e3 * pcc;
   // The same matrix per unit eps (for epsbar).
-  const double f1 = w2 * cz2, f2 = w4 * czsz, f3 = w4 * c2z;
+  const double f1 = w2 * Z.cz2, f2 = w4 * Z.czsz, f3 = __builtin_fma(4.0, f1, -w4);
   const double wxx = f1 * pcc, vxy = f1 * pss, vxz = f2 * psc, vyz = f2 * pcs, wzz = f3 * pcc;
   const double dx = o.dx, dy = o.dy, dz = o.dz;
   const double pxb = a.pxb, pyb = a.pyb, pzb = a.pzb;

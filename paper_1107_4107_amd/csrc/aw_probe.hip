@@ -51,8 +51,9 @@ __global__ __launch_bounds__(BLOCK) void k_fma_chains(double m, double c, int64_
   }
 }
 
-// The table-driven sine and cosine of the propagation and adjoint kernels and
-// the polynomial form of the initial conditions, one argument per lane.
+// The table-driven sine and cosine of the propagation and adjoint kernels, the
+// kicks' doubled-angle z terms and the polynomial form of the initial
+// conditions, one argument per lane.
 __global__ __launch_bounds__(BLOCK) void k_sincos(const double* __restrict__ x, double* __restrict__ s,
                                                   double* __restrict__ c, int64_t n, int32_t form) {
   __shared__ double2 tab[AW_TAB_N];
@@ -63,6 +64,10 @@ __global__ __launch_bounds__(BLOCK) void k_sincos(const double* __restrict__ x, 
     const aw::SinCosT r = aw::sincos_tab(x[i], tab);
     s[i] = r.s;
     c[i] = r.c;
+  } else if (form == 2) {
+    const aw::ZTerms r = aw::zterms_tab(x[i], tab);
+    s[i] = r.czsz;
+    c[i] = r.cz2;
   } else {
     double sv, cv;
     aw::sincos_full(x[i], sv, cv);
@@ -146,11 +151,13 @@ extern "C" int awp_fma_peak(int32_t waves_per_simd, int64_t trips, double* out) 
 // Writes s_dev[i], c_dev[i] = sin, cos of x_dev[i] (device arrays of n
 // doubles) as the kernels compute them: form 0 = the table-driven routine of
 // the step loops, 1 = the polynomial routine of the initial conditions and
-// the energy.  Enqueued on `stream` (NULL = default).  Returns 0, 1 on a HIP
-// error (printed), 2 on bad arguments.
+// the energy; form 2 writes the kicks' z terms instead, s = cos x sin x and
+// c = cos^2 x, from the table at the doubled angle.  Enqueued on `stream`
+// (NULL = default).  Returns 0, 1 on a HIP error (printed), 2 on bad
+// arguments.
 extern "C" int awp_sincos(const double* x_dev, double* s_dev, double* c_dev, int64_t n, int32_t form,
                           void* stream) {
-  if (n < 0 || (form != 0 && form != 1)) return 2;
+  if (n < 0 || form < 0 || form > 2) return 2;
   if (n == 0) return 0;
   if (!x_dev || !s_dev || !c_dev) return 2;
   const int64_t blocks = (n + BLOCK - 1) / BLOCK;

@@ -19,7 +19,10 @@ two-part pi).
 The whole device sequence is replayed here in double precision with each
 fused multiply-add rounded once (exactly, through mpmath), against mpmath's
 sin and cos, over arguments up to 1e6 in magnitude and around the table's
-interval edges; the errors are written into the header.
+interval edges; the errors are written into the header.  So is the error of
+the kicks' z terms, cos^2 z = (1 + cos 2z)/2 and cos z sin z = sin(2z)/2, which
+the device takes from the same table at the doubled angle: same reduction,
+node 2q, and polynomials for sin(2r)/2 and cos(2r)/2 (device_zterms).
 
 Run:  python gen_sincos_tab.py > aw_sincos_tab.h
 """
@@ -76,6 +79,46 @@ def device_sincos(x, tab, ps0, pc, inv, pa, pb):
     return fma(S, cr, C * sr), fma(C, cr, -(S * sr))
 
 
+def device_zterms(z, tab, zs0, zc, inv, pa, pb):
+    """The kicks' z terms (cos z sin z, cos^2 z) as the device computes them
+    from the table at the doubled angle: the reduction of z is sincos_tab's
+    (q, r), 2z = 2q pi/2048 + 2r picks node 2q mod 4096 (the same low word of
+    t, shifted by 5 instead of 4), and two short polynomials in u = r^2 give
+    sin(2r)/2 and cos(2r)/2.  Returns (cos z sin z, cos^2 z)."""
+    t = fma(z, inv, MAGIC)
+    q = t - MAGIC
+    r = fma(-q, pa, z)
+    r = fma(-q, pb, r)
+    k = ((lo32(t) << 5) & 0xFFFF) >> 4
+    S, C = tab[2 * k], tab[2 * k + 1]
+    u = r * r
+    sh = fma(r * u, zs0, r)
+    ph = fma(zc[1], u, zc[0])
+    ch = fma(u, ph, 0.5)
+    return fma(S, ch, C * sh), fma(C, ch, fma(-S, sh, 0.5))
+
+
+def g_zsin(u):
+    if u == 0:
+        return mp.mpf(-2) / 3
+    r = mp.sqrt(u)
+    return (mp.sin(2 * r) / 2 - r) / (u * r)
+
+
+def g_zcos(u):
+    if u == 0:
+        return mp.mpf(-1)
+    return (mp.cos(2 * mp.sqrt(u)) / 2 - mp.mpf(1) / 2) / u
+
+
+def z_constants():
+    """Coefficients of sin(2r)/2 = r + r^3 a and cos(2r)/2 = 1/2 + r^2 B(r^2)
+    on the same reduced range, with their fit errors: (zs, zc, errzs, errzc)."""
+    zs, errzs = fit(g_zsin, 1)
+    zc, errzc = fit(g_zcos, 2)
+    return zs, zc, errzs, errzc
+
+
 def constants():
     """The table, the coefficients and the reduction constants, with the fit
     errors: (tab, ps, pc, inv, pa, pb, errs, errc)."""
@@ -103,18 +146,33 @@ def main():
         s, c = device_sincos(x, tab, ps[0], pc, inv, pa, pb)
         es = max(es, abs(s - float(mp.sin(mp.mpf(x)))))
         ec = max(ec, abs(c - float(mp.cos(mp.mpf(x)))))
+    # The kicks' z terms from the doubled angle, over the same arguments and
+    # around the edges of the doubled angle's intervals.
+    zsc, zcc, errzs, errzc = z_constants()
+    zs = xs[:6000] + [float((k + 0.5) * mp.pi / 4096) * (1 + s * 1e-15) for k in range(-4200, 4200, 7) for s in (-1, 1)]
+    ez2 = ezs = 0.0
+    for z in zs:
+        zsz, z2 = device_zterms(z, tab, zsc[0], zcc, inv, pa, pb)
+        cz, sz = mp.cos(mp.mpf(z)), mp.sin(mp.mpf(z))
+        ez2 = max(ez2, abs(z2 - float(cz * cz)))
+        ezs = max(ezs, abs(zsz - float(cz * sz)))
     out = sys.stdout
     out.write("/* Generated by gen_sincos_tab.py -- do not edit. */\n#pragma once\n")
     out.write(f"/* sin r = r + r^3 c: 1 coefficient, fit error {mp.nstr(errs, 3)}; "
               f"cos r = 1 + r^2 Q(r^2): 2 coefficients, fit error {mp.nstr(errc, 3)}; |r| <= pi/4096 */\n")
     out.write(f"/* device sequence replayed with single-rounding FMAs over {len(xs)} arguments up to 1e6: "
               f"max abs error sin {es:.3e}, cos {ec:.3e} */\n")
+    out.write(f"/* kick z terms from the doubled angle: sin(2r)/2 = r + r^3 a, fit error {mp.nstr(errzs, 3)}; "
+              f"cos(2r)/2 = 1/2 + r^2 B(r^2), fit error {mp.nstr(errzc, 3)}; replayed over {len(zs)} arguments "
+              f"up to 1e6: max abs error cos^2 z {ez2:.3e}, cos z sin z {ezs:.3e} */\n")
     out.write(f"#define AW_TAB_N {N_TAB}\n")
     out.write(f"static constexpr double AW_TSIN_C0 = {ps[0].hex()};\n")
     out.write("static constexpr double AW_TCOS_C[2] = {" + ", ".join(v.hex() for v in pc) + "};\n")
     out.write(f"static constexpr double AW_PI2K_A = {pa.hex()};\n")
     out.write(f"static constexpr double AW_PI2K_B = {pb.hex()};\n")
     out.write(f"static constexpr double AW_INV_PI2K = {inv.hex()};\n")
+    out.write(f"static constexpr double AW_ZSIN_C0 = {zsc[0].hex()};\n")
+    out.write("static constexpr double AW_ZCOS_C[2] = {" + ", ".join(v.hex() for v in zcc) + "};\n")
     out.write("/* (sin, cos)(k pi/2048), k = 0..4095, interleaved */\n")
     out.write("static constexpr double AW_TAB_SC[2 * AW_TAB_N] = {\n")
     for k in range(N_TAB):

@@ -2,6 +2,7 @@
 its ctypes mirrors match the C struct layouts, and the host-side validation
 rejects bad descriptors before touching a device.  CPU only."""
 import ctypes
+import math
 import os
 import re
 import subprocess
@@ -43,7 +44,8 @@ def test_probe_library_loads():
                                ctypes.c_void_p]
     fake = ctypes.c_void_p(0x1000)   # never dereferenced: every call below returns before any launch
     assert lib.awp_sincos(fake, fake, fake, -1, 0, None) == 2
-    assert lib.awp_sincos(fake, fake, fake, 10, 2, None) == 2
+    assert lib.awp_sincos(fake, fake, fake, 10, 3, None) == 2
+    assert lib.awp_sincos(fake, fake, fake, 10, -1, None) == 2
     assert lib.awp_sincos(None, fake, fake, 10, 0, None) == 2
     assert lib.awp_sincos(None, None, None, 0, 1, None) == 0
 
@@ -158,15 +160,18 @@ def test_ftle_grad_workspace_and_validation():
 
 
 def test_step_op_counts_match_the_stage_structure():
-    """Per map step: 9 kicks (3 sincos each) and 10 drifts for the 6th-order
-    triple jump, 7 and 8 for Y6; the counts are those of the kernel's formulas
-    (one sincos from the 4096-entry table = 8 fma, 4 mul, 1 add; the rest of a kick 3 fma
-    and 7 mul, plus 10 fma and 7 mul for the tangent; a drift 3 fma, 6 with the
-    tangent; the J accumulator 3 fma and 3 subtractions)."""
+    """Per map step: 9 kicks and 10 drifts for the 6th-order triple jump, 7
+    and 8 for Y6; the counts are those of the kernel's formulas.  A kick takes
+    the sincos of x and y from the 4096-entry table (8 fma, 4 mul, 1 add each)
+    and cos^2 z, cos z sin z from the same table at the doubled angle (9 fma,
+    3 mul, 1 add); the rest of a kick is 3 fma and 5 mul, plus 10 fma and 6 mul
+    for the tangent; a drift 3 fma, 6 with the tangent; the J accumulator 3 fma
+    and 3 subtractions."""
     from paper_1107_4107_amd import step_op_counts
     sc_f, sc_m, sc_a = 8, 4, 1
-    kick_t = (3 * sc_f + 3 + 10, 3 * sc_m + 7 + 7, 3 * sc_a)
-    kick_n = (3 * sc_f + 3, 3 * sc_m + 7, 3 * sc_a)
+    zt_f, zt_m, zt_a = 9, 3, 1
+    kick_t = (2 * sc_f + zt_f + 3 + 10, 2 * sc_m + zt_m + 5 + 6, 2 * sc_a + zt_a)
+    kick_n = (2 * sc_f + zt_f + 3, 2 * sc_m + zt_m + 5, 2 * sc_a + zt_a)
     f, m, a = step_op_counts("s6", True)
     assert (f, m, a) == (9 * kick_t[0] + 10 * 6 + 3, 9 * kick_t[1], 9 * kick_t[2] + 3)
     f, m, a = step_op_counts("y6", True)   # 7 kicks, 8 drifts
@@ -221,10 +226,43 @@ def test_table_sincos_error_bound():
     tab = open(os.path.join(csrc, "aw_sincos_tab.h")).read()
     m = re.search(r"max abs error sin ([0-9.e+-]+), cos ([0-9.e+-]+)", tab)
     assert m and float(m.group(1)) <= 1.2e-16 and float(m.group(2)) <= 1.2e-16
+    m = re.search(r"max abs error cos\^2 z ([0-9.e+-]+), cos z sin z ([0-9.e+-]+)", tab)
+    assert m and float(m.group(1)) <= 1.2e-16 and float(m.group(2)) <= 6e-17
     assert "#define AW_TAB_N 4096" in tab
     poly = open(os.path.join(csrc, "aw_sincos_coef.h")).read()
     errs = [float(x) for x in re.findall(r"double Horner max abs error ([0-9.e+-]+)", poly)]
     assert len(errs) == 2 and max(errs) <= 2.5e-16
+
+
+def test_doubled_angle_z_terms_error_bound():
+    """The kicks' z terms, cos^2 z and cos z sin z, from the table at the
+    doubled angle (sincos_tab's reduction of z, node 2q, short polynomials for
+    sin(2r)/2 and cos(2r)/2), replayed with exactly rounded FMAs, lie within
+    1.2e-16 and 6e-17 of mpmath's values: over random arguments up to 1e5, the
+    edges of the reduced interval (where q rounds either way), the nodes, far
+    arguments and signed zeros.  Against libm's cos z * cos z and
+    cos z * sin z they agree to 2.5e-16."""
+    import importlib.util
+    import random
+    import mpmath as mp
+    spec = importlib.util.spec_from_file_location(
+        "gen_sincos_tab", os.path.join(ROOT, "paper_1107_4107_amd", "csrc", "gen_sincos_tab.py"))
+    g = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(g)
+    tab, _, _, inv, pa, pb, _, _ = g.constants()
+    zs0, zc, errzs, errzc = g.z_constants()
+    assert errzs < 1e-7 and errzc < 1e-14
+    rnd = random.Random(21)
+    edge = [float((k + 0.5) * mp.pi / 2048) for k in range(-5000, 5000, 37)]
+    zs = [rnd.uniform(-10.0, 10.0) for _ in range(400)] + [rnd.uniform(-1e5, 1e5) for _ in range(300)]
+    zs += edge + [math.nextafter(x, math.inf) for x in edge] + [math.nextafter(x, -math.inf) for x in edge]
+    zs += [k * float(mp.pi) / 2048 for k in range(-60, 60)] + [0.0, -0.0, 1e-300, 1e12, -3e12]
+    for z in zs:
+        zsz, z2 = g.device_zterms(z, tab, zs0[0], zc, inv, pa, pb)
+        cz, sz = mp.cos(mp.mpf(z)), mp.sin(mp.mpf(z))
+        assert abs(z2 - float(cz * cz)) <= 1.2e-16, z
+        assert abs(zsz - float(cz * sz)) <= 6e-17, z
+        assert abs(z2 - math.cos(z) * math.cos(z)) <= 2.5e-16 and abs(zsz - math.cos(z) * math.sin(z)) <= 2.5e-16
 
 
 def test_bench_refuses_more_than_one_gpu():

@@ -4,7 +4,9 @@ The probe library runs the kernels' two sine/cosine routines on given
 arguments.  The table-driven routine of the step loops must reproduce, bit for
 bit, its replay by the table generator (every fused multiply-add rounded once,
 the table offset taken from the same bits), and lie within 1.2e-16 of mpmath's
-values; the polynomial routine of the initial conditions within 3e-16.  Both
+values; the polynomial routine of the initial conditions within 3e-16; the
+kicks' z terms (cos z sin z, cos^2 z from the table at the doubled angle)
+bit for bit their replay and within 6e-17 and 1.2e-16 of mpmath.  Both
 are also held against numpy's libm over a large set of arguments: random ones
 up to 1e6 (and near the magic-number rounding's limit), points at and beside
 the midpoints between table nodes, where the rounding of q decides the node,
@@ -82,6 +84,28 @@ def test_table_sincos_matches_its_model_and_mpmath(probe):
         assert abs(c[i] - float(mp.cos(mp.mpf(float(x[i]))))) <= 1.2e-16
 
 
+def test_doubled_angle_z_terms_match_their_model_and_mpmath(probe):
+    """The kicks' cos z sin z and cos^2 z (probe form 2) from the table at the
+    doubled angle."""
+    print_case("z terms")
+    import mpmath as mp
+    x = np.concatenate([_arguments(1e6), np.array([1e12, -1e12, 3.4e12])])
+    zsz, z2 = _device(probe, x, 2)
+    assert np.max(np.abs(zsz - np.cos(x) * np.sin(x))) <= 2.5e-16
+    assert np.max(np.abs(z2 - np.cos(x) * np.cos(x))) <= 2.5e-16
+    g = _gen()
+    tab, _, _, inv, pa, pb, _, _ = g.constants()
+    zs0, zc, _, _ = g.z_constants()
+    rng = np.random.default_rng(14)
+    pick = np.concatenate([rng.choice(x.size, 1500, replace=False), np.arange(x.size - 12, x.size)])
+    for i in pick:
+        ms, mc = g.device_zterms(float(x[i]), tab, zs0[0], zc, inv, pa, pb)
+        assert zsz[i] == ms and z2[i] == mc, (x[i], zsz[i], ms, z2[i], mc)
+        c, s_ = mp.cos(mp.mpf(float(x[i]))), mp.sin(mp.mpf(float(x[i])))
+        assert abs(zsz[i] - float(c * s_)) <= 6e-17
+        assert abs(z2[i] - float(c * c)) <= 1.2e-16
+
+
 def test_polynomial_sincos_within_its_range(probe):
     print_case("polynomial sincos")
     import mpmath as mp
@@ -95,9 +119,13 @@ def test_polynomial_sincos_within_its_range(probe):
         assert abs(c[i] - float(mp.cos(mp.mpf(float(x[i]))))) <= 3e-16
 
 
-@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("form", [0, 1, 2])
 def test_sincos_of_non_finite_arguments_is_nan(probe, form):
     print_case("sincos non-finite", form)
     s, c = _device(probe, np.array([np.inf, -np.inf, np.nan, 1.0]), form)
     assert np.all(np.isnan(s[:3])) and np.all(np.isnan(c[:3]))
-    assert s[3] == pytest.approx(np.sin(1.0), abs=3e-16) and c[3] == pytest.approx(np.cos(1.0), abs=3e-16)
+    if form == 2:
+        assert s[3] == pytest.approx(np.sin(1.0) * np.cos(1.0), abs=3e-16)
+        assert c[3] == pytest.approx(np.cos(1.0) ** 2, abs=3e-16)
+    else:
+        assert s[3] == pytest.approx(np.sin(1.0), abs=3e-16) and c[3] == pytest.approx(np.cos(1.0), abs=3e-16)
