@@ -331,9 +331,10 @@ def run_adjoint(args, aw, wl, torch):
              lambda w: aw.indicator_grad(fwd, ic, ckpt_every=T, workspace=w)),
             ("ftle_gradient", fwd_t, aw.ftle_grad_workspace_bytes(fwd_t, T),
              lambda w: aw.ftle_grad(fwd_t, ic, w0, ckpt_every=T, workspace=w))):
-        if nbytes + (4 << 30) > free:
+        if args.no_one_segment or nbytes + (4 << 30) > free:
             one[name] = None
-            log(f"{name} in one segment skipped: {nbytes / 1e9:.1f} GB of workspace, {free / 1e9:.1f} GB free")
+            log(f"{name} in one segment skipped: {nbytes / 1e9:.1f} GB of workspace, {free / 1e9:.1f} GB free"
+                + (" (--no-one-segment)" if args.no_one_segment else ""))
             continue
         w = torch.empty((nbytes,), dtype=torch.uint8, device="cuda")
         t1 = timed(lambda: call(w))
@@ -706,6 +707,8 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="lanes per block; 0 = the library's automatic choice")
     ap.add_argument("--opl", type=int, default=1)
     ap.add_argument("--unroll", type=int, default=1)
+    ap.add_argument("--no-one-segment", action="store_true",
+                    help="c4: leave out the one-segment gradients (126 GB and 252 GB of workspace)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
