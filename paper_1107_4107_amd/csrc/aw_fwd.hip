@@ -414,13 +414,13 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first, cons
 
 // Blocks of up to 512 lanes: with the 64 KB table two blocks share a CU, and
 // at four waves per SIMD it takes blocks of 512 to fill it.  The one-orbit
-// tangent kernels of the sixth-order maps are held to four waves per SIMD (at
-// most 128 VGPRs), which they would miss by a register or two and so leave
-// room for a single block per CU.  The window-test and time-window variants
-// hold about twice the registers and keep 256.
+// tangent kernels of the sixth-order maps take 129 VGPRs, one block per CU:
+// two waves per SIMD already saturate the VALU issue, and holding them to 128
+// would cost the single-wave schedule its parallelism (a sixth longer on
+// small ensembles).  The window-test and time-window variants hold about twice the
+// registers and keep 256.
 template <int FORM, bool TAN, int OPL, int UNR, bool FILT = false, bool WINV = false>
-__global__ __launch_bounds__((FILT || WINV) ? 256 : 512, (TAN && FORM >= 6 && !FILT && !WINV && OPL == 1) ? 4 : 1)
-void k_fwd(FwdDesc d) {
+__global__ __launch_bounds__((FILT || WINV) ? 256 : 512) void k_fwd(FwdDesc d) {
   __shared__ double2 s_tab[AW_TAB_N];
   load_sincos_table(s_tab);
   const int64_t first = (int64_t)blockIdx.x * blockDim.x * OPL;
