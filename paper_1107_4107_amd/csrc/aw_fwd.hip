@@ -260,9 +260,9 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first, cons
   // values): across the loop the descriptor fields of the epilogue hold most
   // SGPRs, and kick weights left there are spilled to VGPR lanes and read back
   // with v_readlane every step, 16 VALU instructions per S6 step and 32 per Y6
-  // step.  In VGPRs they cost 16 registers (111 -> 127, still four waves per
-  // SIMD) and no instruction.  The unrolled, two-orbit and window variants
-  // would lose occupancy and keep them in SGPRs.
+  // step.  In VGPRs they cost 16 registers and no instruction.  The
+  // unrolled, two-orbit and window variants would lose occupancy and keep
+  // them in SGPRs.
   constexpr bool kVregW = TAN && OPL == 1 && UNR == 1 && !FILT && !WINV;
   StepWeights sw;
 #pragma unroll

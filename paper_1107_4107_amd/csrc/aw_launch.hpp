@@ -20,7 +20,9 @@ struct Tuning {
 // Lanes per block for a launch over n orbits (or lanes).  A block set in the
 // tuning is used as is.  Automatic: 512 when every CU gets at least one block
 // of 512 (a block holds the 64 KB sine/cosine table, so two blocks share a CU,
-// and it takes two of 512 lanes to fill it at four waves per SIMD); below
+// and it takes two of 512 lanes to fill it at four waves per SIMD; a kernel
+// above 128 VGPRs fits one, whose two waves per SIMD still saturate the
+// issue); below
 // that the largest of 256 and 128 that still gives every CU a block, else 64,
 // so that small ensembles spread over as much of the chip as they can.  No
 // result depends on the block.
