@@ -183,8 +183,10 @@ aw_status aw_map_ensemble(const aw_ensemble *ens, int32_t n_ens,
                           double *const *state_out_dev, uint8_t *const *cls_dev,
                           const aw_tuning *tuning, void *stream);
 
-/* Rows of the resumable carry[AW_NCARRY][N]: X, P, tangent (scaled), X0, P0,
- * J sum, tangent scale exponent, steps done, left-the-window flag. */
+/* Rows of the resumable carry[AW_NCARRY][N], the propagation's own state in
+ * its rotated frame (u = x + y, v = x - y, z; momenta and tangent alike): X,
+ * P, tangent (scaled), X0 (original frame), P0, twice the J sum, tangent scale
+ * exponent, steps done, left-the-window flag.  Only the library reads it. */
 #define AW_NCARRY 22
 
 /* Resumable form of aw_map_ensemble for one ensemble: runs global steps

@@ -225,6 +225,82 @@ __device__ __forceinline__ void kick_tab(Orbit &o, double a2, double a4, const d
   o.pz = __builtin_fma(e2, pcc, o.pz);
 }
 
+// The propagation kernels run in the rotated frame u = x + y, v = x - y, with
+// momenta p_u = p_x + p_y, p_v = p_x - p_y and the tangent transformed alike
+// (the Orbit fields x, y, px, py, dx, dy, dpx, dpy then hold u, v, p_u, p_v,
+// du, dv, dp_u, dp_v).  The drift keeps its form (u advances by t p_u), and
+// eq. 2's H_p = 2 cx cy cz^2 equals (cos u + cos v) cz^2, so the force and its
+// Jacobian no longer couple u and v.  With e1 = a2 cz^2, e2 = a2 cz sz
+// (a2 = 2 t eps), cs = cos u + cos v:
+//   p_u += e1 sin u,  p_v += e1 sin v,  p_z += e2 cs,
+//   dp_u += e1 cos u du - 2 e2 sin u dz,
+//   dp_v += e1 cos v dv - 2 e2 sin v dz,
+//   dp_z += -e2 sin u du - e2 sin v dv + cs (2 e1 - a2) dz.
+template <bool TAN>
+__device__ __forceinline__ void kick_rot(Orbit &o, double a2, const double2 *__restrict__ tab) {
+  const SinCosT U = sincos_tab(o.x, tab), V = sincos_tab(o.y, tab);
+  const ZTerms Z = zterms_tab(o.z, tab);
+  const double e1 = a2 * Z.cz2;
+  const double e2 = a2 * Z.czsz;
+  const double cs = U.c + V.c;
+  if (TAN) {
+    const double k1 = e2 * U.s, k2 = e2 * V.s;
+    const double mu = e1 * U.c, mv = e1 * V.c;
+    const double mz = cs * __builtin_fma(2.0, e1, -a2);
+    const double du = o.dx, dv = o.dy, dz = o.dz;
+    const double m2dz = -2.0 * dz;
+    o.dpx = __builtin_fma(mu, du, __builtin_fma(k1, m2dz, o.dpx));
+    o.dpy = __builtin_fma(mv, dv, __builtin_fma(k2, m2dz, o.dpy));
+    o.dpz = __builtin_fma(-k1, du, __builtin_fma(-k2, dv, __builtin_fma(mz, dz, o.dpz)));
+  }
+  o.px = __builtin_fma(e1, U.s, o.px);
+  o.py = __builtin_fma(e1, V.s, o.py);
+  o.pz = __builtin_fma(e2, cs, o.pz);
+}
+
+template <bool TAN> struct KickRotOps {
+  static constexpr int fma = 2 * SCT_FMA + ZT_FMA + 3 + (TAN ? 1 + 7 : 0);
+  static constexpr int mul = 2 * SCT_MUL + ZT_MUL + 2 + (TAN ? 4 + 1 + 1 : 0);
+  static constexpr int add = 2 * SCT_ADD + ZT_ADD + 1;
+};
+
+// Into and out of the rotated frame (p0 alike; the tangent only with TAN).
+__device__ __forceinline__ void to_rot(Orbit &o) {
+  const double x = o.x, y = o.y, px = o.px, py = o.py;
+  o.x = x + y; o.y = x - y;
+  o.px = px + py; o.py = px - py;
+  const double p0x = o.p0x, p0y = o.p0y;
+  o.p0x = p0x + p0y; o.p0y = p0x - p0y;
+  const double dx = o.dx, dy = o.dy, dpx = o.dpx, dpy = o.dpy;
+  o.dx = dx + dy; o.dy = dx - dy;
+  o.dpx = dpx + dpy; o.dpy = dpx - dpy;
+}
+
+// Back to the original frame, as displacements from the initial state s0
+// (x, y, z, px, py, pz), whose rotated form is recomputed here exactly as
+// to_rot formed it: what the steps did not change comes back unchanged (at
+// eps = 0 the momenta exactly).
+__device__ __forceinline__ void from_rot(Orbit &o, const double (&s0)[6]) {
+#pragma clang fp contract(off)
+  const double du0 = o.x - (s0[0] + s0[1]), dv0 = o.y - (s0[0] - s0[1]);
+  const double dpu0 = o.px - (s0[3] + s0[4]), dpv0 = o.py - (s0[3] - s0[4]);
+  o.x = s0[0] + 0.5 * (du0 + dv0); o.y = s0[1] + 0.5 * (du0 - dv0);
+  o.px = s0[3] + 0.5 * (dpu0 + dpv0); o.py = s0[4] + 0.5 * (dpu0 - dpv0);
+  const double du = o.dx, dv = o.dy, dpu = o.dpx, dpv = o.dpy;
+  o.dx = 0.5 * (du + dv); o.dy = 0.5 * (du - dv);
+  o.dpx = 0.5 * (dpu + dpv); o.dpy = 0.5 * (dpu - dpv);
+}
+
+// In the rotated frame |P - P0|^2 = (du_p^2 + dv_p^2)/2 + dz_p^2: jsum collects
+// twice the step sum, (P_u - P0_u)^2 + (P_v - P0_v)^2 + 2 (P_z - P0_z)^2.
+__device__ __forceinline__ void accum_j_rot(Orbit &o) {
+  const double eu = o.px - o.p0x, ev = o.py - o.p0y, ez = o.pz - o.p0z;
+  const double ez2 = ez + ez;
+  o.jsum = __builtin_fma(eu, eu, o.jsum);
+  o.jsum = __builtin_fma(ev, ev, o.jsum);
+  o.jsum = __builtin_fma(ez, ez2, o.jsum);
+}
+
 template <bool TAN>
 __device__ __forceinline__ void drift(Orbit &o, double t) {
   o.x = __builtin_fma(t, o.px, o.x);
@@ -264,6 +340,26 @@ __device__ __forceinline__ void renorm(Orbit &o) {
   n2 = __builtin_fma(o.dpx, o.dpx, n2);
   n2 = __builtin_fma(o.dpy, o.dpy, n2);
   n2 = __builtin_fma(o.dpz, o.dpz, n2);
+  const int e = __builtin_amdgcn_frexp_exp(n2);
+  const int s = e >> 1;
+  o.dx = __builtin_amdgcn_ldexp(o.dx, -s);
+  o.dy = __builtin_amdgcn_ldexp(o.dy, -s);
+  o.dz = __builtin_amdgcn_ldexp(o.dz, -s);
+  o.dpx = __builtin_amdgcn_ldexp(o.dpx, -s);
+  o.dpy = __builtin_amdgcn_ldexp(o.dpy, -s);
+  o.dpz = __builtin_amdgcn_ldexp(o.dpz, -s);
+  o.kexp += s;
+}
+
+// renorm in the rotated frame: the tangent's true norm is
+// |w|^2 = (du^2 + dv^2 + dp_u^2 + dp_v^2)/2 + dz^2 + dp_z^2.
+__device__ __forceinline__ void renorm_rot(Orbit &o) {
+  double a = o.dx * o.dx;
+  a = __builtin_fma(o.dy, o.dy, a);
+  a = __builtin_fma(o.dpx, o.dpx, a);
+  a = __builtin_fma(o.dpy, o.dpy, a);
+  double n2 = __builtin_fma(o.dz, o.dz, o.dpz * o.dpz);
+  n2 = __builtin_fma(0.5, a, n2);
   const int e = __builtin_amdgcn_frexp_exp(n2);
   const int s = e >> 1;
   o.dx = __builtin_amdgcn_ldexp(o.dx, -s);

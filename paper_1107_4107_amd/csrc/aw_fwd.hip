@@ -97,10 +97,11 @@ __device__ __forceinline__ void gen_w0(uint64_t seed, int64_t n, double w[6]) {
 // ---------------------------------------------------------------------------
 // The distinct stage weights of the form, copied from the descriptor before
 // the step loop.
+// Stage weights of the rotated-frame step: the drift's t and the kick's
+// a2 = 2 t eps (the kick needs no other weight there).
 struct StepWeights {
   double drift[MAX_UNIQUE];
   double ka2[MAX_UNIQUE];
-  double ka4[MAX_UNIQUE];
 };
 
 template <int FORM, bool TAN, int OPL>
@@ -113,13 +114,13 @@ __device__ __forceinline__ void map_step(Orbit (&o)[OPL], const StepWeights &d, 
 #pragma unroll
       for (int j = 0; j < OPL; ++j) drift<TAN>(o[j], d.drift[F::drift_idx[i]]);
 #pragma unroll
-      for (int j = 0; j < OPL; ++j) kick_tab<TAN>(o[j], d.ka2[F::kick_idx[i]], d.ka4[F::kick_idx[i]], tab);
+      for (int j = 0; j < OPL; ++j) kick_rot<TAN>(o[j], d.ka2[F::kick_idx[i]], tab);
     }
 #pragma unroll
     for (int j = 0; j < OPL; ++j) drift<TAN>(o[j], d.drift[F::drift_idx[NK]]);
   } else {
 #pragma unroll
-    for (int j = 0; j < OPL; ++j) kick_tab<TAN>(o[j], d.ka2[0], d.ka4[0], tab);
+    for (int j = 0; j < OPL; ++j) kick_rot<TAN>(o[j], d.ka2[0], tab);
 #pragma unroll
     for (int j = 0; j < OPL; ++j) drift<TAN>(o[j], d.drift[0]);
   }
@@ -224,7 +225,9 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first, cons
         o[j].dx = o[j].dy = o[j].dz = o[j].dpx = o[j].dpy = o[j].dpz = 0.0;
       }
       if (FILT) left[j] = !in_window(s[3], s[4], s[5], d);
+      to_rot(o[j]);
     } else {
+      // The carry holds the rotated-frame state as the loop left it.
       const double *c = d.carry;
       const int64_t N = d.N, m = n[j];
       o[j].x = c[0 * N + m]; o[j].y = c[1 * N + m]; o[j].z = c[2 * N + m];
@@ -238,7 +241,7 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first, cons
     }
   }
 
-  // Positions at the start of this launch (time-window velocity).
+  // Positions at the start of this launch (time-window velocity; rotated).
   double xs[OPL], ys[OPL], zs[OPL];
   if (WINV) {
 #pragma unroll
@@ -260,7 +263,7 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first, cons
   // values): across the loop the descriptor fields of the epilogue hold most
   // SGPRs, and kick weights left there are spilled to VGPR lanes and read back
   // with v_readlane every step, 16 VALU instructions per S6 step and 32 per Y6
-  // step.  In VGPRs they cost 16 registers and no instruction.  The
+  // step.  In VGPRs they cost 8 registers and no instruction.  The
   // unrolled, two-orbit and window variants would lose occupancy and keep
   // them in SGPRs.
   constexpr bool kVregW = TAN && OPL == 1 && UNR == 1 && !FILT && !WINV;
@@ -269,23 +272,25 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first, cons
   for (int q = 0; q < MAX_UNIQUE; ++q) {
     sw.drift[q] = d.drift[q];
     sw.ka2[q] = d.ka2[q];
-    sw.ka4[q] = d.ka4[q];
     if (kVregW) {
+      asm volatile("" : "+v"(sw.drift[q]));
       asm volatile("" : "+v"(sw.ka2[q]));
-      asm volatile("" : "+v"(sw.ka4[q]));
     }
   }
   auto one_step = [&](int64_t k) {
     map_step<FORM, TAN, OPL>(o, sw, tab);
 #pragma unroll
-    for (int j = 0; j < OPL; ++j) accum_j(o[j]);
+    for (int j = 0; j < OPL; ++j) accum_j_rot(o[j]);
     if (FILT) {
+      // 2 P in the original frame, exactly: the window test depends only on
+      // the direction of P.
 #pragma unroll
-      for (int j = 0; j < OPL; ++j) left[j] = left[j] || !in_window(o[j].px, o[j].py, o[j].pz, d);
+      for (int j = 0; j < OPL; ++j)
+        left[j] = left[j] || !in_window(o[j].px + o[j].py, o[j].px - o[j].py, o[j].pz + o[j].pz, d);
     }
     if (TAN && ((k + 1) & mask) == 0) {
 #pragma unroll
-      for (int j = 0; j < OPL; ++j) renorm(o[j]);
+      for (int j = 0; j < OPL; ++j) renorm_rot(o[j]);
     }
   };
   int64_t k = k0;
@@ -305,8 +310,10 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first, cons
     for (int j = 0; j < OPL; ++j) {
       if (!act[j]) continue;
       if (WINV) {
+#pragma clang fp contract(off)
         double phi, mu;
-        vdir_key((o[j].x - xs[j]) / d.wdt, (o[j].y - ys[j]) / d.wdt, (o[j].z - zs[j]) / d.wdt, phi, mu);
+        const double du = o[j].x - xs[j], dv = o[j].y - ys[j];
+        vdir_key(0.5 * (du + dv) / d.wdt, 0.5 * (du - dv) / d.wdt, (o[j].z - zs[j]) / d.wdt, phi, mu);
         d.bins[n[j]] = left[j] ? BIN_DROP : bin_of(phi, mu, d.klo0, d.khi0, d.klo1, d.khi1, d.W, d.H, true);
       }
       double *c = d.carry;
@@ -339,6 +346,7 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first, cons
     const int64_t N = d.N, m = n[j];
     double s0[6];
     gen_ic(d, m, s0);
+    from_rot(o[j], s0);
     double res[9];
     double wn = 1.0;
     if (TAN) {
@@ -361,9 +369,9 @@ __device__ __forceinline__ void run_orbits(const FwdDesc &d, int64_t first, cons
     res[3] = (o[j].x - s0[0]) / d.th;
     res[4] = (o[j].y - s0[1]) / d.th;
     res[5] = (o[j].z - s0[2]) / d.th;
-    const double ex = o[j].px - o[j].p0x, ey = o[j].py - o[j].p0y, ez = o[j].pz - o[j].p0z;
+    const double ex = o[j].px - s0[3], ey = o[j].py - s0[4], ez = o[j].pz - s0[5];
     res[6] = ex * ex + ey * ey + ez * ez;
-    res[7] = o[j].jsum / (double)d.T;
+    res[7] = (0.5 * o[j].jsum) / (double)d.T;
     const double E1 = 0.5 * (o[j].px * o[j].px + o[j].py * o[j].py + o[j].pz * o[j].pz) +
                       d.eps * hp_value(o[j].x, o[j].y, o[j].z);
     const double E0 = 0.5 * (s0[3] * s0[3] + s0[4] * s0[4] + s0[5] * s0[5]) +
@@ -585,13 +593,13 @@ void step_op_counts(int form, bool tan, int64_t *fma, int64_t *mul, int64_t *add
   case 7: nk = 7; nd = 8; break;
   default: break;
   }
-  const int kf = tan ? KickTabOps<true>::fma : KickTabOps<false>::fma;
-  const int km = tan ? KickTabOps<true>::mul : KickTabOps<false>::mul;
-  const int ka = tan ? KickTabOps<true>::add : KickTabOps<false>::add;
+  const int kf = tan ? KickRotOps<true>::fma : KickRotOps<false>::fma;
+  const int km = tan ? KickRotOps<true>::mul : KickRotOps<false>::mul;
+  const int ka = tan ? KickRotOps<true>::add : KickRotOps<false>::add;
   const int df = tan ? DriftOps<true>::fma : DriftOps<false>::fma;
   *fma = (int64_t)nk * kf + (int64_t)nd * df + 3;  // + 3 fma of the J accumulator
   *mul = (int64_t)nk * km;
-  *add = (int64_t)nk * ka + 3;                     // + 3 subtractions of the J accumulator
+  *add = (int64_t)nk * ka + 4;                     // + 3 subtractions and a doubling (J accumulator)
 }
 
 }  // namespace aw

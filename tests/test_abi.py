@@ -161,25 +161,27 @@ def test_ftle_grad_workspace_and_validation():
 
 def test_step_op_counts_match_the_stage_structure():
     """Per map step: 9 kicks and 10 drifts for the 6th-order triple jump, 7
-    and 8 for Y6; the counts are those of the kernel's formulas.  A kick takes
-    the sincos of x and y from the 4096-entry table (8 fma, 4 mul, 1 add each)
-    and cos^2 z, cos z sin z from the same table at the doubled angle (9 fma,
-    3 mul, 1 add); the rest of a kick is 3 fma and 5 mul, plus 10 fma and 6 mul
-    for the tangent; a drift 3 fma, 6 with the tangent; the J accumulator 3 fma
-    and 3 subtractions."""
+    and 8 for Y6; the counts are those of the kernel's formulas in the rotated
+    frame u = x + y, v = x - y.  A kick takes the sincos of u and v from the
+    4096-entry table (8 fma, 4 mul, 1 add each) and cos^2 z, cos z sin z from
+    the same table at the doubled angle (9 fma, 3 mul, 1 add); the rest of a
+    kick is 3 fma, 2 mul and 1 add, plus 8 fma and 6 mul for the tangent; a
+    drift 3 fma, 6 with the tangent; the J accumulator 3 fma, 3 subtractions
+    and a doubling."""
     from paper_1107_4107_amd import step_op_counts
     sc_f, sc_m, sc_a = 8, 4, 1
     zt_f, zt_m, zt_a = 9, 3, 1
-    kick_t = (2 * sc_f + zt_f + 3 + 10, 2 * sc_m + zt_m + 5 + 6, 2 * sc_a + zt_a)
-    kick_n = (2 * sc_f + zt_f + 3, 2 * sc_m + zt_m + 5, 2 * sc_a + zt_a)
+    kick_t = (2 * sc_f + zt_f + 3 + 8, 2 * sc_m + zt_m + 2 + 6, 2 * sc_a + zt_a + 1)
+    kick_n = (2 * sc_f + zt_f + 3, 2 * sc_m + zt_m + 2, 2 * sc_a + zt_a + 1)
     f, m, a = step_op_counts("s6", True)
-    assert (f, m, a) == (9 * kick_t[0] + 10 * 6 + 3, 9 * kick_t[1], 9 * kick_t[2] + 3)
+    assert (f, m, a) == (9 * kick_t[0] + 10 * 6 + 3, 9 * kick_t[1], 9 * kick_t[2] + 4)
+    assert 2 * f + m + a == 985
     f, m, a = step_op_counts("y6", True)   # 7 kicks, 8 drifts
-    assert (f, m, a) == (7 * kick_t[0] + 8 * 6 + 3, 7 * kick_t[1], 7 * kick_t[2] + 3)
+    assert (f, m, a) == (7 * kick_t[0] + 8 * 6 + 3, 7 * kick_t[1], 7 * kick_t[2] + 4)
     f1, m1, a1 = step_op_counts("stdmap", True)
-    assert (f1, m1, a1) == (kick_t[0] + 6 + 3, kick_t[1], kick_t[2] + 3)
+    assert (f1, m1, a1) == (kick_t[0] + 6 + 3, kick_t[1], kick_t[2] + 4)
     f0, m0, a0 = step_op_counts("s6", False)
-    assert (f0, m0, a0) == (9 * kick_n[0] + 10 * 3 + 3, 9 * kick_n[1], 9 * kick_n[2] + 3)
+    assert (f0, m0, a0) == (9 * kick_n[0] + 10 * 3 + 3, 9 * kick_n[1], 9 * kick_n[2] + 4)
 
 
 def test_y6_weights_agree_between_the_two_derivations():

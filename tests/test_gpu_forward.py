@@ -62,7 +62,10 @@ def test_states_match_for_short_runs(aw, form):
     assert_close(out[0], out_o[0], 1e-10, what="L")
     assert_close(out[3:6], out_o[3:6], 1e-11, what="V")
     assert_close(out[6:8], out_o[6:8], 1e-9, floor=1e-6, what="dP2, J")
-    assert np.max(np.abs(out[8] - out_o[8])) < 1e-13
+    # dE carries the state's rounding times |P| (E is near 40 at |P| = 2 pi sqrt 2,
+    # where an ulp is 7e-15); the GPU steps in the rotated frame, rounded apart
+    # from the oracle's (x, y) steps by a few ulps of the state.
+    assert np.max(np.abs(out[8] - out_o[8])) < 5e-13
 
 
 @pytest.mark.parametrize("form,pz0", [("s6", 0.0), ("s6", 1.0), ("stdmap", 0.0), ("y6", 1.0)])

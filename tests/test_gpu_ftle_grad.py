@@ -99,7 +99,11 @@ def test_ftle_gradient_against_gpu_differences(aw):
         ee = aw.Ensemble(eps=ep, n_steps=T, ic_kind="explicit", n_orbits=64, tangent=True)
         return np_(aw.map_ensemble(ee, x, want_class=False).orbit_out[aw.OUT_L])
 
-    np.testing.assert_allclose(np_(L), Lf(icd, eps), rtol=0, atol=1e-13)
+    # The forward kernel steps in the rotated frame (x + y, x - y), the adjoint
+    # in (x, y): the same map, rounded differently, so L agrees to rounding on
+    # the regular orbits (the chaotic ones amplify it).
+    reg = np_(L) / np.log(1 + T * H) < 1.5
+    np.testing.assert_allclose(np_(L)[reg], Lf(icd, eps)[reg], rtol=1e-10, atol=0)
     fd = np.empty((7, 64))
     for c in range(6):
         dp = icd.clone()
@@ -108,7 +112,6 @@ def test_ftle_gradient_against_gpu_differences(aw):
         dm[c] -= d
         fd[c] = (Lf(dp, eps) - Lf(dm, eps)) / (2 * d)
     fd[6] = (Lf(icd, eps + d) - Lf(icd, eps - d)) / (2 * d)
-    reg = np_(L) / np.log(1 + T * H) < 1.5
     assert reg.sum() > 16
     _per_orbit_close(g[:, reg], fd[:, reg], 2e-6, "dL vs differences")
     torch.cuda.synchronize()
