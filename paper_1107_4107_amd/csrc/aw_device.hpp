@@ -183,8 +183,9 @@ struct Orbit {
   int kexp;                            // tangent scale exponent (|w| true = |w| 2^kexp)
 };
 
-// Kick with weight a2 = 2 t eps, a4 = 4 t eps = 2 a2, sines and cosines from
-// the block's LDS table (true values: no sign folding).  Every force and
+// Kick in the (x, y) frame of eq. 2, as the adjoint kernels step it, with
+// weight a2 = 2 t eps, a4 = 4 t eps = 2 a2, sines and cosines from the block's
+// LDS table (true values: no sign folding).  Every force and
 // Hessian term of eq. 2 is a product of one x factor, one y factor and z
 // factors:
 //   e1 = 2 t eps cz^2, e2 = 4 t eps cz sz, e3 = 4 t eps (cz^2 - sz^2) = 4 e1 - a4,
@@ -314,11 +315,6 @@ __device__ __forceinline__ void drift(Orbit &o, double t) {
 }
 
 // Op counts of kick/drift (roofline accounting).
-template <bool TAN> struct KickTabOps {
-  static constexpr int fma = 2 * SCT_FMA + ZT_FMA + 3 + (TAN ? 1 + 9 : 0);
-  static constexpr int mul = 2 * SCT_MUL + ZT_MUL + 5 + (TAN ? 6 : 0);
-  static constexpr int add = 2 * SCT_ADD + ZT_ADD;
-};
 template <bool TAN> struct DriftOps {
   static constexpr int fma = TAN ? 6 : 3;
 };
