@@ -15,6 +15,10 @@
 // and the source of J, (2 gJ / T)(P_k - P_0), enters Pbar at every step
 // boundary k >= 1.  The explicit P_0 dependence of J adds
 // -(2 gJ / T) sum_k (P_k - P_0) to the initial-momentum gradient.
+// All of it runs in the rotated frame of the forward kernels (u = x + y,
+// v = x - y, momenta alike), where the kick's Jacobian has 7 non-zero entries;
+// the checkpoints and step states hold rotated states, and the gradient is
+// taken back to (x, y) at the end.
 // Each lane only reads back what it wrote itself, so no synchronisation
 // between lanes is needed.
 //
@@ -40,11 +44,11 @@ __device__ __forceinline__ void adj_step_fwd(Orbit &o, const AdjDesc &d, const d
 #pragma unroll
     for (int i = 0; i < NK; ++i) {
       drift<false>(o, d.drift[F::drift_idx[i]]);
-      kick_tab<false>(o, d.ka2[F::kick_idx[i]], d.ka4[F::kick_idx[i]], tab);
+      kick_rot<false>(o, d.ka2[F::kick_idx[i]], tab);
     }
     drift<false>(o, d.drift[F::drift_idx[NK]]);
   } else {
-    kick_tab<false>(o, d.ka2[0], d.ka4[0], tab);
+    kick_rot<false>(o, d.ka2[0], tab);
     drift<false>(o, d.drift[0]);
   }
 }
@@ -63,37 +67,35 @@ __device__ __forceinline__ void rev_drift(Orbit &o, Adjoint &a, double t) {
   a.pzb = __builtin_fma(t, a.zb, a.pzb);
 }
 
-// Undo K(t) on the state and apply its transpose to the adjoint.
-// a2 = 2 t eps, a4 = 4 t eps, w2 = 2 t, w4 = 4 t.  Sines and cosines from the
-// same table as the forward kick, so the undone kick matches it.
-__device__ __forceinline__ void rev_kick(Orbit &o, Adjoint &a, double a2, double a4, double w2,
-                                         double w4, const double2 *__restrict__ tab) {
-  const SinCosT X = sincos_tab(o.x, tab), Y = sincos_tab(o.y, tab);
+// Undo K(t) on the state and apply its transpose to the adjoint, in the
+// rotated frame of the forward kernels (u = x + y, v = x - y; the Adjoint's
+// xb, yb, pxb, pyb hold the adjoints of u, v, p_u, p_v).  a2 = 2 t eps,
+// w2 = 2 t.  With e1 = a2 cz^2, e2 = a2 cz sz, cs = cos u + cos v the kick is
+// F = (e1 sin u, e1 sin v, e2 cs) and its Jacobian
+//   [[e1 cos u, 0, -2 e2 sin u], [0, e1 cos v, -2 e2 sin v],
+//    [-e2 sin u, -e2 sin v, cs (2 e1 - a2)]],
+// whose transpose acts on Pbar; dF/deps = F / eps.  Sines and cosines from
+// the same table as the forward kick, so the undone kick matches it.
+__device__ __forceinline__ void rev_kick(Orbit &o, Adjoint &a, double a2, double w2,
+                                         const double2 *__restrict__ tab) {
+  const SinCosT U = sincos_tab(o.x, tab), V = sincos_tab(o.y, tab);
   const ZTerms Z = zterms_tab(o.z, tab);
-  const double cx = X.c, sx = X.s;
-  const double cy = Y.c, sy = Y.s;
-  const double psc = sx * cy, pcs = cx * sy, pcc = cx * cy, pss = sx * sy;
-  const double e1 = a2 * Z.cz2, e2 = a4 * Z.czsz, e3 = __builtin_fma(4.0, e1, -a4);
-  const double f1 = w2 * Z.cz2, f2 = w4 * Z.czsz;
-  // d(P after kick)/d eps = -t grad Hp = (f1 psc, f1 pcs, f2 pcc).
-  a.eb = __builtin_fma(f1, __builtin_fma(psc, a.pxb, pcs * a.pyb), a.eb);
-  a.eb = __builtin_fma(f2 * pcc, a.pzb, a.eb);
-  // Xbar += (-t eps Hess) Pbar, the same symmetric matrix as the tangent kick.
-  const double mxx = e1 * pcc, nxy = e1 * pss, nxz = e2 * psc, nyz = e2 * pcs, mzz = e3 * pcc;
-  const double pxb = a.pxb, pyb = a.pyb, pzb = a.pzb;
-  a.xb = __builtin_fma(mxx, pxb, a.xb);
-  a.xb = __builtin_fma(-nxy, pyb, a.xb);
-  a.xb = __builtin_fma(-nxz, pzb, a.xb);
-  a.yb = __builtin_fma(-nxy, pxb, a.yb);
-  a.yb = __builtin_fma(mxx, pyb, a.yb);
-  a.yb = __builtin_fma(-nyz, pzb, a.yb);
-  a.zb = __builtin_fma(-nxz, pxb, a.zb);
-  a.zb = __builtin_fma(-nyz, pyb, a.zb);
-  a.zb = __builtin_fma(mzz, pzb, a.zb);
+  const double e1 = a2 * Z.cz2, e2 = a2 * Z.czsz;
+  const double f1 = w2 * Z.cz2, f2 = w2 * Z.czsz;
+  const double cs = U.c + V.c;
+  const double pub = a.pxb, pvb = a.pyb, pzb = a.pzb;
+  const double q = __builtin_fma(U.s, pub, V.s * pvb);   // sin u pu_bar + sin v pv_bar
+  a.eb = __builtin_fma(f1, q, a.eb);
+  a.eb = __builtin_fma(f2 * cs, pzb, a.eb);
+  const double e2p = e2 * pzb;
+  a.xb = __builtin_fma(e1 * U.c, pub, __builtin_fma(-U.s, e2p, a.xb));
+  a.yb = __builtin_fma(e1 * V.c, pvb, __builtin_fma(-V.s, e2p, a.yb));
+  const double mz = cs * __builtin_fma(2.0, e1, -a2);
+  a.zb = __builtin_fma(mz, pzb, __builtin_fma(-2.0 * e2, q, a.zb));
   // P before the kick.
-  o.px = __builtin_fma(-e1, psc, o.px);
-  o.py = __builtin_fma(-e1, pcs, o.py);
-  o.pz = __builtin_fma(-e2, pcc, o.pz);
+  o.px = __builtin_fma(-e1, U.s, o.px);
+  o.py = __builtin_fma(-e1, V.s, o.py);
+  o.pz = __builtin_fma(-e2, cs, o.pz);
 }
 
 template <int FORM>
@@ -105,12 +107,12 @@ __device__ __forceinline__ void adj_step_rev(Orbit &o, Adjoint &a, const AdjDesc
 #pragma unroll
     for (int i = NK - 1; i >= 0; --i) {
       const int u = F::kick_idx[i];
-      rev_kick(o, a, d.ka2[u], d.ka4[u], d.kw2[u], d.kw4[u], tab);
+      rev_kick(o, a, d.ka2[u], d.kw2[u], tab);
       rev_drift(o, a, d.drift[F::drift_idx[i]]);
     }
   } else {
     rev_drift(o, a, d.drift[0]);
-    rev_kick(o, a, d.ka2[0], d.ka4[0], d.kw2[0], d.kw4[0], tab);
+    rev_kick(o, a, d.ka2[0], d.kw2[0], tab);
   }
 }
 
@@ -133,6 +135,8 @@ __global__ __launch_bounds__(512) void k_adj_fwd(AdjDesc d) {
   Orbit o;
   load6(d.ic, d.N, n, o);
   o.p0x = o.px; o.p0y = o.py; o.p0z = o.pz;
+  o.dx = o.dy = o.dz = o.dpx = o.dpy = o.dpz = 0.0;
+  to_rot(o);
   o.jsum = 0.0;
   for (int64_t s = 0; s < d.n_seg; ++s) {
     store6(d.ckpts + s * 6 * d.N, d.N, n, o);
@@ -140,12 +144,28 @@ __global__ __launch_bounds__(512) void k_adj_fwd(AdjDesc d) {
     const int64_t g1 = g0 + d.ckpt < d.T ? g0 + d.ckpt : d.T;
     for (int64_t g = g0; g < g1; ++g) {
       adj_step_fwd<FORM>(o, d, s_tab);
-      accum_j(o);
+      accum_j_rot(o);
       if (d.fwd_steps) store6(d.steps + g * 6 * d.N, d.N, n, o);  // one segment: g0 = 0
     }
   }
   store6(d.ckpts + d.n_seg * 6 * d.N, d.N, n, o);   // the final state
-  if (d.J) d.J[n] = o.jsum / (double)d.T;
+  if (d.J) d.J[n] = (0.5 * o.jsum) / (double)d.T;
+}
+
+// The initial-state gradient: the explicit P_0 share of J, then back from the
+// rotated frame (u = x + y, v = x - y, so d/dx = d/du + d/dv and
+// d/dy = d/du - d/dv; momenta alike).
+__device__ __forceinline__ void store_grad(const AdjDesc &d, int64_t n, const Adjoint &a, double ch, double c,
+                                           double su, double sv, double sz) {
+  const int64_t N = d.N;
+  const double pub = __builtin_fma(-ch, su, a.pxb), pvb = __builtin_fma(-ch, sv, a.pyb);
+  d.gic[0 * N + n] = a.xb + a.yb;
+  d.gic[1 * N + n] = a.xb - a.yb;
+  d.gic[2 * N + n] = a.zb;
+  d.gic[3 * N + n] = pub + pvb;
+  d.gic[4 * N + n] = pub - pvb;
+  d.gic[5 * N + n] = __builtin_fma(-c, sz, a.pzb);
+  d.geps[n] = a.eb;
 }
 
 template <int FORM>
@@ -155,8 +175,13 @@ __global__ __launch_bounds__(512) void k_adj_bwd_rev(AdjDesc d) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= d.N) return;
   const int64_t N = d.N;
-  const double p0x = d.ic[3 * N + n], p0y = d.ic[4 * N + n], p0z = d.ic[5 * N + n];
+  // P_0 in the rotated frame, rounded as the forward pass formed it.
+  const double p0x = d.ic[3 * N + n] + d.ic[4 * N + n], p0y = d.ic[3 * N + n] - d.ic[4 * N + n];
+  const double p0z = d.ic[5 * N + n];
+  // J = (1/T) sum ((P_u - P0_u)^2 + (P_v - P0_v)^2) / 2 + (P_z - P0_z)^2: the
+  // source is c/2 on p_u and p_v and c on p_z.
   const double c = 2.0 * (d.gJ ? d.gJ[n] : 1.0) / (double)d.T;
+  const double ch = 0.5 * c;
   Adjoint a{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   double sx = 0.0, sy = 0.0, sz = 0.0;  // sum_k (P_k - P_0)
   Orbit o;
@@ -170,20 +195,14 @@ __global__ __launch_bounds__(512) void k_adj_bwd_rev(AdjDesc d) {
     load6(d.ckpts + (s + 1) * 6 * N, N, n, o);        // exact state after step g1 - 1
     for (int64_t g = g1 - 1; g >= g0; --g) {
       const double ex = o.px - p0x, ey = o.py - p0y, ez = o.pz - p0z;
-      a.pxb = __builtin_fma(c, ex, a.pxb);
-      a.pyb = __builtin_fma(c, ey, a.pyb);
+      a.pxb = __builtin_fma(ch, ex, a.pxb);
+      a.pyb = __builtin_fma(ch, ey, a.pyb);
       a.pzb = __builtin_fma(c, ez, a.pzb);
       sx += ex; sy += ey; sz += ez;
       adj_step_rev<FORM>(o, a, d, s_tab);              // state now at the start of step g
     }
   }
-  d.gic[0 * N + n] = a.xb;
-  d.gic[1 * N + n] = a.yb;
-  d.gic[2 * N + n] = a.zb;
-  d.gic[3 * N + n] = __builtin_fma(-c, sx, a.pxb);
-  d.gic[4 * N + n] = __builtin_fma(-c, sy, a.pyb);
-  d.gic[5 * N + n] = __builtin_fma(-c, sz, a.pzb);
-  d.geps[n] = a.eb;
+  store_grad(d, n, a, ch, c, sx, sy, sz);
 }
 
 template <int FORM>
@@ -193,8 +212,13 @@ __global__ __launch_bounds__(512) void k_adj_bwd(AdjDesc d) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= d.N) return;
   const int64_t N = d.N;
-  const double p0x = d.ic[3 * N + n], p0y = d.ic[4 * N + n], p0z = d.ic[5 * N + n];
+  // P_0 in the rotated frame, rounded as the forward pass formed it.
+  const double p0x = d.ic[3 * N + n] + d.ic[4 * N + n], p0y = d.ic[3 * N + n] - d.ic[4 * N + n];
+  const double p0z = d.ic[5 * N + n];
+  // J = (1/T) sum ((P_u - P0_u)^2 + (P_v - P0_v)^2) / 2 + (P_z - P0_z)^2: the
+  // source is c/2 on p_u and p_v and c on p_z.
   const double c = 2.0 * (d.gJ ? d.gJ[n] : 1.0) / (double)d.T;
+  const double ch = 0.5 * c;
   Adjoint a{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   double sx = 0.0, sy = 0.0, sz = 0.0;  // sum_k (P_k - P_0)
   Orbit o;
@@ -214,20 +238,14 @@ __global__ __launch_bounds__(512) void k_adj_bwd(AdjDesc d) {
     for (int64_t g = g1 - 1; g >= g0; --g) {
       load6(d.steps + (g - g0) * 6 * N, N, n, o);   // state after step g
       const double ex = o.px - p0x, ey = o.py - p0y, ez = o.pz - p0z;
-      a.pxb = __builtin_fma(c, ex, a.pxb);
-      a.pyb = __builtin_fma(c, ey, a.pyb);
+      a.pxb = __builtin_fma(ch, ex, a.pxb);
+      a.pyb = __builtin_fma(ch, ey, a.pyb);
       a.pzb = __builtin_fma(c, ez, a.pzb);
       sx += ex; sy += ey; sz += ez;
       adj_step_rev<FORM>(o, a, d, s_tab);
     }
   }
-  d.gic[0 * N + n] = a.xb;
-  d.gic[1 * N + n] = a.yb;
-  d.gic[2 * N + n] = a.zb;
-  d.gic[3 * N + n] = __builtin_fma(-c, sx, a.pxb);
-  d.gic[4 * N + n] = __builtin_fma(-c, sy, a.pyb);
-  d.gic[5 * N + n] = __builtin_fma(-c, sz, a.pzb);
-  d.geps[n] = a.eb;
+  store_grad(d, n, a, ch, c, sx, sy, sz);
 }
 
 hipError_t launch_adj_forward(const AdjDesc &d, int form, const Tuning &t, hipStream_t s) {
