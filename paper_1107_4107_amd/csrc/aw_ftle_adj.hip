@@ -15,6 +15,11 @@
 //                epsbar += -t grad Hp(X) . Pbar - t (Hess Hp(X) dX) . dPbar
 // where T3 is the third-derivative tensor of Hp (symmetric), contracted
 // with dX and dPbar.  The end condition is dL/dw_T = w_T / |w_T|^2.
+// The kernels step in the rotated frame of the forward kernels (u = x + y,
+// v = x - y, momenta and tangent alike): there the kick's Jacobian has 7
+// non-zero entries and is not symmetric (the frame is not orthonormal), the
+// norm of w carries the weights (1/2, 1/2, 1, 1/2, 1/2, 1), and the gradient
+// is taken back to (x, y) at the end.
 //
 // The tangent is rescaled by exact powers of two after every 8th step
 // (global step count), as in the forward kernel.  A rescale w <- 2^-k w is
@@ -59,11 +64,11 @@ __device__ __forceinline__ void tan_step(Orbit &o, const AdjDesc &d, const doubl
 #pragma unroll
     for (int i = 0; i < NK; ++i) {
       drift<true>(o, d.drift[F::drift_idx[i]]);
-      kick_tab<true>(o, d.ka2[F::kick_idx[i]], d.ka4[F::kick_idx[i]], tab);
+      kick_rot<true>(o, d.ka2[F::kick_idx[i]], tab);
     }
     drift<true>(o, d.drift[F::drift_idx[NK]]);
   } else {
-    kick_tab<true>(o, d.ka2[0], d.ka4[0], tab);
+    kick_rot<true>(o, d.ka2[0], tab);
     drift<true>(o, d.drift[0]);
   }
 }
@@ -90,91 +95,77 @@ __device__ __forceinline__ void rev_drift2(Orbit &o, Adjoint2 &a, double t) {
   a.dpzb = __builtin_fma(t, a.dzb, a.dpzb);
 }
 
-// Undo K(t) and apply its transpose.  a2 = 2 t eps, a4 = 4 t eps, w2 = 2 t,
-// w4 = 4 t.  Sines and cosines from the same table as the forward kick.
-//   t eps Hp_xxx = t eps Hp_xyy = e1 sx cy     t eps Hp_xxy = t eps Hp_yyy = e1 cx sy
-//   t eps Hp_xxz = t eps Hp_yyz = e2 cx cy     t eps Hp_xyz = -e2 sx sy
-//   t eps Hp_xzz = e3 sx cy   t eps Hp_yzz = e3 cx sy   t eps Hp_zzz = 4 e2 cx cy
-// with e1 = 2 t eps cz^2, e2 = 4 t eps cz sz, e3 = 4 t eps (cz^2 - sz^2).
-__device__ __forceinline__ void rev_kick2(Orbit &o, Adjoint2 &a, double a2, double a4, double w2, double w4,
+// Undo K(t) and apply its transpose, in the rotated frame of the steps
+// (u = x + y, v = x - y; the Adjoint2's x, y, px, py fields hold u, v, p_u,
+// p_v and their tangents).  a2 = 2 t eps, w2 = 2 t.  With e1 = a2 cz^2,
+// e2 = a2 cz sz, g = 2 e1 - a2 (= de2/dz; de1/dz = -2 e2) and
+// cs = cos u + cos v, the kick is F = (e1 sin u, e1 sin v, e2 cs) with Jacobian
+//   M = [[e1 cos u, 0, -2 e2 sin u], [0, e1 cos v, -2 e2 sin v],
+//        [-e2 sin u, -e2 sin v, cs g]],
+// and the tangent kick dP += M dX.  Its transpose gives
+//   Xbar  += M^T Pbar + S,   S_k = sum_ij dPbar_i (dM_ij/dX_k) dX_j,
+//   dXbar += M^T dPbar,      epsbar += (F . Pbar + (M dX) . dPbar) / eps,
+// where, with Bu = e2 cos u du + g sin u dz, Bv = e2 cos v dv + g sin v dz,
+//   S_u = -dPbar_u (e1 sin u du + 2 e2 cos u dz) - dPbar_z Bu,
+//   S_v = -dPbar_v (e1 sin v dv + 2 e2 cos v dz) - dPbar_z Bv,
+//   S_z = -2 dPbar_u Bu - 2 dPbar_v Bv
+//         - dPbar_z (g sin u du + g sin v dv + 4 e2 cs dz).
+// Sines and cosines from the same table as the forward kick.
+__device__ __forceinline__ void rev_kick2(Orbit &o, Adjoint2 &a, double a2, double w2,
                                           const double2 *__restrict__ tab) {
-  const SinCosT X = sincos_tab(o.x, tab), Y = sincos_tab(o.y, tab);
+  const SinCosT U = sincos_tab(o.x, tab), V = sincos_tab(o.y, tab);
   const ZTerms Z = zterms_tab(o.z, tab);
-  const double cx = X.c, sx = X.s;
-  const double cy = Y.c, sy = Y.s;
-  const double psc = sx * cy, pcs = cx * sy, pcc = cx * cy, pss = sx * sy;
-  const double e1 = a2 * Z.cz2, e2 = a4 * Z.czsz, e3 = __builtin_fma(4.0, e1, -a4);
-  // M = -t eps Hess: diagonal mxx (= myy), mzz; off-diagonal -nxy, -nxz, -nyz.
-  const double mxx = e1 * pcc, nxy = e1 * pss, nxz = e2 * psc, nyz = e2 * pcs, mzz = e3 * pcc;
-  // The same matrix per unit eps (for epsbar).
-  const double f1 = w2 * Z.cz2, f2 = w4 * Z.czsz, f3 = __builtin_fma(4.0, f1, -w4);
-  const double wxx = f1 * pcc, vxy = f1 * pss, vxz = f2 * psc, vyz = f2 * pcs, wzz = f3 * pcc;
-  const double dx = o.dx, dy = o.dy, dz = o.dz;
-  const double pxb = a.pxb, pyb = a.pyb, pzb = a.pzb;
-  const double dpxb = a.dpxb, dpyb = a.dpyb, dpzb = a.dpzb;
+  const double e1 = a2 * Z.cz2, e2 = a2 * Z.czsz, g = __builtin_fma(2.0, e1, -a2);
+  const double f1 = w2 * Z.cz2, f2 = w2 * Z.czsz, gf = __builtin_fma(2.0, f1, -w2);
+  const double cs = U.c + V.c;
+  const double du = o.dx, dv = o.dy, dz = o.dz;
+  const double pub = a.pxb, pvb = a.pyb, pzb = a.pzb;
+  const double dpub = a.dpxb, dpvb = a.dpyb, dpzb = a.dpzb;
+  // M and M / eps.
+  const double muu = e1 * U.c, mvv = e1 * V.c, muz = -2.0 * e2 * U.s, mvz = -2.0 * e2 * V.s;
+  const double mzu = -e2 * U.s, mzv = -e2 * V.s, mzz = cs * g;
+  const double wuu = f1 * U.c, wvv = f1 * V.c, wuz = -2.0 * f2 * U.s, wvz = -2.0 * f2 * V.s;
+  const double wzu = -f2 * U.s, wzv = -f2 * V.s, wzz = cs * gf;
 
-  // epsbar: d(P')/d eps = -t grad Hp, d(dP')/d eps = (M / eps) dX.
+  // epsbar.
   double eb = a.eb;
-  eb = __builtin_fma(f1, __builtin_fma(psc, pxb, pcs * pyb), eb);
-  eb = __builtin_fma(f2 * pcc, pzb, eb);
-  const double ux = __builtin_fma(wxx, dx, __builtin_fma(-vxy, dy, -vxz * dz));
-  const double uy = __builtin_fma(-vxy, dx, __builtin_fma(wxx, dy, -vyz * dz));
-  const double uz = __builtin_fma(-vxz, dx, __builtin_fma(-vyz, dy, wzz * dz));
-  eb = __builtin_fma(ux, dpxb, eb);
-  eb = __builtin_fma(uy, dpyb, eb);
-  eb = __builtin_fma(uz, dpzb, eb);
+  eb = __builtin_fma(f1, __builtin_fma(U.s, pub, V.s * pvb), eb);
+  eb = __builtin_fma(f2 * cs, pzb, eb);
+  eb = __builtin_fma(__builtin_fma(wuu, du, wuz * dz), dpub, eb);
+  eb = __builtin_fma(__builtin_fma(wvv, dv, wvz * dz), dpvb, eb);
+  eb = __builtin_fma(__builtin_fma(wzu, du, __builtin_fma(wzv, dv, wzz * dz)), dpzb, eb);
   a.eb = eb;
 
-  // Xbar += M Pbar.
+  // Xbar += M^T Pbar + S.
+  const double e2cu = e2 * U.c, e2cv = e2 * V.c, gsu = g * U.s, gsv = g * V.s;
+  const double Au = __builtin_fma(e1 * U.s, du, 2.0 * e2cu * dz);
+  const double Av = __builtin_fma(e1 * V.s, dv, 2.0 * e2cv * dz);
+  const double Bu = __builtin_fma(e2cu, du, gsu * dz);
+  const double Bv = __builtin_fma(e2cv, dv, gsv * dz);
+  const double Cz = __builtin_fma(gsu, du, __builtin_fma(gsv, dv, 4.0 * e2 * cs * dz));
   double xb = a.xb, yb = a.yb, zb = a.zb;
-  xb = __builtin_fma(mxx, pxb, xb);
-  xb = __builtin_fma(-nxy, pyb, xb);
-  xb = __builtin_fma(-nxz, pzb, xb);
-  yb = __builtin_fma(-nxy, pxb, yb);
-  yb = __builtin_fma(mxx, pyb, yb);
-  yb = __builtin_fma(-nyz, pzb, yb);
-  zb = __builtin_fma(-nxz, pxb, zb);
-  zb = __builtin_fma(-nyz, pyb, zb);
-  zb = __builtin_fma(mzz, pzb, zb);
-  // Xbar -= t eps T3[dX, dPbar] from the symmetric products of dX and dPbar.
-  const double mdiag = __builtin_fma(dx, dpxb, dy * dpyb);        // dx dpxb + dy dpyb
-  const double mz = dz * dpzb;
-  const double sxy = __builtin_fma(dx, dpyb, dy * dpxb);
-  const double sxz = __builtin_fma(dx, dpzb, dz * dpxb);
-  const double syz = __builtin_fma(dy, dpzb, dz * dpyb);
-  const double q1 = e1 * psc, q2 = e1 * pcs, q3 = e2 * pcc, q4 = -(e2 * pss), q5 = e3 * psc, q6 = e3 * pcs;
-  const double q7 = 4.0 * q3;
-  xb = __builtin_fma(-q1, mdiag, xb);
-  xb = __builtin_fma(-q2, sxy, xb);
-  xb = __builtin_fma(-q3, sxz, xb);
-  xb = __builtin_fma(-q4, syz, xb);
-  xb = __builtin_fma(-q5, mz, xb);
-  yb = __builtin_fma(-q2, mdiag, yb);
-  yb = __builtin_fma(-q1, sxy, yb);
-  yb = __builtin_fma(-q4, sxz, yb);
-  yb = __builtin_fma(-q3, syz, yb);
-  yb = __builtin_fma(-q6, mz, yb);
-  zb = __builtin_fma(-q3, mdiag, zb);
-  zb = __builtin_fma(-q4, sxy, zb);
-  zb = __builtin_fma(-q5, sxz, zb);
-  zb = __builtin_fma(-q6, syz, zb);
-  zb = __builtin_fma(-q7, mz, zb);
+  xb = __builtin_fma(muu, pub, __builtin_fma(mzu, pzb, xb));
+  yb = __builtin_fma(mvv, pvb, __builtin_fma(mzv, pzb, yb));
+  zb = __builtin_fma(muz, pub, __builtin_fma(mvz, pvb, __builtin_fma(mzz, pzb, zb)));
+  xb = __builtin_fma(-dpub, Au, __builtin_fma(-dpzb, Bu, xb));
+  yb = __builtin_fma(-dpvb, Av, __builtin_fma(-dpzb, Bv, yb));
+  zb = __builtin_fma(-2.0 * dpub, Bu, __builtin_fma(-2.0 * dpvb, Bv, __builtin_fma(-dpzb, Cz, zb)));
   a.xb = xb;
   a.yb = yb;
   a.zb = zb;
 
-  // dXbar += M dPbar.
-  a.dxb = __builtin_fma(mxx, dpxb, __builtin_fma(-nxy, dpyb, __builtin_fma(-nxz, dpzb, a.dxb)));
-  a.dyb = __builtin_fma(-nxy, dpxb, __builtin_fma(mxx, dpyb, __builtin_fma(-nyz, dpzb, a.dyb)));
-  a.dzb = __builtin_fma(-nxz, dpxb, __builtin_fma(-nyz, dpyb, __builtin_fma(mzz, dpzb, a.dzb)));
+  // dXbar += M^T dPbar.
+  a.dxb = __builtin_fma(muu, dpub, __builtin_fma(mzu, dpzb, a.dxb));
+  a.dyb = __builtin_fma(mvv, dpvb, __builtin_fma(mzv, dpzb, a.dyb));
+  a.dzb = __builtin_fma(muz, dpub, __builtin_fma(mvz, dpvb, __builtin_fma(mzz, dpzb, a.dzb)));
 
-  // Undo the kick: dP -= M dX, P -= (e1 sx cy, e1 cx sy, e2 cx cy).
-  o.dpx = __builtin_fma(-mxx, dx, __builtin_fma(nxy, dy, __builtin_fma(nxz, dz, o.dpx)));
-  o.dpy = __builtin_fma(nxy, dx, __builtin_fma(-mxx, dy, __builtin_fma(nyz, dz, o.dpy)));
-  o.dpz = __builtin_fma(nxz, dx, __builtin_fma(nyz, dy, __builtin_fma(-mzz, dz, o.dpz)));
-  o.px = __builtin_fma(-e1, psc, o.px);
-  o.py = __builtin_fma(-e1, pcs, o.py);
-  o.pz = __builtin_fma(-e2, pcc, o.pz);
+  // Undo the kick: dP -= M dX, P -= F.
+  o.dpx = __builtin_fma(-muu, du, __builtin_fma(-muz, dz, o.dpx));
+  o.dpy = __builtin_fma(-mvv, dv, __builtin_fma(-mvz, dz, o.dpy));
+  o.dpz = __builtin_fma(-mzu, du, __builtin_fma(-mzv, dv, __builtin_fma(-mzz, dz, o.dpz)));
+  o.px = __builtin_fma(-e1, U.s, o.px);
+  o.py = __builtin_fma(-e1, V.s, o.py);
+  o.pz = __builtin_fma(-e2, cs, o.pz);
 }
 
 template <int FORM>
@@ -186,12 +177,12 @@ __device__ __forceinline__ void rev_tan_step(Orbit &o, Adjoint2 &a, const AdjDes
 #pragma unroll
     for (int i = NK - 1; i >= 0; --i) {
       const int u = F::kick_idx[i];
-      rev_kick2(o, a, d.ka2[u], d.ka4[u], d.kw2[u], d.kw4[u], tab);
+      rev_kick2(o, a, d.ka2[u], d.kw2[u], tab);
       rev_drift2(o, a, d.drift[F::drift_idx[i]]);
     }
   } else {
     rev_drift2(o, a, d.drift[0]);
-    rev_kick2(o, a, d.ka2[0], d.ka4[0], d.kw2[0], d.kw4[0], tab);
+    rev_kick2(o, a, d.ka2[0], d.kw2[0], tab);
   }
 }
 
@@ -209,6 +200,39 @@ __device__ __forceinline__ void store12(double *p, int64_t N, int64_t n, const O
   p[9 * N + n] = o.dpx; p[10 * N + n] = o.dpy; p[11 * N + n] = o.dpz;
 }
 
+// The tangent's norm in the rotated frame of the steps:
+// |w|^2 = (du^2 + dv^2 + dp_u^2 + dp_v^2)/2 + dz^2 + dp_z^2.
+__device__ __forceinline__ double tan_norm2_rot(const Orbit &o) {
+  double a = o.dx * o.dx;
+  a = __builtin_fma(o.dy, o.dy, a);
+  a = __builtin_fma(o.dpx, o.dpx, a);
+  a = __builtin_fma(o.dpy, o.dpy, a);
+  const double n2 = __builtin_fma(o.dz, o.dz, o.dpz * o.dpz);
+  return __builtin_fma(0.5, a, n2);
+}
+
+// dL/dw_T = G w_T / |w_T|^2 in the rotated frame, G = diag(1/2, 1/2, 1, 1/2, 1/2, 1),
+// scaled by the upstream gradient gl.
+__device__ __forceinline__ void end_condition(const Orbit &o, Adjoint2 &a, double gl) {
+  const double c = gl / tan_norm2_rot(o);
+  const double h = 0.5 * c;
+  a.dxb = h * o.dx; a.dyb = h * o.dy; a.dzb = c * o.dz;
+  a.dpxb = h * o.dpx; a.dpyb = h * o.dpy; a.dpzb = c * o.dpz;
+}
+
+// The initial-state gradient, back from the rotated frame (d/dx = d/du + d/dv,
+// d/dy = d/du - d/dv; momenta alike).
+__device__ __forceinline__ void store_grad2(const FtleDesc &d, int64_t n, const Adjoint2 &a) {
+  const int64_t N = d.N;
+  d.gic[0 * N + n] = a.xb + a.yb;
+  d.gic[1 * N + n] = a.xb - a.yb;
+  d.gic[2 * N + n] = a.zb;
+  d.gic[3 * N + n] = a.pxb + a.pyb;
+  d.gic[4 * N + n] = a.pxb - a.pyb;
+  d.gic[5 * N + n] = a.pzb;
+  d.geps[n] = a.eb;
+}
+
 __device__ __forceinline__ double tan_norm2(const Orbit &o) {
   double n2 = o.dx * o.dx;
   n2 = __builtin_fma(o.dy, o.dy, n2);
@@ -223,7 +247,7 @@ __device__ __forceinline__ double tan_norm2(const Orbit &o) {
 __device__ __forceinline__ int rescale_exponent(const Orbit &o) {
   Orbit t = o;
   t.kexp = 0;
-  renorm(t);
+  renorm_rot(t);
   return t.kexp;
 }
 
@@ -243,6 +267,7 @@ __global__ __launch_bounds__(512) void k_ftle_fwd(FtleDesc d) {
   o.jsum = 0.0;
   o.kexp = 0;
   const double n0 = tan_norm2(o);
+  to_rot(o);
   for (int64_t s = 0; s < d.n_seg; ++s) {
     store12(d.ckpts + s * 12 * N, N, n, o);
     const int64_t g0 = s * d.ckpt;
@@ -252,14 +277,14 @@ __global__ __launch_bounds__(512) void k_ftle_fwd(FtleDesc d) {
       if (d.fwd_steps) store12(d.steps + g * 12 * N, N, n, o);  // one segment: g0 = 0
       if (((g + 1) & RESCALE_MASK) == 0) {
         const int k0 = o.kexp;
-        renorm(o);
+        renorm_rot(o);
         d.exps[((g + 1) / (RESCALE_MASK + 1) - 1) * N + n] = (int16_t)(o.kexp - k0);
       }
     }
   }
   store12(d.ckpts + d.n_seg * 12 * N, N, n, o);   // the final state (after any last rescale)
   if (d.L) {
-    const double n2 = tan_norm2(o);
+    const double n2 = tan_norm2_rot(o);
     const int e = __builtin_amdgcn_frexp_exp(n2);
     const double mant = __builtin_amdgcn_frexp_mant(n2);
     d.L[n] = 0.5 * ((double)(2 * o.kexp + e) * LN2_D + log(mant)) - 0.5 * log(n0);
@@ -287,16 +312,14 @@ __global__ __launch_bounds__(512) void k_ftle_bwd(FtleDesc d) {
       for (int64_t g = g0; g < g1; ++g) {
         tan_step<FORM>(o, d, s_tab);
         store12(d.steps + (g - g0) * 12 * N, N, n, o);
-        if (((g + 1) & RESCALE_MASK) == 0) renorm(o);
+        if (((g + 1) & RESCALE_MASK) == 0) renorm_rot(o);
       }
     }
     for (int64_t g = g1 - 1; g >= g0; --g) {
       load12(d.steps + (g - g0) * 12 * N, N, n, o);   // end of step g, before any rescale
       if (g == d.T - 1) {
         // dL/dw_T = w_T / |w_T|^2 (scaled by the upstream gradient).
-        const double c = gl / tan_norm2(o);
-        a.dxb = c * o.dx; a.dyb = c * o.dy; a.dzb = c * o.dz;
-        a.dpxb = c * o.dpx; a.dpyb = c * o.dpy; a.dpzb = c * o.dpz;
+        end_condition(o, a, gl);
       } else if (((g + 1) & RESCALE_MASK) == 0) {
         const int k = rescale_exponent(o);
         a.dxb = __builtin_amdgcn_ldexp(a.dxb, -k);
@@ -309,13 +332,7 @@ __global__ __launch_bounds__(512) void k_ftle_bwd(FtleDesc d) {
       rev_tan_step<FORM>(o, a, d, s_tab);
     }
   }
-  d.gic[0 * N + n] = a.xb;
-  d.gic[1 * N + n] = a.yb;
-  d.gic[2 * N + n] = a.zb;
-  d.gic[3 * N + n] = a.pxb;
-  d.gic[4 * N + n] = a.pyb;
-  d.gic[5 * N + n] = a.pzb;
-  d.geps[n] = a.eb;
+  store_grad2(d, n, a);
 }
 
 template <int FORM>
@@ -339,9 +356,7 @@ __global__ __launch_bounds__(512) void k_ftle_bwd_rev(FtleDesc d) {
     for (int64_t g = g1 - 1; g >= g0; --g) {
       // o: the state at the end of step g, after any rescale that followed it.
       if (g == d.T - 1) {
-        const double c = gl / tan_norm2(o);
-        a.dxb = c * o.dx; a.dyb = c * o.dy; a.dzb = c * o.dz;
-        a.dpxb = c * o.dpx; a.dpyb = c * o.dpy; a.dpzb = c * o.dpz;
+        end_condition(o, a, gl);
       }
       if (((g + 1) & RESCALE_MASK) == 0) {
         // the forward set w_post = 2^-k w_pre: restore w_pre, and wbar_pre = 2^-k wbar_post
@@ -362,13 +377,7 @@ __global__ __launch_bounds__(512) void k_ftle_bwd_rev(FtleDesc d) {
       rev_tan_step<FORM>(o, a, d, s_tab);   // o: the state at the start of step g
     }
   }
-  d.gic[0 * N + n] = a.xb;
-  d.gic[1 * N + n] = a.yb;
-  d.gic[2 * N + n] = a.zb;
-  d.gic[3 * N + n] = a.pxb;
-  d.gic[4 * N + n] = a.pyb;
-  d.gic[5 * N + n] = a.pzb;
-  d.geps[n] = a.eb;
+  store_grad2(d, n, a);
 }
 
 }  // namespace
