@@ -183,49 +183,6 @@ struct Orbit {
   int kexp;                            // tangent scale exponent (|w| true = |w| 2^kexp)
 };
 
-// Kick in the (x, y) frame of eq. 2, as the adjoint kernels step it, with
-// weight a2 = 2 t eps, a4 = 4 t eps = 2 a2, sines and cosines from the block's
-// LDS table (true values: no sign folding).  Every force and
-// Hessian term of eq. 2 is a product of one x factor, one y factor and z
-// factors:
-//   e1 = 2 t eps cz^2, e2 = 4 t eps cz sz, e3 = 4 t eps (cz^2 - sz^2) = 4 e1 - a4,
-//   P  += (e1 sx cy, e1 cx sy, e2 cx cy)                 (= -t eps grad Hp)
-//   dP += M dX, M = [[e1 cx cy, -e1 sx sy, -e2 sx cy],
-//                    [-e1 sx sy, e1 cx cy, -e2 cx sy],
-//                    [-e2 sx cy, -e2 cx sy, e3 cx cy]]     (= -t eps Hess Hp)
-template <bool TAN>
-__device__ __forceinline__ void kick_tab(Orbit &o, double a2, double a4, const double2 *__restrict__ tab) {
-  const SinCosT X = sincos_tab(o.x, tab), Y = sincos_tab(o.y, tab);
-  const ZTerms Z = zterms_tab(o.z, tab);
-  const double cx = X.c, sx = X.s;
-  const double cy = Y.c, sy = Y.s;
-  const double e1 = a2 * Z.cz2;
-  const double e2 = a4 * Z.czsz;
-  const double psc = sx * cy, pcs = cx * sy, pcc = cx * cy;
-  if (TAN) {
-    const double e3 = __builtin_fma(4.0, e1, -a4);
-    const double pss = sx * sy;
-    const double mxx = e1 * pcc;
-    const double nxy = e1 * pss;
-    const double nxz = e2 * psc;
-    const double nyz = e2 * pcs;
-    const double mzz = e3 * pcc;
-    const double dx = o.dx, dy = o.dy, dz = o.dz;
-    o.dpx = __builtin_fma(mxx, dx, o.dpx);
-    o.dpx = __builtin_fma(-nxy, dy, o.dpx);
-    o.dpx = __builtin_fma(-nxz, dz, o.dpx);
-    o.dpy = __builtin_fma(-nxy, dx, o.dpy);
-    o.dpy = __builtin_fma(mxx, dy, o.dpy);
-    o.dpy = __builtin_fma(-nyz, dz, o.dpy);
-    o.dpz = __builtin_fma(-nxz, dx, o.dpz);
-    o.dpz = __builtin_fma(-nyz, dy, o.dpz);
-    o.dpz = __builtin_fma(mzz, dz, o.dpz);
-  }
-  o.px = __builtin_fma(e1, psc, o.px);
-  o.py = __builtin_fma(e1, pcs, o.py);
-  o.pz = __builtin_fma(e2, pcc, o.pz);
-}
-
 // The propagation kernels run in the rotated frame u = x + y, v = x - y, with
 // momenta p_u = p_x + p_y, p_v = p_x - p_y and the tangent transformed alike
 // (the Orbit fields x, y, px, py, dx, dy, dpx, dpy then hold u, v, p_u, p_v,
@@ -319,35 +276,9 @@ template <bool TAN> struct DriftOps {
   static constexpr int fma = TAN ? 6 : 3;
 };
 
-// Accumulate |P - P0|^2.
-__device__ __forceinline__ void accum_j(Orbit &o) {
-  const double ex = o.px - o.p0x, ey = o.py - o.p0y, ez = o.pz - o.p0z;
-  o.jsum = __builtin_fma(ex, ex, o.jsum);
-  o.jsum = __builtin_fma(ey, ey, o.jsum);
-  o.jsum = __builtin_fma(ez, ez, o.jsum);
-}
-
-// Rescale the tangent vector by an exact power of two so that |w|^2 lies in
+// Rescale the tangent by an exact power of two so that |w|^2 lies in
 // [0.5, 2); the scale is accumulated in kexp.  Exact: it changes no mantissa.
-__device__ __forceinline__ void renorm(Orbit &o) {
-  double n2 = o.dx * o.dx;
-  n2 = __builtin_fma(o.dy, o.dy, n2);
-  n2 = __builtin_fma(o.dz, o.dz, n2);
-  n2 = __builtin_fma(o.dpx, o.dpx, n2);
-  n2 = __builtin_fma(o.dpy, o.dpy, n2);
-  n2 = __builtin_fma(o.dpz, o.dpz, n2);
-  const int e = __builtin_amdgcn_frexp_exp(n2);
-  const int s = e >> 1;
-  o.dx = __builtin_amdgcn_ldexp(o.dx, -s);
-  o.dy = __builtin_amdgcn_ldexp(o.dy, -s);
-  o.dz = __builtin_amdgcn_ldexp(o.dz, -s);
-  o.dpx = __builtin_amdgcn_ldexp(o.dpx, -s);
-  o.dpy = __builtin_amdgcn_ldexp(o.dpy, -s);
-  o.dpz = __builtin_amdgcn_ldexp(o.dpz, -s);
-  o.kexp += s;
-}
-
-// renorm in the rotated frame: the tangent's true norm is
+// In the rotated frame the tangent's true norm is
 // |w|^2 = (du^2 + dv^2 + dp_u^2 + dp_v^2)/2 + dz^2 + dp_z^2.
 __device__ __forceinline__ void renorm_rot(Orbit &o) {
   double a = o.dx * o.dx;
