@@ -122,6 +122,19 @@ def test_symmetry_zeros_on_the_invariant_plane(aw):
 
 
 @pytest.mark.parametrize("reversible", [False, True])
+def test_integrable_limit_gradient_is_zero(aw, reversible):
+    """At eps = 0 every kick adds exactly zero, so P_k = P_0 at every step, J = 0
+    for every initial state, and its whole gradient vanishes exactly (d/deps
+    too: J is of second order in eps)."""
+    print_case("adjoint eps=0", reversible)
+    ic = oracle.ic_box([0.0] * 6, [2 * np.pi] * 6, 9, 64)
+    e = aw.Ensemble(eps=0.0, n_steps=200, ic_kind="explicit", n_orbits=64, tangent=False)
+    J, gic, geps = aw.indicator_grad(e, tensor(ic), ckpt_every=30, reversible=reversible)
+    assert np.all(np_(J) == 0.0)
+    assert np.all(np_(gic) == 0.0) and np.all(np_(geps) == 0.0)
+
+
+@pytest.mark.parametrize("reversible", [False, True])
 def test_autograd_function(aw, reversible):
     import torch
     print_case("autograd", reversible)

@@ -130,6 +130,26 @@ def test_ftle_gradient_independent_of_checkpoints(aw):
             np.testing.assert_array_equal(np_(a), np_(b))
 
 
+@pytest.mark.parametrize("reversible", [False, True])
+def test_ftle_gradient_integrable_limit(aw, reversible):
+    """At eps = 0 the map is free flight, X += t P: L takes the closed form
+    ln(|dX0 + T h dP0|^2 + |dP0|^2)/2 - ln|w0|^2/2, which does not depend on the
+    initial state.  Every kick and its derivatives are then exactly zero, so
+    the state gradient vanishes exactly."""
+    print_case("ftle grad eps=0", reversible)
+    T, N = 300, 32
+    ic = oracle.ic_box([0.0] * 6, [2 * np.pi] * 6, 19, N)
+    w0 = oracle.w0(0, N)
+    L, gic, geps = aw.ftle_grad(_explicit(aw, 0.0, T, N), _to_dev(ic), _to_dev(w0), ckpt_every=40,
+                                reversible=reversible)
+    th = T * H
+    Lc = 0.5 * np.log(np.sum((w0[0:3] + th * w0[3:6]) ** 2, axis=0) + np.sum(w0[3:6] ** 2, axis=0)) \
+        - 0.5 * np.log(np.sum(w0 ** 2, axis=0))
+    np.testing.assert_allclose(np_(L), Lc, rtol=1e-11, atol=0)
+    assert np.all(np_(gic) == 0.0)
+    assert np.all(np.isfinite(np_(geps)))
+
+
 def test_ftle_gradient_edge_cases(aw):
     """T = 1 (one step, no rescale), T = 8 (the last step is a rescale step),
     one orbit, and an empty ensemble."""
