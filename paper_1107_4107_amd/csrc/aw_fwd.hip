@@ -437,8 +437,11 @@ __global__ __launch_bounds__((FILT || WINV) ? 256 : 512) void k_fwd(FwdDesc d) {
 
 // Persistent batched propagation: each workgroup takes (ensemble, tile)
 // items from a device counter until the list, sorted longest-first, is empty.
+// Two orbits per lane take about 266 VGPRs in the rotated frame; held to 256
+// (two waves per SIMD instead of one, the spills outside the step loop) the
+// batch runs a fifth faster.
 template <int FORM, bool TAN, int OPL>
-__global__ __launch_bounds__(256) void k_fwd_persist(const FwdDesc *__restrict__ descs,
+__global__ __launch_bounds__(256, OPL > 1 ? 2 : 1) void k_fwd_persist(const FwdDesc *__restrict__ descs,
                                                      const WorkItem *__restrict__ items,
                                                      int32_t n_items, uint32_t *head) {
   __shared__ double2 s_tab[AW_TAB_N];
