@@ -26,10 +26,18 @@
  *    return nothing was enqueued (AW_EDEVICE: a launch failed) and
  *    aw_last_error() gives a message.  No C++ exception crosses the ABI.
  *  - Asynchronous device faults surface at the caller's next synchronisation.
- *  - Internal scratch (histogram sort buffers, batch tables) is allocated by
- *    the library on first use, grown when needed and kept per device until
- *    aw_release() or process exit; calls that overlap on one device through
- *    different streams must not share the library (they share that scratch).
+ *  - Internal scratch (histogram items and sort buffers, batch tables) is
+ *    one area per (device, stream), allocated by the library on first use and
+ *    kept until aw_release() or process exit, so calls on different streams
+ *    may overlap.  An area too small for a call is replaced by one at least
+ *    twice its size; the old one is retired (earlier work on the stream may
+ *    still use it) and freed by aw_release().  The call path never frees
+ *    device memory (hipFree waits for the device) and never waits for the
+ *    device: to keep it from allocating at all, size the stream's area up
+ *    front with aw_image_workspace() and aw_reserve().  Batch tables travel
+ *    through pinned host buffers that are reused once their copies are done.
+ *    A stream handle's area is tied to the handle's value: destroy a stream
+ *    only after its work has finished before reusing the handle.
  */
 #ifndef AW_H
 #define AW_H
@@ -54,7 +62,8 @@ typedef enum {
 const char *aw_last_error(void);
 /* Library version string. */
 const char *aw_version(void);
-/* Frees the library's internal scratch on the current device (synchronises it). */
+/* Frees the library's internal scratch, retired areas and staging buffers on
+ * the current device (synchronises it). */
 aw_status aw_release(void);
 
 /* Map forms (section "Computational method"): the first-order coupled
@@ -237,6 +246,15 @@ aw_status aw_indicator_image(const aw_ensemble *ens, int32_t n_ens, const aw_ima
                              double *const *image_dev, uint32_t *const *counts_dev,
                              uint8_t *const *cls_dev, const aw_tuning *tuning, void *stream);
 
+/* Bytes of library scratch that one aw_indicator_image call over these
+ * ensembles and spec takes on its stream (spec = NULL: one aw_map_ensemble
+ * call over them; 0 for a single ensemble).  Validates like the call. */
+aw_status aw_image_workspace(const aw_ensemble *ens, int32_t n_ens, const aw_image_spec *spec, size_t *bytes);
+/* Grows the library scratch of `stream` on the current device to at least
+ * `bytes` now (an allocation; it does not wait for the device), so that later
+ * calls on the stream that need no more allocate nothing. */
+aw_status aw_reserve(size_t bytes, void *stream);
+
 /* Time-window density of Fig. 4 (section "Main results"): F averaged over the
  * windows between two plots.  Runs n_windows consecutive windows of
  * window_steps map steps each, starting at global step k_begin (0 = from the
@@ -347,9 +365,15 @@ aw_status aw_ftle_grad_reversible(const aw_ensemble *ens, const double *ic_dev, 
                                   double *grad_ic_dev, double *grad_eps_dev, void *workspace_dev, size_t ws_bytes,
                                   const aw_tuning *tuning, void *stream);
 
-/* A captured HIP graph of aw_indicator_image over n_ens ensembles (one
- * persistent launch plus the reductions).  Buffers are bound at creation;
- * the descriptors are copied.  Launching replays the whole batch. */
+/* A captured HIP graph of aw_indicator_image over n_ens ensembles: the
+ * class-counter clears, one persistent launch (one plain launch for a single
+ * ensemble) and, for HIST_P0 and HIST_VDIR images, every ensemble's histogram
+ * reduction.  The graph owns its scratch area and batch tables (allocated
+ * here, freed by aw_graph_destroy); caller buffers are bound at creation and
+ * the descriptors copied.  Every launch status of the capture is checked: on
+ * a failure the capture is ended, nothing is returned in *out and the status
+ * is AW_EDEVICE.  Launching replays the whole batch; replays on different
+ * streams must not overlap (they share the graph's scratch). */
 typedef struct aw_graph aw_graph;
 aw_status aw_graph_create(const aw_ensemble *ens, int32_t n_ens, const aw_image_spec *spec,
                           double *const *image_dev, uint32_t *const *counts_dev,

@@ -26,17 +26,32 @@ FORMS = {"stdmap": STDMAP, "s2": S2, "s4": S4, "s6": S6, "y6": Y6}
 OUT_ROWS = ("L", "lambda", "chi", "Vx", "Vy", "Vz", "dP2", "J", "dE")
 REC_LEN = 21
 
-CFLAGS = ["-O2", "-std=c11", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+CFLAGS = ["-O3", "-std=c11", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
           "-shared", "-fPIC", "-Wall", "-Wextra"]
+# Build variants.  "default" is portable (it is built here and may run on
+# another host); "native" tunes for the host that builds it (the CPU-baseline
+# timing builds it on the machine it times); "sanitize" instruments the oracle
+# with AddressSanitizer and UndefinedBehaviorSanitizer for the CPU tests.
+# Contraction stays off in every variant, so all of them compute bitwise the
+# same results.
+VARIANT_FLAGS = {
+    "default": [],
+    "native": ["-march=native"],
+    "sanitize": ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                 "-fno-sanitize-recover=undefined"],
+}
+# Set to the path of another build of the oracle to load that one instead.
+LIB_ENV = "AW_ORACLE_LIB"
 
 
-def build(force: bool = True) -> str:
+def build(force: bool = True, variant: str = "default", out: str | None = None) -> str:
     """Compile the oracle with gcc (no FMA contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.run(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"], check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+    out = out or _LIB
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp"
+        subprocess.run(["gcc", *CFLAGS, *VARIANT_FLAGS[variant], "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, out)
+    return out
 
 
 _lib = None
@@ -50,9 +65,17 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    path = os.environ.get(LIB_ENV) or _LIB
+    if path == _LIB and (not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
         build(force=True)
-    lib = ctypes.CDLL(_LIB)
+    lib = open_library(path)
+    _lib = lib
+    return lib
+
+
+def open_library(path: str):
+    """Load one build of the oracle and declare its entry points."""
+    lib = ctypes.CDLL(path)
     i, l, d, u64 = ctypes.c_int, ctypes.c_long, ctypes.c_double, ctypes.c_uint64
     sig = {
         "oracle_rec_init": (None, [_dp, _dp, _dp]),
@@ -87,7 +110,6 @@ def _load():
         f = getattr(lib, name)
         f.restype = res
         f.argtypes = args
-    _lib = lib
     return lib
 
 

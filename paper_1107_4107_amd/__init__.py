@@ -28,7 +28,8 @@ OUT_ROWS = ("L", "lambda", "chi", "Vx", "Vy", "Vz", "dP2", "J", "dE")
 
 __all__ = [
     "Ensemble", "Tuning", "ImageSpec", "map_ensemble", "map_ensembles", "map_ensemble_steps",
-    "indicator_image", "indicator_images", "histogram2d", "vdir_keys", "generate_ic",
+    "indicator_image", "indicator_images", "histogram2d", "vdir_keys", "generate_ic", "image_workspace_bytes",
+    "reserve",
     "indicator_grad", "IndicatorJ", "ftle_grad_workspace_bytes", "ftle_grad", "IndicatorL", "Graph", "timing_enable", "timing_read", "step_op_counts",
     "AwError", "H_PAPER", "OUT_ROWS",
 ]
@@ -298,6 +299,22 @@ def vdir_keys(V: torch.Tensor):
     return phi, mu
 
 
+def image_workspace_bytes(ens: List[Ensemble], spec: Optional[ImageSpec]) -> int:
+    """Library scratch one indicator_images (spec None: map_ensembles) call over
+    these ensembles takes on its stream."""
+    n = len(ens)
+    c_ens = (_abi.AwEnsemble * n)(*[e.to_c() for e in ens])
+    nb = ctypes.c_size_t()
+    _abi.check(_lib().aw_image_workspace(c_ens, n, ctypes.byref(spec.to_c()) if spec is not None else None,
+                                         ctypes.byref(nb)))
+    return int(nb.value)
+
+
+def reserve(nbytes: int) -> None:
+    """Grow the current stream's library scratch to at least nbytes now."""
+    _abi.check(_lib().aw_reserve(int(nbytes), _stream()))
+
+
 def generate_ic(ens: Ensemble, ic_in: Optional[torch.Tensor] = None):
     """The exact initial state ic[6, N] and tangent start w0[6, N] of an ensemble."""
     dev = _device()
@@ -439,7 +456,8 @@ class IndicatorL(torch.autograd.Function):
 
 
 class Graph:
-    """A HIP graph of the batched IC-grid image path (aw_graph_*)."""
+    """A HIP graph of the image path (aw_graph_*): the persistent launch over
+    every ensemble and, for histogram images, their reductions."""
 
     def __init__(self, ens: List[Ensemble], spec: ImageSpec, images: List[torch.Tensor],
                  counts: Optional[List[torch.Tensor]] = None, classes: Optional[List[torch.Tensor]] = None,

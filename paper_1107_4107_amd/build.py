@@ -2,10 +2,12 @@
 peak and clock probe the benchmark uses) in-tree with hipcc."""
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import shutil
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -42,16 +44,29 @@ def command(out: str = LIB, extra=(), sources=SOURCES) -> list:
     return [hipcc(), *HIPCC_FLAGS, *extra, "-I", INCLUDE, "-I", CSRC, *srcs, "-o", out]
 
 
-def _compile(lib: str, sources, verbose: bool) -> str:
-    tmp = lib + ".tmp"
-    cmd = command(tmp, sources=sources)
+def _run(cmd, verbose: bool, what: str) -> None:
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError(f"hipcc failed building {os.path.basename(lib)}")
-    os.replace(tmp, lib)
+        raise RuntimeError(f"hipcc failed building {what}")
+
+
+def _compile(lib: str, sources, verbose: bool) -> str:
+    """Compile each source to an object in parallel, then link the library."""
+    flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    with tempfile.TemporaryDirectory(prefix="aw_build_") as tmpdir:
+        objs = [os.path.join(tmpdir, os.path.splitext(s)[0] + ".o") for s in sources]
+        cmds = [[hipcc(), *flags, "-c", "-I", INCLUDE, "-I", CSRC, os.path.join(CSRC, s), "-o", o]
+                for s, o in zip(sources, objs)]
+        workers = max(1, min(len(cmds), (os.cpu_count() or 1)))
+        with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(lambda c: _run(c, verbose, os.path.basename(c[-3])), cmds))
+        tmp = lib + ".tmp"
+        _run([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp], verbose,
+             os.path.basename(lib))
+        os.replace(tmp, lib)
     return lib
 
 

@@ -41,47 +41,118 @@ aw_status hip_fail(hipError_t e, const char *what) {
 }
 
 // ---------------------------------------------------------------------------
-// Library scratch per device (grow-only).
+// Scratch layout of one call: one area, carved into 256-byte aligned parts.
 // ---------------------------------------------------------------------------
-struct Buf {
-  void *p = nullptr;
-  size_t n = 0;
+constexpr size_t align_up(size_t n) { return (n + 255) / 256 * 256; }
+
+struct Layout {
+  // byte offsets into the area
+  size_t bins = 0, vals = 0;                               // per orbit, every ensemble (histograms)
+  size_t block_counts = 0, block_dropped = 0, tile_start = 0;
+  size_t sorted_local = 0, sorted_val = 0;                 // the largest single reduction
+  size_t descs = 0, items = 0, head = 0;                   // tables of a batched launch
+  size_t total = 0;
 };
 
-struct DevScratch {
-  Buf bins, vals, block_counts, block_dropped, tile_start, sorted_local, sorted_val;
-  Buf descs, items, head;
-  void *stage = nullptr;  // pinned host staging of batch tables
-  size_t stage_n = 0;
-  hipEvent_t stage_done = nullptr;
+// hist: histogram images over n_all orbits in all, of which one reduction
+// sorts at most n_max items into n_tiles tiles; vals: the items carry values;
+// n_descs, n_items: tables of a batched launch (0 for none).
+constexpr Layout layout_of(bool hist, bool vals, int64_t n_all, int64_t n_max, int64_t n_tiles, size_t n_descs,
+                           size_t n_items) {
+  Layout l{};
+  size_t o = 0;
+  if (hist) {
+    const size_t na = (size_t)(n_all > 0 ? n_all : 1), nm = (size_t)(n_max > 0 ? n_max : 1);
+    const size_t G = (nm + HIST_ITEMS_PER_BLOCK - 1) / HIST_ITEMS_PER_BLOCK;
+    l.bins = o;
+    o += align_up(sizeof(uint32_t) * na);
+    if (vals) {
+      l.vals = o;
+      o += align_up(sizeof(double) * na);
+    }
+    l.block_counts = o;
+    o += align_up(sizeof(uint32_t) * (size_t)n_tiles * G);
+    l.block_dropped = o;
+    o += align_up(sizeof(uint32_t) * G);
+    l.tile_start = o;
+    o += align_up(sizeof(uint32_t) * (2 * (size_t)n_tiles + 1));
+    l.sorted_local = o;
+    o += align_up(sizeof(uint16_t) * nm);
+    if (vals) {
+      l.sorted_val = o;
+      o += align_up(sizeof(double) * nm);
+    }
+  }
+  if (n_descs > 0) {
+    l.descs = o;
+    o += align_up(sizeof(FwdDesc) * n_descs);
+    l.items = o;
+    o += align_up(sizeof(WorkItem) * (n_items ? n_items : 1));
+    l.head = o;
+    o += align_up(sizeof(uint32_t));
+  }
+  l.total = o;
+  return l;
+}
+
+HistScratch hist_scratch_at(char *base, const Layout &l, bool vals, int64_t n_tiles) {
+  HistScratch w;
+  w.block_counts = (uint32_t *)(base + l.block_counts);
+  w.block_dropped = (uint32_t *)(base + l.block_dropped);
+  w.tile_start = (uint32_t *)(base + l.tile_start);
+  w.tile_total = w.tile_start + n_tiles + 1;
+  w.sorted_local = (uint16_t *)(base + l.sorted_local);
+  w.sorted_val = vals ? (double *)(base + l.sorted_val) : nullptr;
+  return w;
+}
+
+// ---------------------------------------------------------------------------
+// Library scratch: one area per (device, stream), so that calls on different
+// streams never share it.  It grows by allocating a larger area -- at least
+// twice the old one, so that retired areas add up to less than the live one --
+// and retiring the old area, which earlier work on the stream may still be
+// using.  hipFree waits for the device, so the call path never frees: retired
+// areas and staging buffers are freed by aw_release().
+// ---------------------------------------------------------------------------
+// Pinned host staging of batch tables, reused once its copies are done.
+struct Stage {
+  void *p = nullptr;
+  size_t n = 0;
+  hipEvent_t done = nullptr;  // recorded after the copies out of p
+};
+
+struct StreamScratch {
+  void *area = nullptr;
+  size_t n = 0;
+  std::vector<Stage> stages;
+};
+
+struct Retired {
+  std::vector<void *> dev;
 };
 
 std::mutex g_mu;
-std::map<int, DevScratch> g_scratch;
+std::map<std::pair<int, uintptr_t>, StreamScratch> g_scratch;
+std::map<int, Retired> g_retired;
 
-hipError_t grow(Buf &b, size_t need) {
-  if (need == 0) need = 256;
-  if (b.n >= need) return hipSuccess;
-  if (b.p) {
-    hipError_t e = hipFree(b.p);
-    if (e != hipSuccess) return e;
-    b.p = nullptr;
-    b.n = 0;
-  }
-  size_t n = need + need / 4;
-  hipError_t e = hipMalloc(&b.p, n);
-  if (e != hipSuccess) {
-    b.p = nullptr;
-    return e;
-  }
-  b.n = n;
-  return hipSuccess;
-}
-
-DevScratch &scratch() {
+int cur_device() {
   int dev = 0;
   (void)hipGetDevice(&dev);
-  return g_scratch[dev];
+  return dev;
+}
+
+StreamScratch &stream_scratch(hipStream_t s) { return g_scratch[{cur_device(), (uintptr_t)s}]; }
+
+aw_status reserve_area(StreamScratch &sc, size_t need) {
+  if (sc.n >= need) return AW_OK;
+  const size_t n = std::max(need, 2 * sc.n);
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, n);
+  if (e != hipSuccess) return fail(AW_ENOMEM, "library scratch of %zu bytes: %s", n, hipGetErrorString(e));
+  if (sc.area) g_retired[cur_device()].dev.push_back(sc.area);
+  sc.area = p;
+  sc.n = n;
+  return AW_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -383,31 +454,41 @@ int persistent_wgs(int form, bool tan, const Tuning &t) {
   return ncu * persistent_blocks_per_cu(form, tan, t);
 }
 
-aw_status upload_tables(DevScratch &sc, const std::vector<FwdDesc> &descs, const std::vector<WorkItem> &items,
-                        hipStream_t s) {
+// Copy the batch tables into the area (at l.descs and l.items) through one of
+// the stream's pinned staging buffers: one whose earlier copies have finished,
+// or a new one -- the host never waits for the device here.
+aw_status upload_tables(StreamScratch &sc, const Layout &l, const std::vector<FwdDesc> &descs,
+                        const std::vector<WorkItem> &items, hipStream_t s) {
   const size_t bd = descs.size() * sizeof(FwdDesc), bi = items.size() * sizeof(WorkItem);
   hipError_t e;
-  if ((e = grow(sc.descs, bd)) != hipSuccess || (e = grow(sc.items, bi)) != hipSuccess ||
-      (e = grow(sc.head, 256)) != hipSuccess)
-    return fail(AW_ENOMEM, "batch tables: %s", hipGetErrorString(e));
-  if (!sc.stage_done && (e = hipEventCreateWithFlags(&sc.stage_done, hipEventDisableTiming)) != hipSuccess)
-    return hip_fail(e, "hipEventCreate");
-  // The pinned staging buffer may still feed the previous batch's copy.
-  if ((e = hipEventSynchronize(sc.stage_done)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
-  if (sc.stage_n < bd + bi) {
-    if (sc.stage) (void)hipHostFree(sc.stage);
-    sc.stage = nullptr;
-    sc.stage_n = 0;
-    if ((e = hipHostMalloc(&sc.stage, bd + bi, hipHostMallocDefault)) != hipSuccess)
-      return fail(AW_ENOMEM, "pinned staging: %s", hipGetErrorString(e));
-    sc.stage_n = bd + bi;
+  Stage *st = nullptr;
+  for (Stage &c : sc.stages) {
+    if (c.n < bd + bi) continue;
+    e = hipEventQuery(c.done);
+    if (e == hipErrorNotReady) continue;
+    if (e != hipSuccess) return hip_fail(e, "hipEventQuery");
+    st = &c;
+    break;
   }
-  std::memcpy(sc.stage, descs.data(), bd);
-  std::memcpy((char *)sc.stage + bd, items.data(), bi);
-  if ((e = hipMemcpyAsync(sc.descs.p, sc.stage, bd, hipMemcpyHostToDevice, s)) != hipSuccess ||
-      (e = hipMemcpyAsync(sc.items.p, (char *)sc.stage + bd, bi, hipMemcpyHostToDevice, s)) != hipSuccess)
+  if (!st) {
+    Stage c;
+    c.n = align_up(bd + bi);
+    if ((e = hipHostMalloc(&c.p, c.n, hipHostMallocDefault)) != hipSuccess)
+      return fail(AW_ENOMEM, "pinned staging: %s", hipGetErrorString(e));
+    if ((e = hipEventCreateWithFlags(&c.done, hipEventDisableTiming)) != hipSuccess) {
+      (void)hipHostFree(c.p);
+      return hip_fail(e, "hipEventCreate");
+    }
+    sc.stages.push_back(c);
+    st = &sc.stages.back();
+  }
+  std::memcpy(st->p, descs.data(), bd);
+  std::memcpy((char *)st->p + bd, items.data(), bi);
+  char *base = (char *)sc.area;
+  if ((e = hipMemcpyAsync(base + l.descs, st->p, bd, hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(base + l.items, (char *)st->p + bd, bi, hipMemcpyHostToDevice, s)) != hipSuccess)
     return hip_fail(e, "batch table upload");
-  if ((e = hipEventRecord(sc.stage_done, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  if ((e = hipEventRecord(st->done, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
   return AW_OK;
 }
 
@@ -498,81 +579,132 @@ aw_status apply_image(const aw_image_spec *sp, const aw_ensemble &e, int idx, Fw
   return AW_OK;
 }
 
-aw_status hist_scratch(DevScratch &sc, const HistPlan &p, int64_t n_items, bool want_vals, HistScratch &w) {
-  hipError_t e;
-  if ((e = grow(sc.block_counts, p.bytes_block_counts)) != hipSuccess ||
-      (e = grow(sc.block_dropped, p.bytes_block_dropped)) != hipSuccess ||
-      (e = grow(sc.tile_start, p.bytes_tile_start)) != hipSuccess ||
-      (e = grow(sc.sorted_local, sizeof(uint16_t) * (size_t)std::max<int64_t>(n_items, 1))) != hipSuccess ||
-      (want_vals && (e = grow(sc.sorted_val, sizeof(double) * (size_t)std::max<int64_t>(n_items, 1))) != hipSuccess))
-    return fail(AW_ENOMEM, "histogram scratch: %s", hipGetErrorString(e));
-  w.block_counts = (uint32_t *)sc.block_counts.p;
-  w.block_dropped = (uint32_t *)sc.block_dropped.p;
-  w.tile_start = (uint32_t *)sc.tile_start.p;
-  w.tile_total = w.tile_start + p.n_tiles + 1;
-  w.sorted_local = (uint16_t *)sc.sorted_local.p;
-  w.sorted_val = want_vals ? (double *)sc.sorted_val.p : nullptr;
+// One image call: validated descriptors, work items and scratch layout.
+// batched: one persistent launch over every ensemble, their histogram items
+// side by side in the area; otherwise the ensembles run one after the other,
+// each reusing the same part of the area (stream order keeps them apart).
+struct ImageCall {
+  std::vector<FwdDesc> descs;
+  std::vector<WorkItem> items;
+  std::vector<int64_t> off;  // first item of each ensemble in the bins array
+  Layout lay;
+  bool hist = false, vals = false, batched = false;
+  int form = 6;
+  bool tan = true;
+  int64_t n_tiles = 0;
+};
+
+aw_status prepare_image(const aw_ensemble *ens, int32_t n_ens, const aw_image_spec *spec, double *const *image,
+                        uint32_t *const *counts, uint8_t *const *cls, const Tuning &t, bool batched,
+                        ImageCall &c) {
+  c.descs.assign(n_ens, FwdDesc{});
+  c.off.assign(n_ens + 1, 0);
+  c.batched = batched && n_ens > 1;
+  c.hist = spec->kind != AW_IMG_IC_GRID;
+  c.vals = spec->kind == AW_IMG_HIST_P0;
+  c.form = ens[0].map_form;
+  c.tan = tangent_on(ens[0]);
+  int64_t n_max = 0;
+  for (int e = 0; e < n_ens; ++e) {
+    c.descs[e] = make_desc(ens[e], nullptr, t);
+    aw_status st = apply_image(spec, ens[e], e, c.descs[e], image[e], counts ? counts[e] : nullptr);
+    if (st != AW_OK) return st;
+    c.descs[e].cls = cls ? cls[e] : nullptr;
+    c.off[e + 1] = c.off[e] + (c.batched ? c.descs[e].N : 0);
+    n_max = std::max<int64_t>(n_max, c.descs[e].N);
+  }
+  if (c.hist) c.n_tiles = hist_plan(n_max, spec->W, spec->H).n_tiles;
+  if (c.batched) c.items = make_items(c.descs, t).items;
+  const int64_t n_all = c.batched ? c.off[n_ens] : n_max;
+  c.lay = layout_of(c.hist, c.vals, n_all, n_max, c.n_tiles, c.batched ? c.descs.size() : 0,
+                    c.batched ? c.items.size() : 0);
   return AW_OK;
 }
 
-// Propagate n ensembles with image epilogues and run the reductions.
-// bins/vals point into one scratch area, offset per ensemble.
+// Point the descriptors' histogram items into the area at `base`.
+void place_image(ImageCall &c, char *base) {
+  if (!c.hist) return;
+  for (size_t e = 0; e < c.descs.size(); ++e) {
+    c.descs[e].bins = (uint32_t *)(base + c.lay.bins) + c.off[e];
+    c.descs[e].vals = c.vals ? (double *)(base + c.lay.vals) + c.off[e] : nullptr;
+  }
+}
+
+// Histogram reduction of ensemble e's items into its image.
+hipError_t reduce_image(const ImageCall &c, char *base, int e, const aw_image_spec *spec, double *const *image,
+                        uint32_t *const *counts, hipStream_t s) {
+  const FwdDesc &d = c.descs[e];
+  const HistPlan p = hist_plan(d.N, spec->W, spec->H);
+  const HistScratch w = hist_scratch_at(base, c.lay, c.vals, p.n_tiles);
+  const int mode = c.vals ? 1 : 2;
+  const double norm = 1.0 / ((double)d.N * ((d.khi0 - d.klo0) / spec->W) * ((d.khi1 - d.klo1) / spec->H));
+  return launch_hist_reduce(d.N, d.bins, d.vals, p, w, mode, norm, counts ? counts[e] : nullptr, image[e], nullptr,
+                            s);
+}
+
+// Enqueue a prepared and placed image call.  A batched call needs its tables
+// at lay.descs / lay.items of the area already (or on their way, earlier on
+// the stream).  timed: record the propagation launches for aw_timing_read
+// (never inside a graph capture).
+aw_status enqueue_image(const ImageCall &c, char *base, const aw_image_spec *spec, double *const *image,
+                        uint32_t *const *counts, const Tuning &t, hipStream_t s, bool timed) {
+  hipError_t herr;
+  const int n_ens = (int)c.descs.size();
+  auto propagate = [&](const FwdDesc &d) -> aw_status {
+    if (timed) return launch_one(d, t, c.form, c.tan, s);
+    hipError_t e2 = launch_fwd(d, t, c.form, c.tan, s);
+    return e2 == hipSuccess ? AW_OK : hip_fail(e2, "propagation launch");
+  };
+  auto zero_counter = [&](const FwdDesc &d) -> aw_status {
+    if (d.epi != EPI_IC_GRID || !d.n_class) return AW_OK;
+    hipError_t e2 = launch_zero_u32(d.n_class, 1, s);
+    return e2 == hipSuccess ? AW_OK : hip_fail(e2, "zero counter");
+  };
+  aw_status st;
+  if (!c.batched) {
+    for (int e = 0; e < n_ens; ++e) {
+      if ((st = zero_counter(c.descs[e])) != AW_OK || (st = propagate(c.descs[e])) != AW_OK) return st;
+      if (c.hist && (herr = reduce_image(c, base, e, spec, image, counts, s)) != hipSuccess)
+        return hip_fail(herr, "histogram reduction");
+    }
+    return AW_OK;
+  }
+  for (int e = 0; e < n_ens; ++e)
+    if ((st = zero_counter(c.descs[e])) != AW_OK) return st;
+  if (!c.items.empty()) {
+    const FwdDesc *dd = (const FwdDesc *)(base + c.lay.descs);
+    const WorkItem *di = (const WorkItem *)(base + c.lay.items);
+    uint32_t *head = (uint32_t *)(base + c.lay.head);
+    if (timed) {
+      st = launch_batched_tables(dd, di, (int32_t)c.items.size(), head, t, c.form, c.tan, s);
+    } else {
+      const int nwg = std::max(1, std::min<int>(persistent_wgs(c.form, c.tan, t), (int)c.items.size()));
+      herr = launch_fwd_batched(dd, di, (int32_t)c.items.size(), head, t, c.form, c.tan, nwg, s);
+      st = herr == hipSuccess ? AW_OK : hip_fail(herr, "persistent launch");
+    }
+    if (st != AW_OK) return st;
+  }
+  if (c.hist)
+    for (int e = 0; e < n_ens; ++e)
+      if ((herr = reduce_image(c, base, e, spec, image, counts, s)) != hipSuccess)
+        return hip_fail(herr, "histogram reduction");
+  return AW_OK;
+}
+
+// Propagate n ensembles with image epilogues and run the reductions, in the
+// stream's library scratch.
 aw_status image_run(const aw_ensemble *ens, int32_t n_ens, const aw_image_spec *spec, double *const *image,
                     uint32_t *const *counts, uint8_t *const *cls, const Tuning &t, hipStream_t s) {
-  std::lock_guard<std::mutex> lk(g_mu);
-  DevScratch &sc = scratch();
-  std::vector<FwdDesc> descs(n_ens);
-  std::vector<int64_t> off(n_ens + 1, 0);
-  for (int e = 0; e < n_ens; ++e) {
-    descs[e] = make_desc(ens[e], nullptr, t);
-    off[e + 1] = off[e] + descs[e].N;
-  }
-  const bool hist = spec->kind != AW_IMG_IC_GRID;
-  hipError_t herr;
-  if (hist) {
-    if ((herr = grow(sc.bins, sizeof(uint32_t) * (size_t)off[n_ens])) != hipSuccess ||
-        (spec->kind == AW_IMG_HIST_P0 && (herr = grow(sc.vals, sizeof(double) * (size_t)off[n_ens])) != hipSuccess))
-      return fail(AW_ENOMEM, "image scratch: %s", hipGetErrorString(herr));
-  }
-  for (int e = 0; e < n_ens; ++e) {
-    aw_status st = apply_image(spec, ens[e], e, descs[e], image[e], counts ? counts[e] : nullptr);
-    if (st != AW_OK) return st;
-    descs[e].cls = cls ? cls[e] : nullptr;
-    if (hist) {
-      descs[e].bins = (uint32_t *)sc.bins.p + off[e];
-      descs[e].vals = spec->kind == AW_IMG_HIST_P0 ? (double *)sc.vals.p + off[e] : nullptr;
-    }
-    if (descs[e].epi == EPI_IC_GRID && descs[e].n_class) {
-      if ((herr = launch_zero_u32(descs[e].n_class, 1, s)) != hipSuccess) return hip_fail(herr, "zero counter");
-    }
-  }
-  const int form = ens[0].map_form;
-  const bool tan = tangent_on(ens[0]);
-  aw_status st;
-  if (n_ens == 1) {
-    st = launch_one(descs[0], t, form, tan, s);
-  } else {
-    BatchTables b = make_items(descs, t);
-    st = upload_tables(sc, descs, b.items, s);
-    if (st == AW_OK)
-      st = launch_batched_tables((const FwdDesc *)sc.descs.p, (const WorkItem *)sc.items.p, (int32_t)b.items.size(),
-                                 (uint32_t *)sc.head.p, t, form, tan, s);
-  }
+  ImageCall c;
+  aw_status st = prepare_image(ens, n_ens, spec, image, counts, cls, t, true, c);
   if (st != AW_OK) return st;
-  if (!hist) return AW_OK;
-  for (int e = 0; e < n_ens; ++e) {
-    const HistPlan p = hist_plan(descs[e].N, spec->W, spec->H);
-    HistScratch w;
-    st = hist_scratch(sc, p, descs[e].N, spec->kind == AW_IMG_HIST_P0, w);
-    if (st != AW_OK) return st;
-    const int mode = spec->kind == AW_IMG_HIST_P0 ? 1 : 2;
-    const double norm = 1.0 / ((double)descs[e].N * ((descs[e].khi0 - descs[e].klo0) / spec->W) *
-                               ((descs[e].khi1 - descs[e].klo1) / spec->H));
-    herr = launch_hist_reduce(descs[e].N, descs[e].bins, descs[e].vals, p, w, mode, norm,
-                              counts ? counts[e] : nullptr, image[e], nullptr, s);
-    if (herr != hipSuccess) return hip_fail(herr, "histogram reduction");
-  }
-  return AW_OK;
+  std::lock_guard<std::mutex> lk(g_mu);
+  StreamScratch &sc = stream_scratch(s);
+  if ((st = reserve_area(sc, c.lay.total)) != AW_OK) return st;
+  char *base = (char *)sc.area;
+  place_image(c, base);
+  if (c.batched && !c.items.empty() && (st = upload_tables(sc, c.lay, c.descs, c.items, s)) != AW_OK) return st;
+  return enqueue_image(c, base, spec, image, counts, t, s, true);
 }
 
 }  // namespace
@@ -588,20 +720,55 @@ const char *aw_version(void) { return "libaw 0.1 (gfx950, FP64)"; }
 
 aw_status aw_release(void) {
   std::lock_guard<std::mutex> lk(g_mu);
-  int dev = 0;
-  (void)hipGetDevice(&dev);
-  auto it = g_scratch.find(dev);
-  if (it == g_scratch.end()) return AW_OK;
+  const int dev = cur_device();
   (void)hipDeviceSynchronize();
-  DevScratch &sc = it->second;
-  Buf *bufs[] = {&sc.bins, &sc.vals, &sc.block_counts, &sc.block_dropped, &sc.tile_start,
-                 &sc.sorted_local, &sc.sorted_val, &sc.descs, &sc.items, &sc.head};
-  for (Buf *b : bufs)
-    if (b->p) (void)hipFree(b->p);
-  if (sc.stage) (void)hipHostFree(sc.stage);
-  if (sc.stage_done) (void)hipEventDestroy(sc.stage_done);
-  g_scratch.erase(it);
+  for (auto it = g_scratch.begin(); it != g_scratch.end();) {
+    if (it->first.first != dev) {
+      ++it;
+      continue;
+    }
+    StreamScratch &sc = it->second;
+    if (sc.area) (void)hipFree(sc.area);
+    for (Stage &st : sc.stages) {
+      (void)hipHostFree(st.p);
+      (void)hipEventDestroy(st.done);
+    }
+    it = g_scratch.erase(it);
+  }
+  auto r = g_retired.find(dev);
+  if (r != g_retired.end()) {
+    for (void *p : r->second.dev) (void)hipFree(p);
+    g_retired.erase(r);
+  }
   return AW_OK;
+}
+
+aw_status aw_image_workspace(const aw_ensemble *ens, int32_t n_ens, const aw_image_spec *spec, size_t *bytes) {
+  if (!bytes) return fail(AW_EINVAL, "null bytes");
+  aw_status st = validate_batch(ens, n_ens, nullptr);
+  if (st != AW_OK) return st;
+  if (!spec) {
+    if (n_ens == 1) {
+      *bytes = 0;
+      return AW_OK;
+    }
+    std::vector<FwdDesc> descs(n_ens);
+    for (int e = 0; e < n_ens; ++e) descs[e] = make_desc(ens[e], nullptr, Tuning{});
+    *bytes = layout_of(false, false, 0, 0, 0, descs.size(), make_items(descs, Tuning{}).items.size()).total;
+    return AW_OK;
+  }
+  std::vector<double> dummy(n_ens, 0.0);
+  std::vector<double *> img(n_ens);
+  for (int e = 0; e < n_ens; ++e) img[e] = &dummy[e];
+  ImageCall c;
+  if ((st = prepare_image(ens, n_ens, spec, img.data(), nullptr, nullptr, Tuning{}, true, c)) != AW_OK) return st;
+  *bytes = c.lay.total;
+  return AW_OK;
+}
+
+aw_status aw_reserve(size_t bytes, void *stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return reserve_area(stream_scratch((hipStream_t)stream), bytes);
 }
 
 int64_t aw_ensemble_size(const aw_ensemble *ens) {
@@ -637,13 +804,16 @@ aw_status aw_map_ensemble(const aw_ensemble *ens, int32_t n_ens, const double *c
   const int form = ens[0].map_form;
   const bool tan = tangent_on(ens[0]);
   if (n_ens == 1) return launch_one(descs[0], t, form, tan, s);
-  std::lock_guard<std::mutex> lk(g_mu);
-  DevScratch &sc = scratch();
   BatchTables b = make_items(descs, t);
   if (b.items.empty()) return AW_OK;
-  if ((st = upload_tables(sc, descs, b.items, s)) != AW_OK) return st;
-  return launch_batched_tables((const FwdDesc *)sc.descs.p, (const WorkItem *)sc.items.p, (int32_t)b.items.size(),
-                               (uint32_t *)sc.head.p, t, form, tan, s);
+  const Layout l = layout_of(false, false, 0, 0, 0, descs.size(), b.items.size());
+  std::lock_guard<std::mutex> lk(g_mu);
+  StreamScratch &sc = stream_scratch(s);
+  if ((st = reserve_area(sc, l.total)) != AW_OK) return st;
+  if ((st = upload_tables(sc, l, descs, b.items, s)) != AW_OK) return st;
+  char *base = (char *)sc.area;
+  return launch_batched_tables((const FwdDesc *)(base + l.descs), (const WorkItem *)(base + l.items),
+                               (int32_t)b.items.size(), (uint32_t *)(base + l.head), t, form, tan, s);
 }
 
 aw_status aw_map_ensemble_steps(const aw_ensemble *ens, const double *ic_dev, double *carry_dev, int64_t k_begin,
@@ -704,16 +874,16 @@ aw_status aw_window_density(const aw_ensemble *ens, const double *ic_dev, double
   d.window_v = 1;
   d.wdt = (double)window_steps * ens->h;
   d.carry = carry_dev;
-  std::lock_guard<std::mutex> lk(g_mu);
-  DevScratch &sc = scratch();
-  hipError_t e;
-  if ((e = grow(sc.bins, sizeof(uint32_t) * (size_t)std::max<int64_t>(d.N, 1))) != hipSuccess)
-    return fail(AW_ENOMEM, "window scratch: %s", hipGetErrorString(e));
-  const HistPlan p = hist_plan(d.N, spec->W, spec->H);
-  HistScratch w;
-  if ((st = hist_scratch(sc, p, d.N, false, w)) != AW_OK) return st;
-  d.bins = (uint32_t *)sc.bins.p;
   hipStream_t s = (hipStream_t)stream;
+  const HistPlan p = hist_plan(d.N, spec->W, spec->H);
+  const Layout l = layout_of(true, false, d.N, d.N, p.n_tiles, 0, 0);
+  std::lock_guard<std::mutex> lk(g_mu);
+  StreamScratch &sc = stream_scratch(s);
+  if ((st = reserve_area(sc, l.total)) != AW_OK) return st;
+  char *base = (char *)sc.area;
+  const HistScratch w = hist_scratch_at(base, l, false, p.n_tiles);
+  d.bins = (uint32_t *)(base + l.bins);
+  hipError_t e;
   for (int64_t k = 0; k < n_windows; ++k) {
     d.k_begin = k_begin + k * window_steps;
     d.k_end = d.k_begin + window_steps;
@@ -736,22 +906,22 @@ aw_status aw_histogram2d(int64_t N, const double *a_dev, const double *b_dev, co
   if (!counts_dev) return fail(AW_EINVAL, "null counts");
   const HistPlan p = hist_plan(N, W, H);
   if (p.n_tiles > MAX_TILES) return fail(AW_EINVAL, "image too large: %d tiles (max %d)", p.n_tiles, MAX_TILES);
-  std::lock_guard<std::mutex> lk(g_mu);
-  DevScratch &sc = scratch();
-  hipError_t e;
-  if ((e = grow(sc.bins, sizeof(uint32_t) * (size_t)std::max<int64_t>(N, 1))) != hipSuccess ||
-      (v_dev && (e = grow(sc.vals, sizeof(double) * (size_t)std::max<int64_t>(N, 1))) != hipSuccess))
-    return fail(AW_ENOMEM, "histogram scratch: %s", hipGetErrorString(e));
-  HistScratch w;
-  aw_status st = hist_scratch(sc, p, N, v_dev != nullptr, w);
-  if (st != AW_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  double *vals = v_dev ? (double *)sc.vals.p : nullptr;
-  if ((e = launch_hist_bins(N, a_dev, b_dev, v_dev, lo0, hi0, lo1, hi1, W, H, closed_upper, (uint32_t *)sc.bins.p,
-                            vals, s)) != hipSuccess)
+  const bool with_v = v_dev != nullptr;
+  const Layout l = layout_of(true, with_v, N, N, p.n_tiles, 0, 0);
+  std::lock_guard<std::mutex> lk(g_mu);
+  StreamScratch &sc = stream_scratch(s);
+  aw_status st = reserve_area(sc, l.total);
+  if (st != AW_OK) return st;
+  char *base = (char *)sc.area;
+  const HistScratch w = hist_scratch_at(base, l, with_v, p.n_tiles);
+  uint32_t *bins = (uint32_t *)(base + l.bins);
+  double *vals = with_v ? (double *)(base + l.vals) : nullptr;
+  hipError_t e;
+  if ((e = launch_hist_bins(N, a_dev, b_dev, v_dev, lo0, hi0, lo1, hi1, W, H, closed_upper, bins, vals, s)) !=
+      hipSuccess)
     return hip_fail(e, "histogram bins");
-  if ((e = launch_hist_reduce(N, (uint32_t *)sc.bins.p, vals, p, w, 0, 1.0, counts_dev, sums_dev, dropped_dev,
-                              s)) != hipSuccess)
+  if ((e = launch_hist_reduce(N, bins, vals, p, w, 0, 1.0, counts_dev, sums_dev, dropped_dev, s)) != hipSuccess)
     return hip_fail(e, "histogram reduction");
   return AW_OK;
 }
@@ -959,52 +1129,44 @@ aw_status aw_graph_create(const aw_ensemble *ens, int32_t n_ens, const aw_image_
   aw_status st = validate_batch(ens, n_ens, nullptr);
   if (st != AW_OK) return st;
   if (!spec || !image_dev) return fail(AW_EINVAL, "null image spec or array");
-  if (spec->kind != AW_IMG_IC_GRID) return fail(AW_EUNSUPPORTED, "graphs are built for IC_GRID images");
   for (int e = 0; e < n_ens; ++e)
     if (ens[e].ic_kind == AW_IC_EXPLICIT) return fail(AW_EINVAL, "graph ensembles generate their initial conditions");
   Tuning t;
   if ((st = check_tuning(tuning, t)) != AW_OK) return st;
-  std::vector<FwdDesc> descs(n_ens);
-  for (int e = 0; e < n_ens; ++e) {
-    descs[e] = make_desc(ens[e], nullptr, t);
-    if ((st = apply_image(spec, ens[e], e, descs[e], image_dev[e], counts_dev ? counts_dev[e] : nullptr)) != AW_OK)
-      return st;
-    descs[e].cls = cls_dev ? cls_dev[e] : nullptr;
-  }
-  BatchTables b = make_items(descs, t);
+  ImageCall c;
+  if ((st = prepare_image(ens, n_ens, spec, image_dev, counts_dev, cls_dev, t, true, c)) != AW_OK) return st;
   aw_graph *g = new aw_graph();
   auto cleanup = [&](aw_status s2) {
     aw_graph_destroy(g);
     return s2;
   };
-  void *dd = nullptr, *di = nullptr, *dh = nullptr;
+  // The graph owns its scratch area (histogram items and sort buffers, batch tables).
+  void *area = nullptr;
   hipError_t e;
-  if ((e = hipMalloc(&dd, std::max<size_t>(1, descs.size() * sizeof(FwdDesc)))) != hipSuccess)
-    return cleanup(fail(AW_ENOMEM, "graph tables: %s", hipGetErrorString(e)));
-  g->dev_allocs.push_back(dd);
-  if ((e = hipMalloc(&di, std::max<size_t>(1, b.items.size() * sizeof(WorkItem)))) != hipSuccess)
-    return cleanup(fail(AW_ENOMEM, "graph tables: %s", hipGetErrorString(e)));
-  g->dev_allocs.push_back(di);
-  if ((e = hipMalloc(&dh, 256)) != hipSuccess) return cleanup(fail(AW_ENOMEM, "graph tables: %s", hipGetErrorString(e)));
-  g->dev_allocs.push_back(dh);
-  if ((e = hipMemcpy(dd, descs.data(), descs.size() * sizeof(FwdDesc), hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(di, b.items.data(), b.items.size() * sizeof(WorkItem), hipMemcpyHostToDevice)) != hipSuccess)
-    return cleanup(hip_fail(e, "graph table upload"));
+  if ((e = hipMalloc(&area, c.lay.total)) != hipSuccess)
+    return cleanup(fail(AW_ENOMEM, "graph scratch of %zu bytes: %s", c.lay.total, hipGetErrorString(e)));
+  g->dev_allocs.push_back(area);
+  char *base = (char *)area;
+  place_image(c, base);
+  if (c.batched && !c.items.empty()) {
+    if ((e = hipMemcpy(base + c.lay.descs, c.descs.data(), c.descs.size() * sizeof(FwdDesc),
+                       hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(base + c.lay.items, c.items.data(), c.items.size() * sizeof(WorkItem),
+                       hipMemcpyHostToDevice)) != hipSuccess)
+      return cleanup(hip_fail(e, "graph table upload"));
+  }
   hipStream_t cs;
   if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) return cleanup(hip_fail(e, "stream"));
-  const int form = ens[0].map_form;
-  const bool tan = tangent_on(ens[0]);
-  const int nwg = std::max(1, std::min<int>(persistent_wgs(form, tan, t), (int)b.items.size()));
-  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-  if (e == hipSuccess) {
-    for (int k = 0; k < n_ens; ++k)
-      if (descs[k].n_class) (void)launch_zero_u32(descs[k].n_class, 1, cs);
-    if (!b.items.empty())
-      (void)launch_fwd_batched((const FwdDesc *)dd, (const WorkItem *)di, (int32_t)b.items.size(), (uint32_t *)dh, t,
-                               form, tan, nwg, cs);
-    e = hipStreamEndCapture(cs, &g->graph);
+  if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return cleanup(hip_fail(e, "graph capture"));
   }
+  // Every launch status is checked; on a failure the capture is still ended
+  // (and its partial graph destroyed) before the error is returned.
+  st = enqueue_image(c, base, spec, image_dev, counts_dev, t, cs, false);
+  e = hipStreamEndCapture(cs, &g->graph);
   (void)hipStreamDestroy(cs);
+  if (st != AW_OK) return cleanup(st);
   if (e != hipSuccess) return cleanup(hip_fail(e, "graph capture"));
   if ((e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0)) != hipSuccess)
     return cleanup(hip_fail(e, "graph instantiate"));

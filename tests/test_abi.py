@@ -275,3 +275,33 @@ def test_bench_refuses_more_than_one_gpu():
     assert res.returncode != 0
     assert "one GPU" in res.stderr
     assert res.stdout == ""
+
+
+def test_image_workspace_query():
+    """The library scratch of one image call, from the host alone: none for a
+    single IC-grid ensemble or a single unbatched propagation; per-orbit
+    histogram items plus sort buffers, growing with the ensemble; batch tables
+    for several ensembles; invalid descriptors refused like the call itself."""
+    from paper_1107_4107_amd import ImageSpec
+    lib = _abi.load()
+    nb = ctypes.c_size_t()
+
+    def ws(ens, spec):
+        arr = (_abi.AwEnsemble * len(ens))(*ens)
+        st = lib.aw_image_workspace(arr, len(ens), ctypes.byref(spec.to_c()) if spec else None, ctypes.byref(nb))
+        return st, nb.value
+
+    assert ws([_ens()], ImageSpec(kind="ic_grid", W=8, H=8)) == (0, 0)
+    assert ws([_ens()], None) == (0, 0)
+    p0 = ImageSpec(kind="hist_p0", field=6, W=64, H=64)
+    st, small = ws([_ens(ic_kind="box", n_orbits=1000)], p0)
+    assert st == 0 and small >= 1000 * (4 + 8 + 2 + 8)
+    st, big = ws([_ens(ic_kind="box", n_orbits=100_000)], p0)
+    assert st == 0 and big >= 100_000 * (4 + 8 + 2 + 8) and big > small
+    st, vdir = ws([_ens(ic_kind="box", n_orbits=100_000)], ImageSpec(kind="hist_vdir", W=64, H=64))
+    assert st == 0 and 100_000 * (4 + 2) <= vdir < big          # no values to carry
+    st, two = ws([_ens(), _ens(nx=16, ny=16)], None)
+    assert st == 0 and two > 0                                  # descriptors and work items
+    assert ws([_ens(M=4)], p0)[0] == _abi.AW_EUNSUPPORTED
+    assert ws([_ens(ic_kind="box", n_orbits=10)], ImageSpec(kind="hist_p0", W=0, H=8))[0] == _abi.AW_EINVAL
+    assert lib.aw_image_workspace(None, 1, None, ctypes.byref(nb)) == _abi.AW_EINVAL

@@ -183,6 +183,11 @@ def test_integrable_limit(orc, form):
     np.testing.assert_allclose(st[0:3], ic[0:3] + th * ic[3:6], rtol=1e-12, atol=1e-12)
     L = 0.5 * np.log(np.sum((w0[0:3] + th * w0[3:6]) ** 2, axis=0) + np.sum(w0[3:6] ** 2, axis=0))
     np.testing.assert_allclose(out[0], L, rtol=1e-11)
+    # lambda = L / (T h) (the finite-time Lyapunov exponent) and
+    # chi = L / ln(1 + T h): the shear alone gives chi <= 1 + ln 2 / (2 ln(1 + T h)).
+    np.testing.assert_allclose(out[1], L / th, rtol=1e-11)
+    np.testing.assert_allclose(out[2], L / np.log1p(th), rtol=1e-11)
+    assert np.all(out[2] <= 1.0 + 0.5 * np.log(2.0) / np.log1p(th))
     np.testing.assert_allclose(out[3:6], ic[3:6], rtol=1e-12, atol=1e-13)
     assert np.all(out[6] == 0) and np.all(out[7] == 0) and np.all(out[8] == 0)
 
@@ -275,6 +280,73 @@ def test_invariant_plane_is_two_chirikov_maps(orc):
     # The 6th-order map keeps the plane invariant too (exact zeros).
     s6 = orc.map_state("s6", 0.01, H_PAPER, 500, np.array([0.0, 0.0, 0.0, 2.0, 1.0, 0.0]))
     assert s6[2] == 0.0 and s6[5] == 0.0
+
+
+def _chirikov_observables(s0, w0, eps, h, T):
+    """Per-orbit rows (L, lambda, chi, V, dP2, J, dE) of the kick-then-drift
+    map on the invariant plane, accumulated from two textbook Chirikov maps
+    in u = x + y, v = x - y (I = 2 h p_u, K = 2 eps h^2) and the linear map of
+    the out-of-plane tangent.  On the plane eq. 2 is eps (cos u + cos v), so
+    H = p_u^2 + p_v^2 + eps (cos u + cos v) with p_u = (px + py)/2, and
+    |P - P0|^2 = 2 (dp_u^2 + dp_v^2).  Off the plane, Hp_zz = -4 cos x cos y =
+    -2 (cos u + cos v) at z = 0, so the kick sends dp_z -> dp_z + 2 h eps
+    (cos u + cos v) dz; the drift dz -> dz + h dp_z."""
+    K = 2.0 * eps * h * h
+    u, v = s0[0] + s0[1], s0[0] - s0[1]
+    Iu, Iv = h * (s0[3] + s0[4]), h * (s0[3] - s0[4])
+    u0, v0, Iu0, Iv0 = u, v, Iu, Iv
+    # tangent: (du, dIu), (dv, dIv), (dz, dpz)
+    du, dv = w0[0] + w0[1], w0[0] - w0[1]
+    dIu, dIv = h * (w0[3] + w0[4]), h * (w0[3] - w0[4])
+    dz, dpz = w0[2], w0[5]
+    jsum = 0.0
+    for _ in range(T):
+        cs = np.cos(u) + np.cos(v)
+        dIu = dIu + K * np.cos(u) * du
+        dIv = dIv + K * np.cos(v) * dv
+        dpz = dpz + 2.0 * h * eps * cs * dz
+        Iu = Iu + K * np.sin(u)
+        Iv = Iv + K * np.sin(v)
+        u, v = u + Iu, v + Iv
+        du, dv = du + dIu, dv + dIv
+        dz = dz + h * dpz
+        jsum += 2.0 * ((Iu - Iu0) ** 2 + (Iv - Iv0) ** 2) / (2.0 * h) ** 2
+    th = T * h
+    w2 = ((du + dv) / 2) ** 2 + ((du - dv) / 2) ** 2 + dz ** 2 + \
+         ((dIu + dIv) / (2 * h)) ** 2 + ((dIu - dIv) / (2 * h)) ** 2 + dpz ** 2
+    L = 0.5 * np.log(w2 / np.sum(np.asarray(w0) ** 2))
+    energy = lambda a, b, Ia, Ib: (Ia ** 2 + Ib ** 2) / (2 * h) ** 2 + eps * (np.cos(a) + np.cos(b))
+    return np.array([L, L / th, L / np.log1p(th),
+                     ((u + v) - (u0 + v0)) / 2 / th, ((u - v) - (u0 - v0)) / 2 / th, 0.0,
+                     2.0 * ((Iu - Iu0) ** 2 + (Iv - Iv0) ** 2) / (2.0 * h) ** 2, jsum / T,
+                     energy(u, v, Iu, Iv) - energy(u0, v0, Iu0, Iv0)])
+
+
+def test_accumulators_on_invariant_plane(orc):
+    """Every per-orbit row at eps != 0 against the two Chirikov maps of the
+    invariant plane: the step-averaged drift J = (1/T) sum_{k=1..T} |P_k - P_0|^2,
+    the final drift dP2, the mean velocity V, the energy change and the
+    tangent growth L (with lambda and chi) -- all from independently written
+    textbook maps, so that a slip in the oracle's accumulators (a shifted step
+    range, a missing factor, a wrong norm) shows at eps != 0, where J and dP2
+    are not zero.  Regular and chaotic starts (K = 0.5 over 30 steps, short enough
+    that rounding has not yet separated chaotic orbits), T = 30 to 200."""
+    rng = np.random.default_rng(12)
+    for eps, h, T in ((0.2, 0.3, 80), (1.0, 0.5, 30), (0.05, H_PAPER, 200)):
+        N = 8
+        ic = np.zeros((6, N))
+        ic[0:2] = rng.uniform(0, 2 * np.pi, (2, N))
+        ic[3:5] = rng.uniform(-2.0, 2.0, (2, N))
+        w0 = orc.w0(5, N)
+        out = orc.ensemble("stdmap", eps, h, T, ic, w0)
+        for n in range(N):
+            ref = _chirikov_observables(ic[:, n], w0[:, n], eps, h, T)
+            assert out[5, n] == 0.0
+            np.testing.assert_allclose(out[:, n], ref, rtol=1e-9, atol=1e-12 * max(1.0, abs(ref[0])),
+                                       err_msg=f"eps={eps} h={h} T={T} orbit {n}")
+            assert out[7, n] > 1e-6 and out[6, n] > 0.0
+        # summing over k = 0..T-1 instead would move J by dP2 / T, far beyond the tolerance
+        assert np.all(out[6] / T > 1e-6 * out[7])
 
 
 # ---------------------------------------------------------------- energy
