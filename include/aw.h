@@ -284,6 +284,32 @@ aw_status aw_histogram2d(int64_t N, const double *a_dev, const double *b_dev, co
                          int32_t closed_upper, uint32_t *counts_dev, double *sums_dev,
                          uint64_t *dropped_dev, void *stream);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the same
+ * histogram as aw_histogram2d (same arguments, results and errors), with its
+ * scratch in a fixed device array of AW_NOALLOC_SCRATCH_BYTES instead of the
+ * stream's library scratch.  It calls no hipMalloc, hipFree or allocating
+ * routine; the array is a file-scope device variable that every GPU the
+ * library runs on holds (its own copy) until the process ends.  The first
+ * call on a device looks up that device's address of the array (the HIP
+ * runtime may place the array in device memory then); later calls change
+ * nothing in the device's memory use.  Scratch a
+ * call needs, each part rounded up to 256 bytes: 4 N (bins) + 2 N (sorted
+ * local bins), with values (v_dev != NULL) + 8 N + 8 N, plus 4 T G + 4 G +
+ * 4 (2 T + 1) of tile tables, where T = ceil(W/32) ceil(H/32) and
+ * G = ceil(N/8192) (N = 0 counts as 1); about 2.9e6 items with values or
+ * 1.1e7 without.  A larger request returns AW_EWORKSPACE and enqueues nothing.
+ * Every call on a GPU shares that GPU's array, and the array keeps the last
+ * call's contents (each call writes every part it reads before reading it):
+ * calls on one stream are ordered and safe, but calls that overlap on one
+ * GPU -- on different streams, or from host threads that do not order their
+ * streams -- race on the array and give wrong results. */
+#define AW_NOALLOC_SCRATCH_BYTES (64u << 20)
+aw_status aw_histogram2d_noalloc(int64_t N, const double *a_dev, const double *b_dev, const double *v_dev,
+                                 double lo0, double hi0, double lo1, double hi1, int32_t W, int32_t H,
+                                 int32_t closed_upper, uint32_t *counts_dev, double *sums_dev,
+                                 uint64_t *dropped_dev, void *stream);
+
 /* Equal-area keys of the direction of V[3][N]: phi = atan2(Vy, Vx),
  * mu = Vz / |V|; NaN for a zero V. */
 aw_status aw_vdir_keys(int64_t N, const double *V_dev, double *phi_dev, double *mu_dev, void *stream);

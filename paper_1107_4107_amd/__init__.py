@@ -274,8 +274,10 @@ def window_density(ens: Ensemble, carry: torch.Tensor, k_begin: int, n_windows: 
 
 
 def histogram2d(a: torch.Tensor, b: torch.Tensor, v: Optional[torch.Tensor], lo, hi, W: int, H: int,
-                closed_upper: bool = False):
-    """Counts[H, W] (int32 holding uint32), sums[H, W] (or None) and the dropped count."""
+                closed_upper: bool = False, noalloc: bool = False):
+    """Counts[H, W] (int32 holding uint32), sums[H, W] (or None) and the dropped count.
+    noalloc=True calls aw_histogram2d_noalloc (scratch in the library's fixed
+    device array; the outputs are still allocated here)."""
     N = a.numel()
     _dev_f64(a, (N,), "a")
     _dev_f64(b, (N,), "b")
@@ -284,9 +286,9 @@ def histogram2d(a: torch.Tensor, b: torch.Tensor, v: Optional[torch.Tensor], lo,
     counts = torch.empty((H, W), dtype=torch.int32, device=a.device)
     sums = torch.empty((H, W), dtype=torch.float64, device=a.device) if v is not None else None
     dropped = torch.empty((1,), dtype=torch.int64, device=a.device)
-    _abi.check(_lib().aw_histogram2d(N, _p(a), _p(b), _p(v), float(lo[0]), float(hi[0]), float(lo[1]),
-                                     float(hi[1]), int(W), int(H), int(bool(closed_upper)), _p(counts),
-                                     _p(sums), _p(dropped), _stream()))
+    fn = _lib().aw_histogram2d_noalloc if noalloc else _lib().aw_histogram2d
+    _abi.check(fn(N, _p(a), _p(b), _p(v), float(lo[0]), float(hi[0]), float(lo[1]), float(hi[1]), int(W), int(H),
+                  int(bool(closed_upper)), _p(counts), _p(sums), _p(dropped), _stream()))
     return counts, sums, dropped
 
 

@@ -17,10 +17,11 @@ F_WINDOW = 2
 OUT_L, OUT_LAMBDA, OUT_CHI, OUT_VX, OUT_VY, OUT_VZ, OUT_DP2, OUT_J, OUT_DE, NOUT = range(10)
 NCARRY = 22
 IMG_IC_GRID, IMG_HIST_P0, IMG_HIST_VDIR = 0, 1, 2
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 EXPORTS = [
     "aw_last_error", "aw_version", "aw_release", "aw_ensemble_size", "aw_generate_ic",
-    "aw_map_ensemble", "aw_map_ensemble_steps", "aw_indicator_image", "aw_window_density", "aw_histogram2d",
+    "aw_map_ensemble", "aw_map_ensemble_steps", "aw_indicator_image", "aw_window_density", "aw_histogram2d", "aw_histogram2d_noalloc",
     "aw_vdir_keys", "aw_image_workspace", "aw_reserve", "aw_indicator_grad_workspace", "aw_indicator_grad", "aw_indicator_grad_reversible",
     "aw_ftle_grad_workspace", "aw_ftle_grad", "aw_ftle_grad_reversible",
     "aw_graph_create",
@@ -96,6 +97,8 @@ SIGNATURES = {
     "aw_indicator_image": (_i32, [_PE, _i32, _PS, _PP, _PP, _PP, _PT, _vp]),
     "aw_window_density": (_i32, [_PE, _vp, _vp, _i64, _i64, _i64, _PS, _vp, _PT, _vp]),
     "aw_histogram2d": (_i32, [_i64, _vp, _vp, _vp, _f64, _f64, _f64, _f64, _i32, _i32, _i32, _vp, _vp, _vp, _vp]),
+    "aw_histogram2d_noalloc": (_i32, [_i64, _vp, _vp, _vp, _f64, _f64, _f64, _f64, _i32, _i32, _i32, _vp, _vp, _vp,
+                                      _vp]),
     "aw_vdir_keys": (_i32, [_i64, _vp, _vp, _vp, _vp]),
     "aw_image_workspace": (_i32, [_PE, _i32, _PS, ctypes.POINTER(ctypes.c_size_t)]),
     "aw_reserve": (_i32, [ctypes.c_size_t, _vp]),

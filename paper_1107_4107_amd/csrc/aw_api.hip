@@ -709,6 +709,38 @@ aw_status image_run(const aw_ensemble *ens, int32_t n_ens, const aw_image_spec *
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Fixed scratch of aw_histogram2d_noalloc, for callers that cannot allocate.
+// Every GPU the library runs on holds its own copy until the process ends.
+// In host code `scratch` names a host-side stand-in, not device memory: the
+// device address of each GPU's copy is looked up once per device (with that
+// device current) and only that address is ever handed to kernels.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[AW_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_fixed_mu;
+char *g_fixed_ptr[MAX_DEVICES] = {};
+
+aw_status fixed_scratch(char **out) {
+  const int dev = cur_device();
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(AW_EUNSUPPORTED, "device %d: more than %d devices", dev, MAX_DEVICES);
+  std::lock_guard<std::mutex> lk(g_fixed_mu);
+  if (!g_fixed_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "device address of the fixed scratch");
+    if (!p) return fail(AW_EDEVICE, "device address of the fixed scratch is null");
+    g_fixed_ptr[dev] = (char *)p;
+  }
+  *out = g_fixed_ptr[dev];
+  return AW_OK;
+}
+
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -895,25 +927,27 @@ aw_status aw_window_density(const aw_ensemble *ens, const double *ic_dev, double
   return AW_OK;
 }
 
-aw_status aw_histogram2d(int64_t N, const double *a_dev, const double *b_dev, const double *v_dev, double lo0,
-                         double hi0, double lo1, double hi1, int32_t W, int32_t H, int32_t closed_upper,
-                         uint32_t *counts_dev, double *sums_dev, uint64_t *dropped_dev, void *stream) {
+// Validation and enqueue of one histogram over caller keys, with its scratch
+// in the area at `base` (`avail` bytes).  hist2d_layout gives the area the
+// call needs; hist2d_run enqueues nothing unless it fits.
+static aw_status hist2d_check(int64_t N, const double *a_dev, const double *b_dev, double lo0, double hi0, double lo1,
+                              double hi1, int32_t W, int32_t H, uint32_t *counts_dev, HistPlan &p) {
   if (N < 0 || N > (int64_t(1) << 31) - 1) return fail(AW_EINVAL, "N out of range");
   if (W < 1 || H < 1) return fail(AW_EINVAL, "W, H must be >= 1");
   if (!(lo0 < hi0) || !(lo1 < hi1) || !is_fin(hi0 - lo0) || !is_fin(hi1 - lo1))
     return fail(AW_EINVAL, "ranges must satisfy lo < hi");
   if (N > 0 && (!a_dev || !b_dev)) return fail(AW_EINVAL, "null key arrays");
   if (!counts_dev) return fail(AW_EINVAL, "null counts");
-  const HistPlan p = hist_plan(N, W, H);
+  p = hist_plan(N, W, H);
   if (p.n_tiles > MAX_TILES) return fail(AW_EINVAL, "image too large: %d tiles (max %d)", p.n_tiles, MAX_TILES);
-  hipStream_t s = (hipStream_t)stream;
+  return AW_OK;
+}
+
+static aw_status hist2d_run(char *base, const Layout &l, const HistPlan &p, int64_t N, const double *a_dev,
+                            const double *b_dev, const double *v_dev, double lo0, double hi0, double lo1, double hi1,
+                            int32_t W, int32_t H, int32_t closed_upper, uint32_t *counts_dev, double *sums_dev,
+                            uint64_t *dropped_dev, hipStream_t s) {
   const bool with_v = v_dev != nullptr;
-  const Layout l = layout_of(true, with_v, N, N, p.n_tiles, 0, 0);
-  std::lock_guard<std::mutex> lk(g_mu);
-  StreamScratch &sc = stream_scratch(s);
-  aw_status st = reserve_area(sc, l.total);
-  if (st != AW_OK) return st;
-  char *base = (char *)sc.area;
   const HistScratch w = hist_scratch_at(base, l, with_v, p.n_tiles);
   uint32_t *bins = (uint32_t *)(base + l.bins);
   double *vals = with_v ? (double *)(base + l.vals) : nullptr;
@@ -924,6 +958,39 @@ aw_status aw_histogram2d(int64_t N, const double *a_dev, const double *b_dev, co
   if ((e = launch_hist_reduce(N, bins, vals, p, w, 0, 1.0, counts_dev, sums_dev, dropped_dev, s)) != hipSuccess)
     return hip_fail(e, "histogram reduction");
   return AW_OK;
+}
+
+aw_status aw_histogram2d(int64_t N, const double *a_dev, const double *b_dev, const double *v_dev, double lo0,
+                         double hi0, double lo1, double hi1, int32_t W, int32_t H, int32_t closed_upper,
+                         uint32_t *counts_dev, double *sums_dev, uint64_t *dropped_dev, void *stream) {
+  HistPlan p;
+  aw_status st = hist2d_check(N, a_dev, b_dev, lo0, hi0, lo1, hi1, W, H, counts_dev, p);
+  if (st != AW_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const Layout l = layout_of(true, v_dev != nullptr, N, N, p.n_tiles, 0, 0);
+  std::lock_guard<std::mutex> lk(g_mu);
+  StreamScratch &sc = stream_scratch(s);
+  if ((st = reserve_area(sc, l.total)) != AW_OK) return st;
+  return hist2d_run((char *)sc.area, l, p, N, a_dev, b_dev, v_dev, lo0, hi0, lo1, hi1, W, H, closed_upper,
+                    counts_dev, sums_dev, dropped_dev, s);
+}
+
+aw_status aw_histogram2d_noalloc(int64_t N, const double *a_dev, const double *b_dev, const double *v_dev,
+                                 double lo0, double hi0, double lo1, double hi1, int32_t W, int32_t H,
+                                 int32_t closed_upper, uint32_t *counts_dev, double *sums_dev, uint64_t *dropped_dev,
+                                 void *stream) {
+  HistPlan p;
+  aw_status st = hist2d_check(N, a_dev, b_dev, lo0, hi0, lo1, hi1, W, H, counts_dev, p);
+  if (st != AW_OK) return st;
+  const Layout l = layout_of(true, v_dev != nullptr, N, N, p.n_tiles, 0, 0);
+  if (l.total > (size_t)AW_NOALLOC_SCRATCH_BYTES)
+    return fail(AW_EWORKSPACE, "aw_histogram2d_noalloc: %lld items into %d x %d bins need %zu bytes of scratch, "
+                               "more than its fixed %zu", (long long)N, W, H, l.total,
+                (size_t)AW_NOALLOC_SCRATCH_BYTES);
+  char *area = nullptr;
+  if ((st = fixed_scratch(&area)) != AW_OK) return st;
+  return hist2d_run(area, l, p, N, a_dev, b_dev, v_dev, lo0, hi0, lo1, hi1, W, H, closed_upper, counts_dev, sums_dev,
+                    dropped_dev, (hipStream_t)stream);
 }
 
 aw_status aw_vdir_keys(int64_t N, const double *V_dev, double *phi_dev, double *mu_dev, void *stream) {
