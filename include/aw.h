@@ -322,13 +322,18 @@ aw_status aw_vdir_keys(int64_t N, const double *V_dev, double *phi_dev, double *
  *   grad_J_dev [N]: upstream dL/dJ_n (NULL = all ones)
  *   J_out_dev [N] or NULL; grad_ic_dev [6][N]: dL/d(initial x..pz);
  *   grad_eps_dev [N]: per-orbit dL/deps contributions (sum them for the scalar).
+ * The recompute keeps the state at the end of every 4th step (global count)
+ * and of the segment's last step; the sweep rebuilds the steps in between by
+ * inverting their stages from the next kept state.
  * Requires a caller workspace of aw_indicator_grad_workspace() bytes: the
- * n_seg = ceil(T / ckpt_every) checkpoints, the final state and the step
- * states of one segment, 6 doubles per orbit each.  With ckpt_every >= T
- * (one segment) the forward pass stores every step state itself and the
- * backward pass sweeps them without a recompute: T*N*48 bytes of workspace,
- * for a sweep about a quarter faster.  The result is bitwise the same for
- * every ckpt_every. */
+ * n_seg = ceil(T / ckpt_every) checkpoints, the final state and the kept step
+ * states of one segment (at most floor((ck + 2)/4) + 1 with ck =
+ * min(ckpt_every, T)), 6 doubles per orbit each.  With ckpt_every >= T (one
+ * segment) the forward pass keeps the step states itself and the backward
+ * pass sweeps them without a recompute: about T*N*12 bytes of workspace.
+ * The result is bitwise the same for every ckpt_every that is a multiple of 4
+ * and for ckpt_every >= T (the same states are kept); other intervals keep
+ * more states and agree to rounding. */
 aw_status aw_indicator_grad_workspace(const aw_ensemble *ens, int64_t ckpt_every, size_t *bytes);
 aw_status aw_indicator_grad(const aw_ensemble *ens, const double *ic_dev, const double *grad_J_dev,
                             int64_t ckpt_every, double *J_out_dev, double *grad_ic_dev,
@@ -343,8 +348,10 @@ aw_status aw_indicator_grad(const aw_ensemble *ens, const double *ic_dev, const 
  * invertible stages; the reconstructed states carry the rounding of the
  * inversion, which restarts from an exact state at every checkpoint.  The
  * result agrees with aw_indicator_grad to rounding, not bitwise.  Same
- * arguments and workspace query; only the checkpoints and the final state
- * are used. */
+ * arguments; the workspace holds only the checkpoints and the final state:
+ * aw_indicator_grad_reversible_workspace() bytes (aw_indicator_grad_workspace()
+ * bytes are enough too). */
+aw_status aw_indicator_grad_reversible_workspace(const aw_ensemble *ens, int64_t ckpt_every, size_t *bytes);
 aw_status aw_indicator_grad_reversible(const aw_ensemble *ens, const double *ic_dev, const double *grad_J_dev,
                                        int64_t ckpt_every, double *J_out_dev, double *grad_ic_dev,
                                        double *grad_eps_dev, void *workspace_dev, size_t ws_bytes,
@@ -366,12 +373,15 @@ aw_status aw_indicator_grad_reversible(const aw_ensemble *ens, const double *ic_
  *   grad_eps_dev [N]: per-orbit dF/deps contributions (sum for the scalar).
  * lambda = L/(T h) and chi = L/ln(1 + T h) scale the same gradients.  On
  * chaotic orbits the derivative grows like exp(lambda T h) and is only
- * meaningful where the trajectory is. Requires a caller workspace of
- * aw_ftle_grad_workspace() bytes: 12 doubles per orbit per checkpoint, for
- * the final state and per step of a segment, then one 16-bit rescale exponent
- * per orbit per 8 steps.  As for aw_indicator_grad, ckpt_every >= T stores
- * every step in the forward pass and skips the recompute (T*N*96 bytes), with
- * a bitwise-identical result. */
+ * meaningful where the trajectory is.  As for aw_indicator_grad, the
+ * recompute keeps (state, tangent) at the end of every 4th step and of the
+ * segment's last step, and the sweep inverts the steps in between.
+ * Requires a caller workspace of aw_ftle_grad_workspace() bytes: 12 doubles
+ * per orbit per checkpoint, for the final state and per kept step of a
+ * segment, then one 16-bit rescale exponent per orbit per 8 steps.  As for
+ * aw_indicator_grad, ckpt_every >= T keeps the step states in the forward pass
+ * and skips the recompute (about T*N*24 bytes); the result is bitwise the same
+ * for ckpt_every a multiple of 4 and for ckpt_every >= T. */
 aw_status aw_ftle_grad_workspace(const aw_ensemble *ens, int64_t ckpt_every, size_t *bytes);
 aw_status aw_ftle_grad(const aw_ensemble *ens, const double *ic_dev, const double *w0_dev,
                        const double *grad_L_dev, int64_t ckpt_every, double *L_out_dev,
@@ -385,7 +395,10 @@ aw_status aw_ftle_grad(const aw_ensemble *ens, const double *ic_dev, const doubl
  * result agrees with aw_ftle_grad to rounding, not bitwise: the reconstructed
  * states carry the inversion's rounding, and on chaotic orbits the tangent's
  * reconstruction error grows like exp(2 lambda h ckpt_every) within a
- * segment.  Same arguments and workspace query. */
+ * segment.  Same arguments; the workspace holds the checkpoints, the final
+ * state and the rescale exponents: aw_ftle_grad_reversible_workspace() bytes
+ * (aw_ftle_grad_workspace() bytes are enough too). */
+aw_status aw_ftle_grad_reversible_workspace(const aw_ensemble *ens, int64_t ckpt_every, size_t *bytes);
 aw_status aw_ftle_grad_reversible(const aw_ensemble *ens, const double *ic_dev, const double *w0_dev,
                                   const double *grad_L_dev, int64_t ckpt_every, double *L_out_dev,
                                   double *grad_ic_dev, double *grad_eps_dev, void *workspace_dev, size_t ws_bytes,

@@ -327,9 +327,10 @@ def generate_ic(ens: Ensemble, ic_in: Optional[torch.Tensor] = None):
     return ic, w0
 
 
-def grad_workspace_bytes(ens: Ensemble, ckpt_every: int) -> int:
+def grad_workspace_bytes(ens: Ensemble, ckpt_every: int, reversible: bool = False) -> int:
     nb = ctypes.c_size_t()
-    _abi.check(_lib().aw_indicator_grad_workspace(ctypes.byref(ens.to_c()), int(ckpt_every), ctypes.byref(nb)))
+    fn = _lib().aw_indicator_grad_reversible_workspace if reversible else _lib().aw_indicator_grad_workspace
+    _abi.check(fn(ctypes.byref(ens.to_c()), int(ckpt_every), ctypes.byref(nb)))
     return int(nb.value)
 
 
@@ -345,7 +346,7 @@ def indicator_grad(ens: Ensemble, ic: torch.Tensor, grad_J: Optional[torch.Tenso
     _dev_f64(ic, (6, N), "ic")
     if grad_J is not None:
         _dev_f64(grad_J, (N,), "grad_J")
-    nb = grad_workspace_bytes(ens, ckpt_every)
+    nb = grad_workspace_bytes(ens, ckpt_every, reversible)
     if workspace is None or workspace.numel() * workspace.element_size() < nb:
         workspace = torch.empty((max(nb, 8),), dtype=torch.uint8, device=ic.device)
     J = torch.empty((N,), dtype=torch.float64, device=ic.device)
@@ -389,9 +390,10 @@ class IndicatorJ(torch.autograd.Function):
         return gic.t().contiguous(), g_eps, None, None, None, None, None
 
 
-def ftle_grad_workspace_bytes(ens: Ensemble, ckpt_every: int) -> int:
+def ftle_grad_workspace_bytes(ens: Ensemble, ckpt_every: int, reversible: bool = False) -> int:
     nb = ctypes.c_size_t()
-    _abi.check(_lib().aw_ftle_grad_workspace(ctypes.byref(ens.to_c()), int(ckpt_every), ctypes.byref(nb)))
+    fn = _lib().aw_ftle_grad_reversible_workspace if reversible else _lib().aw_ftle_grad_workspace
+    _abi.check(fn(ctypes.byref(ens.to_c()), int(ckpt_every), ctypes.byref(nb)))
     return int(nb.value)
 
 
@@ -411,7 +413,7 @@ def ftle_grad(ens: Ensemble, ic: torch.Tensor, w0: Optional[torch.Tensor] = None
     _dev_f64(w0, (6, N), "w0")
     if grad_L is not None:
         _dev_f64(grad_L, (N,), "grad_L")
-    nb = ftle_grad_workspace_bytes(ens, ckpt_every)
+    nb = ftle_grad_workspace_bytes(ens, ckpt_every, reversible)
     if workspace is None or workspace.numel() * workspace.element_size() < nb:
         workspace = torch.empty((max(nb, 8),), dtype=torch.uint8, device=ic.device)
     L = torch.empty((N,), dtype=torch.float64, device=ic.device)

@@ -23,6 +23,7 @@ EXPORTS = [
     "aw_last_error", "aw_version", "aw_release", "aw_ensemble_size", "aw_generate_ic",
     "aw_map_ensemble", "aw_map_ensemble_steps", "aw_indicator_image", "aw_window_density", "aw_histogram2d", "aw_histogram2d_noalloc",
     "aw_vdir_keys", "aw_image_workspace", "aw_reserve", "aw_indicator_grad_workspace", "aw_indicator_grad", "aw_indicator_grad_reversible",
+    "aw_indicator_grad_reversible_workspace", "aw_ftle_grad_reversible_workspace",
     "aw_ftle_grad_workspace", "aw_ftle_grad", "aw_ftle_grad_reversible",
     "aw_graph_create",
     "aw_graph_launch", "aw_graph_destroy", "aw_timing_enable", "aw_timing_read",
@@ -106,6 +107,8 @@ SIGNATURES = {
     "aw_indicator_grad": (_i32, [_PE, _vp, _vp, _i64, _vp, _vp, _vp, _vp, ctypes.c_size_t, _PT, _vp]),
     "aw_indicator_grad_reversible": (_i32, [_PE, _vp, _vp, _i64, _vp, _vp, _vp, _vp, ctypes.c_size_t, _PT, _vp]),
     "aw_ftle_grad_workspace": (_i32, [_PE, _i64, ctypes.POINTER(ctypes.c_size_t)]),
+    "aw_indicator_grad_reversible_workspace": (_i32, [_PE, _i64, ctypes.POINTER(ctypes.c_size_t)]),
+    "aw_ftle_grad_reversible_workspace": (_i32, [_PE, _i64, ctypes.POINTER(ctypes.c_size_t)]),
     "aw_ftle_grad": (_i32, [_PE, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, ctypes.c_size_t, _PT, _vp]),
     "aw_ftle_grad_reversible": (_i32, [_PE, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, ctypes.c_size_t, _PT, _vp]),
     "aw_graph_create": (_i32, [_PE, _i32, _PS, _PP, _PP, _PP, _PT, ctypes.POINTER(_vp)]),

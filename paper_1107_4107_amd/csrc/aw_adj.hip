@@ -5,11 +5,13 @@
 // Forward kernel: one lane per orbit runs the map (no tangent), accumulates J
 // and stores the state at the start of every segment of `ckpt` steps.
 // Backward kernel: one lane per orbit walks the segments from the last one;
-// for each it recomputes the segment from its checkpoint, storing the end
-// state of every step, then sweeps the steps backwards.  Inside a step the
-// stages are undone in reverse order by inverting them exactly in exact
-// arithmetic (drift: X -= t P; kick: P += t eps grad Hp(X)), starting from the
-// stored end state, while the adjoint is propagated:
+// for each it recomputes the segment from its checkpoint, keeping the end
+// state of every ADJ_SUB-th step (and of the segment's last step), then sweeps
+// the steps backwards.  The stages are undone in reverse order by inverting
+// them exactly in exact arithmetic (drift: X -= t P; kick: P += t eps grad
+// Hp(X)), starting from the kept state at the end of each group of ADJ_SUB
+// steps and carrying the rebuilt state through the group, while the adjoint
+// is propagated:
 //   drift  D(t):  Pbar += t Xbar
 //   kick   K(t):  Xbar -= t eps Hess(X) Pbar,  epsbar -= t grad Hp(X) . Pbar
 // and the source of J, (2 gJ / T)(P_k - P_0), enters Pbar at every step
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(512) void k_adj_fwd(AdjDesc d) {
     for (int64_t g = g0; g < g1; ++g) {
       adj_step_fwd<FORM>(o, d, s_tab);
       accum_j_rot(o);
-      if (d.fwd_steps) store6(d.steps + g * 6 * d.N, d.N, n, o);  // one segment: g0 = 0
+      if (d.fwd_steps && adj_kept(g, g1)) store6(d.steps + adj_slot(g, 0) * 6 * d.N, d.N, n, o);  // one segment
     }
   }
   store6(d.ckpts + d.n_seg * 6 * d.N, d.N, n, o);   // the final state
@@ -228,15 +230,16 @@ __global__ __launch_bounds__(512) void k_adj_bwd(AdjDesc d) {
   for (int64_t s = d.n_seg - 1; s >= 0; --s) {
     const int64_t g0 = s * d.ckpt;
     const int64_t g1 = g0 + d.ckpt < d.T ? g0 + d.ckpt : d.T;
-    if (!d.fwd_steps) {  // else the forward pass has stored the steps already
+    if (!d.fwd_steps) {  // else the forward pass has kept the step states already
       load6(d.ckpts + s * 6 * N, N, n, o);
       for (int64_t g = g0; g < g1; ++g) {
         adj_step_fwd<FORM>(o, d, s_tab);
-        store6(d.steps + (g - g0) * 6 * N, N, n, o);
+        if (adj_kept(g, g1)) store6(d.steps + adj_slot(g, g0) * 6 * N, N, n, o);
       }
     }
     for (int64_t g = g1 - 1; g >= g0; --g) {
-      load6(d.steps + (g - g0) * 6 * N, N, n, o);   // state after step g
+      // state after step g: kept, or rebuilt by the inverse of step g + 1
+      if (adj_kept(g, g1)) load6(d.steps + adj_slot(g, g0) * 6 * N, N, n, o);
       const double ex = o.px - p0x, ey = o.py - p0y, ez = o.pz - p0z;
       a.pxb = __builtin_fma(ch, ex, a.pxb);
       a.pyb = __builtin_fma(ch, ey, a.pyb);

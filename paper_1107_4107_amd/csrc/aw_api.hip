@@ -1010,21 +1010,36 @@ aw_status aw_indicator_grad_workspace(const aw_ensemble *ens, int64_t ckpt_every
   if (N < 0) return fail(AW_EINVAL, "bad ensemble size");
   const int64_t ck = std::min(ckpt_every, ens->n_steps);
   const int64_t n_seg = (ens->n_steps + ck - 1) / ck;
-  // n_seg checkpoints, the final state, and the step states of one segment
-  *bytes = sizeof(double) * 6 * (size_t)N * (size_t)(n_seg + 1 + ck);
+  // n_seg checkpoints, the final state, and the kept step states of one segment
+  *bytes = sizeof(double) * 6 * (size_t)N * (size_t)(n_seg + 1 + adj_slots_max(ck));
+  return AW_OK;
+}
+
+aw_status aw_indicator_grad_reversible_workspace(const aw_ensemble *ens, int64_t ckpt_every, size_t *bytes) {
+  size_t full = 0;
+  aw_status st = aw_indicator_grad_workspace(ens, ckpt_every, &full);
+  if (st != AW_OK) return st;
+  const int64_t N = ens_size(*ens);
+  const int64_t ck = std::min(ckpt_every, ens->n_steps);
+  const int64_t n_seg = (ens->n_steps + ck - 1) / ck;
+  // n_seg checkpoints and the final state
+  *bytes = sizeof(double) * 6 * (size_t)N * (size_t)(n_seg + 1);
   return AW_OK;
 }
 
 // Validation and descriptor of the adjoint of J (both sweeps).
 static aw_status adj_setup(const aw_ensemble *ens, const double *ic_dev, const double *grad_J_dev, int64_t ckpt_every,
                     double *J_out_dev, double *grad_ic_dev, double *grad_eps_dev, void *workspace_dev,
-                    size_t ws_bytes, const aw_tuning *tuning, const char *who, AdjDesc &d, Tuning &t) {
+                    size_t ws_bytes, const aw_tuning *tuning, const char *who, bool reversible, AdjDesc &d,
+                    Tuning &t) {
   aw_status st = check_ensemble(ens, ic_dev, 0);
   if (st != AW_OK) return st;
   if (ens->ic_kind != AW_IC_EXPLICIT) return fail(AW_EINVAL, "%s needs an EXPLICIT ensemble", who);
   if ((st = check_tuning(tuning, t)) != AW_OK) return st;
   size_t need = 0;
-  if ((st = aw_indicator_grad_workspace(ens, ckpt_every, &need)) != AW_OK) return st;
+  st = reversible ? aw_indicator_grad_reversible_workspace(ens, ckpt_every, &need)
+                  : aw_indicator_grad_workspace(ens, ckpt_every, &need);
+  if (st != AW_OK) return st;
   const int64_t N = ens_size(*ens);
   if (N > 0 && (!grad_ic_dev || !grad_eps_dev)) return fail(AW_EINVAL, "null gradient outputs");
   if (ws_bytes < need || (N > 0 && !workspace_dev))
@@ -1049,7 +1064,7 @@ static aw_status adj_setup(const aw_ensemble *ens, const double *ic_dev, const d
   d.gic = grad_ic_dev;
   d.geps = grad_eps_dev;
   d.ckpts = (double *)workspace_dev;
-  d.steps = d.ckpts + (size_t)(d.n_seg + 1) * 6 * (size_t)N;
+  d.steps = reversible ? nullptr : d.ckpts + (size_t)(d.n_seg + 1) * 6 * (size_t)N;
   return AW_OK;
 }
 
@@ -1059,7 +1074,7 @@ aw_status aw_indicator_grad(const aw_ensemble *ens, const double *ic_dev, const 
   AdjDesc d;
   Tuning t;
   aw_status st = adj_setup(ens, ic_dev, grad_J_dev, ckpt_every, J_out_dev, grad_ic_dev, grad_eps_dev, workspace_dev,
-                           ws_bytes, tuning, "aw_indicator_grad", d, t);
+                           ws_bytes, tuning, "aw_indicator_grad", false, d, t);
   if (st != AW_OK) return st;
   d.fwd_steps = d.n_seg == 1 ? 1 : 0;
   hipStream_t s = (hipStream_t)stream;
@@ -1077,7 +1092,7 @@ aw_status aw_indicator_grad_reversible(const aw_ensemble *ens, const double *ic_
   AdjDesc d;
   Tuning t;
   aw_status st = adj_setup(ens, ic_dev, grad_J_dev, ckpt_every, J_out_dev, grad_ic_dev, grad_eps_dev, workspace_dev,
-                           ws_bytes, tuning, "aw_indicator_grad_reversible", d, t);
+                           ws_bytes, tuning, "aw_indicator_grad_reversible", true, d, t);
   if (st != AW_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = launch_adj_forward(d, ens->map_form, t, s);
@@ -1096,9 +1111,23 @@ aw_status aw_ftle_grad_workspace(const aw_ensemble *ens, int64_t ckpt_every, siz
   if (N < 0) return fail(AW_EINVAL, "bad ensemble size");
   const int64_t ck = std::min(ckpt_every, ens->n_steps);
   const int64_t n_seg = (ens->n_steps + ck - 1) / ck;
-  // checkpoints, the final state and one segment's step states (12 doubles
-  // per orbit each), then one 16-bit rescale exponent per orbit per 8 steps
-  *bytes = sizeof(double) * 12 * (size_t)N * (size_t)(n_seg + 1 + ck) +
+  // checkpoints, the final state and one segment's kept step states (12
+  // doubles per orbit each), then one 16-bit rescale exponent per orbit per 8 steps
+  *bytes = sizeof(double) * 12 * (size_t)N * (size_t)(n_seg + 1 + adj_slots_max(ck)) +
+           sizeof(int16_t) * (size_t)N * (size_t)(ens->n_steps / 8);
+  return AW_OK;
+}
+
+aw_status aw_ftle_grad_reversible_workspace(const aw_ensemble *ens, int64_t ckpt_every, size_t *bytes) {
+  size_t full = 0;
+  aw_status st = aw_ftle_grad_workspace(ens, ckpt_every, &full);
+  if (st != AW_OK) return st;
+  const int64_t N = ens_size(*ens);
+  const int64_t ck = std::min(ckpt_every, ens->n_steps);
+  const int64_t n_seg = (ens->n_steps + ck - 1) / ck;
+  // checkpoints and the final state (12 doubles per orbit each), then the
+  // rescale exponents
+  *bytes = sizeof(double) * 12 * (size_t)N * (size_t)(n_seg + 1) +
            sizeof(int16_t) * (size_t)N * (size_t)(ens->n_steps / 8);
   return AW_OK;
 }
@@ -1107,13 +1136,15 @@ aw_status aw_ftle_grad_workspace(const aw_ensemble *ens, int64_t ckpt_every, siz
 static aw_status ftle_setup(const aw_ensemble *ens, const double *ic_dev, const double *w0_dev,
                             const double *grad_L_dev, int64_t ckpt_every, double *L_out_dev, double *grad_ic_dev,
                             double *grad_eps_dev, void *workspace_dev, size_t ws_bytes, const aw_tuning *tuning,
-                            const char *who, FtleDesc &d, Tuning &t) {
+                            const char *who, bool reversible, FtleDesc &d, Tuning &t) {
   aw_status st = check_ensemble(ens, ic_dev, 0);
   if (st != AW_OK) return st;
   if (ens->ic_kind != AW_IC_EXPLICIT) return fail(AW_EINVAL, "%s needs an EXPLICIT ensemble", who);
   if ((st = check_tuning(tuning, t)) != AW_OK) return st;
   size_t need = 0;
-  if ((st = aw_ftle_grad_workspace(ens, ckpt_every, &need)) != AW_OK) return st;
+  st = reversible ? aw_ftle_grad_reversible_workspace(ens, ckpt_every, &need)
+                  : aw_ftle_grad_workspace(ens, ckpt_every, &need);
+  if (st != AW_OK) return st;
   const int64_t N = ens_size(*ens);
   if (N > 0 && !w0_dev) return fail(AW_EINVAL, "null tangent start");
   if (N > 0 && (!grad_ic_dev || !grad_eps_dev)) return fail(AW_EINVAL, "null gradient outputs");
@@ -1140,8 +1171,13 @@ static aw_status ftle_setup(const aw_ensemble *ens, const double *ic_dev, const 
   d.gic = grad_ic_dev;
   d.geps = grad_eps_dev;
   d.ckpts = (double *)workspace_dev;
-  d.steps = d.ckpts + (size_t)(d.n_seg + 1) * 12 * (size_t)N;
-  d.exps = (int16_t *)(d.steps + (size_t)d.ckpt * 12 * (size_t)N);
+  if (reversible) {
+    d.steps = nullptr;
+    d.exps = (int16_t *)(d.ckpts + (size_t)(d.n_seg + 1) * 12 * (size_t)N);
+  } else {
+    d.steps = d.ckpts + (size_t)(d.n_seg + 1) * 12 * (size_t)N;
+    d.exps = (int16_t *)(d.steps + (size_t)adj_slots_max(d.ckpt) * 12 * (size_t)N);
+  }
   return AW_OK;
 }
 
@@ -1151,7 +1187,7 @@ aw_status aw_ftle_grad(const aw_ensemble *ens, const double *ic_dev, const doubl
   FtleDesc d;
   Tuning t;
   aw_status st = ftle_setup(ens, ic_dev, w0_dev, grad_L_dev, ckpt_every, L_out_dev, grad_ic_dev, grad_eps_dev,
-                            workspace_dev, ws_bytes, tuning, "aw_ftle_grad", d, t);
+                            workspace_dev, ws_bytes, tuning, "aw_ftle_grad", false, d, t);
   if (st != AW_OK) return st;
   d.fwd_steps = d.n_seg == 1 ? 1 : 0;
   hipStream_t s = (hipStream_t)stream;
@@ -1169,7 +1205,7 @@ aw_status aw_ftle_grad_reversible(const aw_ensemble *ens, const double *ic_dev, 
   FtleDesc d;
   Tuning t;
   aw_status st = ftle_setup(ens, ic_dev, w0_dev, grad_L_dev, ckpt_every, L_out_dev, grad_ic_dev, grad_eps_dev,
-                            workspace_dev, ws_bytes, tuning, "aw_ftle_grad_reversible", d, t);
+                            workspace_dev, ws_bytes, tuning, "aw_ftle_grad_reversible", true, d, t);
   if (st != AW_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = launch_ftle_forward(d, ens->map_form, t, s);

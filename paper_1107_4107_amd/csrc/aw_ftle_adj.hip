@@ -30,11 +30,12 @@
 // Forward kernel: one lane per orbit runs the map with its tangent, stores
 // (s, w) at the start of every segment of `ckpt` steps and writes L.
 // Backward kernel: one lane per orbit walks the segments from the last; for
-// each it recomputes the segment from its checkpoint, storing (s, w) at the
-// end of every step (before any rescale), then sweeps the steps backwards,
-// undoing each stage by its exact inverse (drift: X -= t P, dX -= t dP;
-// kick: P -= the kick's increment, dP -= M dX) while the adjoint above is
-// propagated.  Each lane only reads back what it wrote itself.
+// each it recomputes the segment from its checkpoint, keeping (s, w) at the
+// end of every ADJ_SUB-th step and of the segment's last step (before any
+// rescale), then sweeps the steps backwards, undoing each stage by its exact
+// inverse (drift: X -= t P, dX -= t dP; kick: P -= the kick's increment,
+// dP -= M dX) from the kept state at the end of each group of steps, while the
+// adjoint above is propagated.  Each lane only reads back what it wrote itself.
 //
 // Reversible sweep (k_ftle_bwd_rev): no recompute and no stored step states.
 // Each segment is swept back from the exact state at its end (the next
@@ -55,6 +56,7 @@ namespace {
 
 constexpr double LN2_D = 0.693147180559945309417232121458176568;
 constexpr int64_t RESCALE_MASK = 7;  // rescale after steps k with (k + 1) % 8 == 0
+static_assert(((RESCALE_MASK + 1) % ADJ_SUB) == 0, "every rescale step must be a kept step");
 
 template <int FORM>
 __device__ __forceinline__ void tan_step(Orbit &o, const AdjDesc &d, const double2 *__restrict__ tab) {
@@ -274,7 +276,7 @@ __global__ __launch_bounds__(512) void k_ftle_fwd(FtleDesc d) {
     const int64_t g1 = g0 + d.ckpt < d.T ? g0 + d.ckpt : d.T;
     for (int64_t g = g0; g < g1; ++g) {
       tan_step<FORM>(o, d, s_tab);
-      if (d.fwd_steps) store12(d.steps + g * 12 * N, N, n, o);  // one segment: g0 = 0
+      if (d.fwd_steps && adj_kept(g, g1)) store12(d.steps + adj_slot(g, 0) * 12 * N, N, n, o);  // one segment
       if (((g + 1) & RESCALE_MASK) == 0) {
         const int k0 = o.kexp;
         renorm_rot(o);
@@ -307,16 +309,18 @@ __global__ __launch_bounds__(512) void k_ftle_bwd(FtleDesc d) {
   for (int64_t s = d.n_seg - 1; s >= 0; --s) {
     const int64_t g0 = s * d.ckpt;
     const int64_t g1 = g0 + d.ckpt < d.T ? g0 + d.ckpt : d.T;
-    if (!d.fwd_steps) {  // else the forward pass has stored the steps already
+    if (!d.fwd_steps) {  // else the forward pass has kept the step states already
       load12(d.ckpts + s * 12 * N, N, n, o);
       for (int64_t g = g0; g < g1; ++g) {
         tan_step<FORM>(o, d, s_tab);
-        store12(d.steps + (g - g0) * 12 * N, N, n, o);
+        if (adj_kept(g, g1)) store12(d.steps + adj_slot(g, g0) * 12 * N, N, n, o);
         if (((g + 1) & RESCALE_MASK) == 0) renorm_rot(o);
       }
     }
     for (int64_t g = g1 - 1; g >= g0; --g) {
-      load12(d.steps + (g - g0) * 12 * N, N, n, o);   // end of step g, before any rescale
+      // end of step g, before any rescale: kept (every rescale step is kept,
+      // since ADJ_SUB divides 8), or rebuilt by the inverse of step g + 1
+      if (adj_kept(g, g1)) load12(d.steps + adj_slot(g, g0) * 12 * N, N, n, o);
       if (g == d.T - 1) {
         // dL/dw_T = w_T / |w_T|^2 (scaled by the upstream gradient).
         end_condition(o, a, gl);

@@ -110,6 +110,28 @@ struct WorkItem {
   int64_t first;
 };
 
+// The store sweeps of the adjoints keep the state at the end of every
+// ADJ_SUB-th step (global count: steps g with (g + 1) % ADJ_SUB == 0) and at
+// the end of every segment; the reverse sweep rebuilds the steps in between by
+// inverting their stages from the next kept state.  Slot of step g in the
+// buffer of a segment that starts at g0: (g >> ADJ_SUB_LOG2) - (g0 >> ADJ_SUB_LOG2).
+#ifndef AW_ADJ_SUB_LOG2
+#define AW_ADJ_SUB_LOG2 2
+#endif
+constexpr int ADJ_SUB_LOG2 = AW_ADJ_SUB_LOG2;
+constexpr int64_t ADJ_SUB = int64_t(1) << ADJ_SUB_LOG2;
+
+__host__ __device__ inline bool adj_kept(int64_t g, int64_t g1) {
+  return ((g + 1) & (ADJ_SUB - 1)) == 0 || g == g1 - 1;
+}
+
+__host__ __device__ inline int64_t adj_slot(int64_t g, int64_t g0) {
+  return (g >> ADJ_SUB_LOG2) - (g0 >> ADJ_SUB_LOG2);
+}
+
+// Slots a segment of ck steps needs at most, wherever it starts.
+__host__ __device__ inline int64_t adj_slots_max(int64_t ck) { return (ck + ADJ_SUB - 2) / ADJ_SUB + 1; }
+
 // Adjoint descriptor.
 struct AdjDesc {
   double drift[MAX_UNIQUE];
@@ -128,7 +150,7 @@ struct AdjDesc {
   double *gic;            // [6][N]
   double *geps;           // [N]
   double *ckpts;          // [n_seg + 1][6][N] (the last slot: the final state)
-  double *steps;          // [ckpt][6][N] (per-segment step states)
+  double *steps;          // [adj_slots_max(ckpt)][6][N] (kept step states of a segment)
   int32_t fwd_steps;      // 1: one segment, and the forward pass stores the step
                           // states itself, so that the store sweep skips its recompute
 };

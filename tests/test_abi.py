@@ -127,20 +127,45 @@ def test_grad_workspace_size():
     e = _ens(ic_kind="explicit", n_orbits=1000, n_steps=10_000)
     nb = ctypes.c_size_t()
     assert lib.aw_indicator_grad_workspace(ctypes.byref(e), 100, ctypes.byref(nb)) == 0
-    # 100 checkpoints + the final state + 100 step states, 6 doubles per orbit each.
-    assert nb.value == 8 * 6 * 1000 * (100 + 1 + 100)
+    # 100 checkpoints + the final state + the states kept in one segment (every
+    # 4th step and the last: 25 for segments that start on a multiple of 4,
+    # floor((100 + 2)/4) + 1 = 26 for any start), 6 doubles per orbit each.
+    assert nb.value == 8 * 6 * 1000 * (100 + 1 + 26)
     assert lib.aw_indicator_grad_workspace(ctypes.byref(e), 0, ctypes.byref(nb)) == _abi.AW_EINVAL
+    # one segment: ceil(T/4) kept states at most (+1 for a start off the multiples of 4)
+    assert lib.aw_indicator_grad_workspace(ctypes.byref(e), 10_000, ctypes.byref(nb)) == 0
+    assert nb.value == 8 * 6 * 1000 * (1 + 1 + 2501)
+    # the store-free sweep: checkpoints and the final state only
+    assert lib.aw_indicator_grad_reversible_workspace(ctypes.byref(e), 100, ctypes.byref(nb)) == 0
+    assert nb.value == 8 * 6 * 1000 * (100 + 1)
+    assert lib.aw_indicator_grad_reversible_workspace(ctypes.byref(e), 0, ctypes.byref(nb)) == _abi.AW_EINVAL
+
+
+def test_kept_step_slots_cover_every_segment():
+    """The slot of a kept step, (g >> 2) - (g0 >> 2), stays below the slot count
+    the workspace query reserves, floor((ck + 2)/4) + 1, for every segment
+    start and length, and distinct kept steps of a segment get distinct slots."""
+    for ck in range(1, 40):
+        bound = (ck + 2) // 4 + 1
+        for g0 in range(0, 64):
+            g1 = g0 + ck
+            kept = [g for g in range(g0, g1) if (g + 1) % 4 == 0 or g == g1 - 1]
+            slots = [(g >> 2) - (g0 >> 2) for g in kept]
+            assert len(set(slots)) == len(slots) and min(slots) >= 0 and max(slots) < bound, (ck, g0)
 
 
 def test_ftle_grad_workspace_and_validation():
     """Workspace of the FTLE gradient: 12 doubles (state and tangent) per orbit
-    per checkpoint and per step of a segment; bad calls are refused on the
-    host before any device work."""
+    per checkpoint and per kept step of a segment (none for the store-free
+    sweep), and the rescale exponents; bad calls are refused on the host
+    before any device work."""
     lib = _abi.load()
     e = _ens(ic_kind="explicit", n_orbits=1000, n_steps=10_000)
     nb = ctypes.c_size_t()
+    assert lib.aw_ftle_grad_reversible_workspace(ctypes.byref(e), 100, ctypes.byref(nb)) == 0
+    assert nb.value == 8 * 12 * 1000 * (100 + 1) + 2 * 1000 * (10_000 // 8)
     assert lib.aw_ftle_grad_workspace(ctypes.byref(e), 100, ctypes.byref(nb)) == 0
-    assert nb.value == 8 * 12 * 1000 * (100 + 1 + 100) + 2 * 1000 * (10_000 // 8)
+    assert nb.value == 8 * 12 * 1000 * (100 + 1 + 26) + 2 * 1000 * (10_000 // 8)
     assert lib.aw_ftle_grad_workspace(ctypes.byref(e), 0, ctypes.byref(nb)) == _abi.AW_EINVAL
     fake = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation first
     # not EXPLICIT
