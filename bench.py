@@ -125,12 +125,31 @@ def host_threads() -> int:
         return os.cpu_count() or 1
 
 
+_ORACLE_BUILD = None
+
+
+def oracle_native():
+    """The oracle built for this host (gcc -O3 -march=native, contraction off:
+    bitwise the results of the portable build), loaded for the timing."""
+    global _ORACLE_BUILD
+    import tempfile
+
+    import oracle
+    if _ORACLE_BUILD is None:
+        path = os.path.join(tempfile.mkdtemp(prefix="aw_oracle_"), "liboracle_native.so")
+        oracle.build(force=True, variant="native", out=path)
+        oracle.use_build(path)
+        _ORACLE_BUILD = "gcc " + " ".join(oracle.CFLAGS + oracle.VARIANT_FLAGS["native"])
+    return _ORACLE_BUILD
+
+
 def cpu_baseline(ens, target_s: float, threads: int):
     """The oracle as it stands on a bounded sample of the same workload: an
     evenly strided set of its orbits, each run for the full T steps."""
     import numpy as np
 
     import oracle
+    build = oracle_native()
     N = ens.size
 
     def sample(m):
@@ -157,7 +176,8 @@ def cpu_baseline(ens, target_s: float, threads: int):
     where = f"{ens.nx}x{ens.ny} slice" if ens.ic_kind == "grid2" else f"{N} orbits"
     return {"value": m * ens.n_steps / t, "unit": "map-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{m} orbits (evenly strided over the {where}) x {ens.n_steps} steps each, "
-                      f"{t:.1f} s on {threads} host threads", "host": host_info()}
+                      f"{t:.1f} s on {threads} host thread{'s' if threads > 1 else ''}", "host": host_info(),
+            "build": build}
 
 
 def roofline(aw, ens, kernel_ms, workload, steps_per_launch=None):
@@ -242,6 +262,31 @@ def run_slice(args, aw, wl, torch):
     rec["roofline"] = roofline(aw, ens, kern_ms / max(launches, 1), args.workload)
     rec["chaotic_fraction"] = n_chaotic / N
     return rec, ens
+
+
+def run_c5_chunk(aw, wl, torch, chunk: int = 100_000):
+    """One chunk of the largest configuration: the 1e7-orbit ensemble uniform
+    on [0, 2 pi)^6 (eps = 5e-3) advanced by 1e5 of its 1e6 steps from the
+    initial conditions, the state left in HBM as the chunked run carries it."""
+    e = wl.c5()
+    N = e.size
+    carry = torch.empty((aw.NCARRY, N), dtype=torch.float64, device="cuda")
+    aw.map_ensemble_steps(e, carry, 0, 1000)          # warm-up (loads the kernel)
+    torch.cuda.synchronize()
+    aw.timing_read()
+    aw.timing_enable(True)
+    t0 = time.perf_counter()
+    aw.map_ensemble_steps(e, carry, 0, chunk)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    aw.timing_enable(False)
+    kern_ms, launches = aw.timing_read()
+    del carry
+    log(f"c5 chunk: {N} orbits x {chunk} steps in {elapsed:.2f} s")
+    return {"workload": f"c5 chunk: {N} orbits uniform on [0,2pi)^6 (seed 2), eps=5e-3, steps 0..{chunk} of 1e6, "
+                        f"S6 + tangent, state carried in HBM", "value": N * chunk / elapsed, "unit": "map-steps/s",
+            "ms": elapsed * 1e3, "n_orbits": N, "n_steps": chunk,
+            "roofline": roofline(aw, e, kern_ms / max(launches, 1), "c5", steps_per_launch=chunk)}
 
 
 def run_batched(args, aw, wl, torch):
@@ -702,8 +747,10 @@ def main():
     ap.add_argument("--n-orbits", type=int, default=10_000_000, help="c5: ensemble size")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-1core", action="store_true",
-                    help="also time the oracle on one host thread (cpu_baseline_1core)")
+    ap.add_argument("--no-cpu-1core", action="store_true",
+                    help="leave out the oracle on one host thread (cpu_baseline_1core)")
+    ap.add_argument("--no-c5-chunk", action="store_true",
+                    help="c2: leave out the sub-record of one 1e5-step chunk of the 1e7-orbit ensemble")
     ap.add_argument("--block", type=int, default=0, help="lanes per block; 0 = the library's automatic choice")
     ap.add_argument("--opl", type=int, default=1)
     ap.add_argument("--unroll", type=int, default=1)
@@ -739,13 +786,15 @@ def main():
               "fig2": run_sphere, "fig3": run_sphere, "fig4": run_diffusion, "sweep": run_sweep,
               "nsweep": run_nsweep, "peak": run_peak, "forms": run_forms}
     rec, ens = runner[args.workload](args, aw, wl, torch)
+    if args.workload == "c2" and not args.no_c5_chunk:
+        rec["c5_chunk"] = run_c5_chunk(aw, wl, torch)
     rec.setdefault("cpu_baseline", None)
     if ens is not None and not args.no_cpu_baseline and args.workload in ("c1", "c2", "c5"):
         threads = host_threads()
         log(f"cpu baseline on {threads} threads ...")
         rec["cpu_baseline"] = cpu_baseline(ens, args.cpu_seconds, threads)
         rec["speedup_vs_oracle"] = rec["value"] / rec["cpu_baseline"]["value"]
-        if args.cpu_1core:
+        if not args.no_cpu_1core:
             log("cpu baseline on 1 thread ...")
             rec["cpu_baseline_1core"] = cpu_baseline(ens, args.cpu_seconds, 1)
             rec["speedup_vs_oracle_1core"] = rec["value"] / rec["cpu_baseline_1core"]["value"]

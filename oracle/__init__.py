@@ -61,6 +61,13 @@ _lp = ctypes.POINTER(ctypes.c_long)
 _up = ctypes.POINTER(ctypes.c_uint32)
 
 
+def use_build(path: str) -> None:
+    """Load the oracle from another build of the same source (a build
+    variant) for every later call in this process."""
+    global _lib
+    _lib = open_library(path)
+
+
 def _load():
     global _lib
     if _lib is not None:
