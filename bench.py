@@ -316,8 +316,18 @@ def run_batched(args, aw, wl, torch):
         sep.append(aw.indicator_image(e, spec, want_counts=True, tuning=tun))
     torch.cuda.synchronize()
     ts = time.perf_counter() - t0
-    log(f"separate (64 launches): {ts:.2f} s")
+    log(f"separate (64 launches, the batch's launch shape): {ts:.2f} s")
+    # The separate launches again, each with the shape tuned for it alone.
+    own = [autotune([e]) for e in ens]
+    aw.map_ensembles([small[0]], tuning=own[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sep_own = [aw.indicator_image(e, spec, want_counts=True, tuning=t) for e, t in zip(ens, own)]
+    torch.cuda.synchronize()
+    ts_own = time.perf_counter() - t0
+    log(f"separate (64 launches, each with its own tuned shape): {ts_own:.2f} s")
     same = all(torch.equal(a, b[0]) and torch.equal(c, b[1]) for a, c, b in zip(imgs, cnts, sep))
+    same = same and all(torch.equal(a, b[0]) for a, b in zip(imgs, sep_own))
     graph.close()
     rec = base_record(total / tb, 1, 0, tb * 1e3)
     rec["config"] = {"workload": f"c3: 64 ensembles, eps 1e-4..1e-1 log-spaced, grids 128^2..1024^2 and T "
@@ -326,7 +336,9 @@ def run_batched(args, aw, wl, torch):
                      "tuning": dataclasses.asdict(tun)}
     rec["batched_s"] = tb
     rec["separate_s"] = ts
-    rec["batched_over_separate_throughput"] = ts / tb
+    rec["separate_own_tuning_s"] = ts_own
+    rec["batched_over_separate_throughput"] = ts_own / tb
+    rec["batched_over_separate_same_shape"] = ts / tb
     rec["batched_equals_separate_bitwise"] = bool(same)
     return rec, None
 

@@ -3,13 +3,16 @@
 Times short probes of an ensemble (the same descriptor with a reduced number
 of steps) under every candidate (block, orbits per lane, unroll) with the
 library's HIP-event kernel timing, keeps the fastest, and caches the choice in
-a JSON file keyed by device, map form, tangent flag and ensemble-size bucket.
-Results are bitwise independent of the choice, so tuning never changes
-numbers, only speed.
+a JSON file keyed by device, library build, single launch or batch, map form,
+tangent flag and ensemble-size bucket.  A batch runs as one persistent launch,
+which takes blocks of at most 256 lanes and does not unroll, so a batch is
+tuned over block and orbits per lane only.  Results are bitwise independent
+of the choice, so tuning never changes numbers, only speed.
 """
 from __future__ import annotations
 
 import dataclasses
+import hashlib
 import json
 import math
 import os
@@ -17,17 +20,33 @@ from typing import Dict, List, Optional, Sequence, Tuple
 
 import torch
 
-from . import Ensemble, Tuning, map_ensembles, timing_enable, timing_read
+from . import Ensemble, Tuning, _abi, map_ensembles, timing_enable, timing_read
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "arnoldweb_tuning.json")
 CANDIDATES: Tuple[Tuple[int, int, int], ...] = tuple(
     (b, o, u) for b in (64, 128, 256, 512) for o in (1, 2) for u in (1, 2))
+# The persistent launch of a batch: blocks above 256 lanes run as 256, and the
+# step loop is not unrolled.
+BATCH_CANDIDATES: Tuple[Tuple[int, int, int], ...] = tuple((b, o, 1) for b in (64, 128, 256) for o in (1, 2))
+
+_LIB_ID = None
 
 
-def _key(ens: Ensemble, n_total: int) -> str:
+def _lib_id() -> str:
+    """Identity of the library build: size and a hash of libaw.so."""
+    global _LIB_ID
+    if _LIB_ID is None:
+        with open(_abi.LIB_PATH, "rb") as f:
+            data = f.read()
+        _LIB_ID = f"{len(data)}:{hashlib.sha1(data).hexdigest()[:12]}"
+    return _LIB_ID
+
+
+def _key(ens: Ensemble, n_total: int, batch: bool) -> str:
     name = torch.cuda.get_device_name(torch.cuda.current_device()).replace("|", "/")
     bucket = 1 << max(0, int(math.log2(max(1, n_total))))
-    return f"{name}|form={ens.map_form}|tangent={int(ens.tangent)}|N~{bucket}"
+    return (f"{name}|lib={_lib_id()}|{'batch' if batch else 'single'}|form={ens.map_form}|"
+            f"tangent={int(ens.tangent)}|N~{bucket}")
 
 
 def _load(path: str) -> Dict[str, dict]:
@@ -64,11 +83,14 @@ def probe_time(ens_list: Sequence[Ensemble], tuning: Tuning, reps: int = 3) -> f
 
 
 def autotune(ens_list: Sequence[Ensemble], probe_steps: int = 200, cache: Optional[str] = DEFAULT_CACHE,
-             force: bool = False, candidates=CANDIDATES, verbose: bool = False) -> Tuning:
+             force: bool = False, candidates=None, verbose: bool = False) -> Tuning:
     """Pick the fastest launch shape for one ensemble or a batch of them."""
     ens_list = list(ens_list)
+    batch = len(ens_list) > 1
+    if candidates is None:
+        candidates = BATCH_CANDIDATES if batch else CANDIDATES
     n_total = sum(e.size for e in ens_list)
-    key = _key(ens_list[0], n_total)
+    key = _key(ens_list[0], n_total, batch)
     data = _load(cache) if cache else {}
     if not force and key in data:
         return Tuning(**data[key]["tuning"])

@@ -22,17 +22,21 @@ Workloads (all M = 3, FP64, the sixth-order map S6, h = 0.01 * 2 pi -- section
   c5     orbits 0..4095 of the 1e7-orbit ensemble uniform on [0, 2 pi)^6
          (SplitMix64 seed 2, counter 16 n + k), eps = 5e-3, T = 1e6: all nine
          per-orbit rows.
+  c5spread  the same orbits' one-ulp spread: for every orbit and row, the
+         largest change of the oracle's value when one initial coordinate
+         moves by one ulp either way (12 runs per orbit; how far binary64
+         fixes each value at this horizon).
   sweep  the pz0 = 1 companion slice of the 256 x 256 grid, T = 3e4, 16 eps
          values 10^(-4 + 3k/15), on its stride-2 128 x 128 sub-grid: packed
          class bits per eps, chi of every point in [1.4, 3.0], and the
          oracle's chaotic fractions and their log-log slope against eps.
 
-Usage: python tests/golden/make_goldens.py [--only c4,c5,sweep,c2sub,c2full]
+Usage: python tests/golden/make_goldens.py [--only c4,c5,c5spread,sweep,c2sub,c2full]
        [--threads N] [--work DIR]
 Chunks of the long runs are kept under --work so that an interrupted run
 resumes where it stopped.  The oracle takes about 1e6 map steps per second
-per core: on 7 cores c4 ~7 min, c5 ~10 min, sweep ~20 min, c2sub ~16 min,
-c2full ~4 h.
+per core: on 7 cores c4 ~7 min, c5 ~10 min, c5spread ~2 h, sweep ~20 min,
+c2sub ~16 min, c2full ~4 h.
 """
 from __future__ import annotations
 
@@ -153,6 +157,34 @@ def make_c5(threads, work):
     log(f"c5: {np.sum(out[2] < 1.5)} of {M} orbits regular (chi < 1.5)")
 
 
+def one_ulp_spread(ic, w0, eps, T, threads):
+    """For every orbit (column of ic[6, n]): the largest change of each of the
+    oracle's nine output rows when one of its six initial coordinates moves by
+    one ulp down or up (12 runs per orbit).  Returns spread[9, n] (absolute)."""
+    n = ic.shape[1]
+    base = oracle.ensemble("s6", eps, H, T, ic, w0, nthreads=threads)
+    moved = np.repeat(ic, 12, axis=1)
+    for k in range(n):
+        for a in range(6):
+            moved[a, 12 * k + 2 * a] = np.nextafter(ic[a, k], -np.inf)
+            moved[a, 12 * k + 2 * a + 1] = np.nextafter(ic[a, k], np.inf)
+    out = oracle.ensemble("s6", eps, H, T, moved, np.repeat(w0, 12, axis=1), nthreads=threads)
+    return np.max(np.abs(out.reshape(9, n, 12) - base[:, :, None]), axis=2)
+
+
+def make_c5spread(threads, work):
+    T, eps, M = 1_000_000, 5e-3, 4096
+
+    def run(idx):
+        ic = oracle.ic_box([0.0] * 6, [TWO_PI] * 6, 2, idx=idx)
+        return one_ulp_spread(ic, oracle.w0(0, idx=idx), eps, T, threads)
+
+    spread = chunked("c5spread", M, 64, run, work)
+    np.savez_compressed(os.path.join(HERE, "c5_box_orbits0-4095_T1e6_one_ulp_spread.npz"), eps=eps, T=T,
+                        seed_ic=2, spread=spread)
+    log(f"c5spread: median one-ulp spread of L {np.median(spread[0]):.3e}")
+
+
 def make_sweep(threads, work):
     n, T, pz0, stride = 256, 30_000, 1.0, 2
     eps = np.array([10.0 ** (-4.0 + 3.0 * k / 15.0) for k in range(16)])
@@ -185,7 +217,8 @@ def main():
     ap.add_argument("--work", default=os.path.join(ROOT, "_work", "golden_chunks"))
     a = ap.parse_args()
     os.makedirs(a.work, exist_ok=True)
-    jobs = {"c2sub": make_c2sub, "c2full": make_c2full, "c4": make_c4, "c5": make_c5, "sweep": make_sweep}
+    jobs = {"c2sub": make_c2sub, "c2full": make_c2full, "c4": make_c4, "c5": make_c5, "c5spread": make_c5spread,
+            "sweep": make_sweep}
     for name in a.only.split(","):
         t0 = time.time()
         jobs[name](a.threads, a.work)

@@ -67,3 +67,11 @@ def test_autotuner_picks_caches_and_reuses(aw, tmp_path):
     assert all(ms > 0 for ms in rec["probe_ms"].values())
     again = autotune.autotune([e], probe_steps=50, cache=cache, candidates=((128, 1, 1),))
     assert (again.block, again.orbits_per_lane, again.unroll) == (t.block, t.orbits_per_lane, t.unroll)
+    # a batch runs as one persistent launch: tuned over its own candidates
+    # (blocks up to 256, no unroll) and cached under its own key
+    tb = autotune.autotune([e, wl.slice_ensemble(2e-2, 32, 300)], probe_steps=50, cache=cache)
+    assert (tb.block, tb.orbits_per_lane, tb.unroll) in autotune.BATCH_CANDIDATES
+    data = json.load(open(cache))
+    keys = [k for k in data if "|batch|" in k]
+    assert len(data) == 2 and len(keys) == 1
+    assert set(data[keys[0]]["probe_ms"]) == {f"{b},{o},{u}" for b, o, u in autotune.BATCH_CANDIDATES}
