@@ -112,31 +112,51 @@ __device__ __forceinline__ void rev_drift2(Orbit &o, Adjoint2 &a, double t) {
 //   S_v = -dPbar_v (e1 sin v dv + 2 e2 cos v dz) - dPbar_z Bv,
 //   S_z = -2 dPbar_u Bu - 2 dPbar_v Bv
 //         - dPbar_z (g sin u du + g sin v dv + 4 e2 cs dz).
+// F and M carry the factor eps.  For eps != 0 (EPS0 false) a.eb collects
+// eps epsbar, F . Pbar + (M dX) . dPbar with the M dX the undo needs anyway,
+// and the kernel divides by eps once at the end.  For eps = 0 (EPS0 true)
+// F / eps and M / eps are formed from w2 = 2 t directly.
 // Sines and cosines from the same table as the forward kick.
+template <bool EPS0>
 __device__ __forceinline__ void rev_kick2(Orbit &o, Adjoint2 &a, double a2, double w2,
                                           const double2 *__restrict__ tab) {
   const SinCosT U = sincos_tab(o.x, tab), V = sincos_tab(o.y, tab);
   const ZTerms Z = zterms_tab(o.z, tab);
   const double e1 = a2 * Z.cz2, e2 = a2 * Z.czsz, g = __builtin_fma(2.0, e1, -a2);
-  const double f1 = w2 * Z.cz2, f2 = w2 * Z.czsz, gf = __builtin_fma(2.0, f1, -w2);
   const double cs = U.c + V.c;
   const double du = o.dx, dv = o.dy, dz = o.dz;
   const double pub = a.pxb, pvb = a.pyb, pzb = a.pzb;
   const double dpub = a.dpxb, dpvb = a.dpyb, dpzb = a.dpzb;
-  // M and M / eps.
+  // M.
   const double muu = e1 * U.c, mvv = e1 * V.c, muz = -2.0 * e2 * U.s, mvz = -2.0 * e2 * V.s;
   const double mzu = -e2 * U.s, mzv = -e2 * V.s, mzz = cs * g;
-  const double wuu = f1 * U.c, wvv = f1 * V.c, wuz = -2.0 * f2 * U.s, wvz = -2.0 * f2 * V.s;
-  const double wzu = -f2 * U.s, wzv = -f2 * V.s, wzz = cs * gf;
+  // M dX: the tangent kick of the forward step.
+  const double mdu = __builtin_fma(muu, du, muz * dz);
+  const double mdv = __builtin_fma(mvv, dv, mvz * dz);
+  const double mdz = __builtin_fma(mzu, du, __builtin_fma(mzv, dv, mzz * dz));
 
-  // epsbar.
-  double eb = a.eb;
-  eb = __builtin_fma(f1, __builtin_fma(U.s, pub, V.s * pvb), eb);
-  eb = __builtin_fma(f2 * cs, pzb, eb);
-  eb = __builtin_fma(__builtin_fma(wuu, du, wuz * dz), dpub, eb);
-  eb = __builtin_fma(__builtin_fma(wvv, dv, wvz * dz), dpvb, eb);
-  eb = __builtin_fma(__builtin_fma(wzu, du, __builtin_fma(wzv, dv, wzz * dz)), dpzb, eb);
-  a.eb = eb;
+  if constexpr (EPS0) {
+    // epsbar from F / eps and M / eps.
+    const double f1 = w2 * Z.cz2, f2 = w2 * Z.czsz, gf = __builtin_fma(2.0, f1, -w2);
+    const double wuu = f1 * U.c, wvv = f1 * V.c, wuz = -2.0 * f2 * U.s, wvz = -2.0 * f2 * V.s;
+    const double wzu = -f2 * U.s, wzv = -f2 * V.s, wzz = cs * gf;
+    double eb = a.eb;
+    eb = __builtin_fma(f1, __builtin_fma(U.s, pub, V.s * pvb), eb);
+    eb = __builtin_fma(f2 * cs, pzb, eb);
+    eb = __builtin_fma(__builtin_fma(wuu, du, wuz * dz), dpub, eb);
+    eb = __builtin_fma(__builtin_fma(wvv, dv, wvz * dz), dpvb, eb);
+    eb = __builtin_fma(__builtin_fma(wzu, du, __builtin_fma(wzv, dv, wzz * dz)), dpzb, eb);
+    a.eb = eb;
+  } else {
+    // eps epsbar.
+    double eb = a.eb;
+    eb = __builtin_fma(e1, __builtin_fma(U.s, pub, V.s * pvb), eb);
+    eb = __builtin_fma(e2 * cs, pzb, eb);
+    eb = __builtin_fma(mdu, dpub, eb);
+    eb = __builtin_fma(mdv, dpvb, eb);
+    eb = __builtin_fma(mdz, dpzb, eb);
+    a.eb = eb;
+  }
 
   // Xbar += M^T Pbar + S.
   const double e2cu = e2 * U.c, e2cv = e2 * V.c, gsu = g * U.s, gsv = g * V.s;
@@ -162,15 +182,15 @@ __device__ __forceinline__ void rev_kick2(Orbit &o, Adjoint2 &a, double a2, doub
   a.dzb = __builtin_fma(muz, dpub, __builtin_fma(mvz, dpvb, __builtin_fma(mzz, dpzb, a.dzb)));
 
   // Undo the kick: dP -= M dX, P -= F.
-  o.dpx = __builtin_fma(-muu, du, __builtin_fma(-muz, dz, o.dpx));
-  o.dpy = __builtin_fma(-mvv, dv, __builtin_fma(-mvz, dz, o.dpy));
-  o.dpz = __builtin_fma(-mzu, du, __builtin_fma(-mzv, dv, __builtin_fma(-mzz, dz, o.dpz)));
+  o.dpx -= mdu;
+  o.dpy -= mdv;
+  o.dpz -= mdz;
   o.px = __builtin_fma(-e1, U.s, o.px);
   o.py = __builtin_fma(-e1, V.s, o.py);
   o.pz = __builtin_fma(-e2, cs, o.pz);
 }
 
-template <int FORM>
+template <int FORM, bool EPS0>
 __device__ __forceinline__ void rev_tan_step(Orbit &o, Adjoint2 &a, const AdjDesc &d, const double2 *__restrict__ tab) {
   using F = FormPattern<FORM>;
   constexpr int NK = F::NK;
@@ -179,12 +199,12 @@ __device__ __forceinline__ void rev_tan_step(Orbit &o, Adjoint2 &a, const AdjDes
 #pragma unroll
     for (int i = NK - 1; i >= 0; --i) {
       const int u = F::kick_idx[i];
-      rev_kick2(o, a, d.ka2[u], d.kw2[u], tab);
+      rev_kick2<EPS0>(o, a, d.ka2[u], d.kw2[u], tab);
       rev_drift2(o, a, d.drift[F::drift_idx[i]]);
     }
   } else {
     rev_drift2(o, a, d.drift[0]);
-    rev_kick2(o, a, d.ka2[0], d.kw2[0], tab);
+    rev_kick2<EPS0>(o, a, d.ka2[0], d.kw2[0], tab);
   }
 }
 
@@ -293,7 +313,7 @@ __global__ __launch_bounds__(512) void k_ftle_fwd(FtleDesc d) {
   }
 }
 
-template <int FORM>
+template <int FORM, bool EPS0>
 __global__ __launch_bounds__(512) void k_ftle_bwd(FtleDesc d) {
   __shared__ double2 s_tab[AW_TAB_N];
   load_sincos_table(s_tab);
@@ -333,13 +353,14 @@ __global__ __launch_bounds__(512) void k_ftle_bwd(FtleDesc d) {
         a.dpyb = __builtin_amdgcn_ldexp(a.dpyb, -k);
         a.dpzb = __builtin_amdgcn_ldexp(a.dpzb, -k);
       }
-      rev_tan_step<FORM>(o, a, d, s_tab);
+      rev_tan_step<FORM, EPS0>(o, a, d, s_tab);
     }
   }
+  if (!EPS0) a.eb /= d.eps;   // the kicks collected eps epsbar
   store_grad2(d, n, a);
 }
 
-template <int FORM>
+template <int FORM, bool EPS0>
 __global__ __launch_bounds__(512) void k_ftle_bwd_rev(FtleDesc d) {
   __shared__ double2 s_tab[AW_TAB_N];
   load_sincos_table(s_tab);
@@ -378,9 +399,10 @@ __global__ __launch_bounds__(512) void k_ftle_bwd_rev(FtleDesc d) {
         a.dpyb = __builtin_amdgcn_ldexp(a.dpyb, -k);
         a.dpzb = __builtin_amdgcn_ldexp(a.dpzb, -k);
       }
-      rev_tan_step<FORM>(o, a, d, s_tab);   // o: the state at the start of step g
+      rev_tan_step<FORM, EPS0>(o, a, d, s_tab);   // o: the state at the start of step g
     }
   }
+  if (!EPS0) a.eb /= d.eps;   // the kicks collected eps epsbar
   store_grad2(d, n, a);
 }
 
@@ -388,14 +410,30 @@ __global__ __launch_bounds__(512) void k_ftle_bwd_rev(FtleDesc d) {
 
 hipError_t launch_ftle_backward_reversible(const FtleDesc &d, int form, const Tuning &t, hipStream_t s) {
   if (d.N <= 0) return hipSuccess;
+  const bool e0 = d.eps == 0.0;
   const int tb = block_for(t, d.N);
   const unsigned blocks = (unsigned)((d.N + tb - 1) / tb);
   switch (form) {
-  case 1: hipLaunchKernelGGL(k_ftle_bwd_rev<1>, dim3(blocks), dim3(tb), 0, s, d); break;
-  case 2: hipLaunchKernelGGL(k_ftle_bwd_rev<2>, dim3(blocks), dim3(tb), 0, s, d); break;
-  case 4: hipLaunchKernelGGL(k_ftle_bwd_rev<4>, dim3(blocks), dim3(tb), 0, s, d); break;
-  case 6: hipLaunchKernelGGL(k_ftle_bwd_rev<6>, dim3(blocks), dim3(tb), 0, s, d); break;
-  case 7: hipLaunchKernelGGL(k_ftle_bwd_rev<7>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 1:
+    if (e0) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ftle_bwd_rev<1, true>), dim3(blocks), dim3(tb), 0, s, d);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ftle_bwd_rev<1, false>), dim3(blocks), dim3(tb), 0, s, d);
+    break;
+  case 2:
+    if (e0) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ftle_bwd_rev<2, true>), dim3(blocks), dim3(tb), 0, s, d);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ftle_bwd_rev<2, false>), dim3(blocks), dim3(tb), 0, s, d);
+    break;
+  case 4:
+    if (e0) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ftle_bwd_rev<4, true>), dim3(blocks), dim3(tb), 0, s, d);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ftle_bwd_rev<4, false>), dim3(blocks), dim3(tb), 0, s, d);
+    break;
+  case 6:
+    if (e0) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ftle_bwd_rev<6, true>), dim3(blocks), dim3(tb), 0, s, d);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ftle_bwd_rev<6, false>), dim3(blocks), dim3(tb), 0, s, d);
+    break;
+  case 7:
+    if (e0) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ftle_bwd_rev<7, true>), dim3(blocks), dim3(tb), 0, s, d);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ftle_bwd_rev<7, false>), dim3(blocks), dim3(tb), 0, s, d);
+    break;
   default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -418,14 +456,30 @@ hipError_t launch_ftle_forward(const FtleDesc &d, int form, const Tuning &t, hip
 
 hipError_t launch_ftle_backward(const FtleDesc &d, int form, const Tuning &t, hipStream_t s) {
   if (d.N <= 0) return hipSuccess;
+  const bool e0 = d.eps == 0.0;
   const int tb = block_for(t, d.N);
   const unsigned blocks = (unsigned)((d.N + tb - 1) / tb);
   switch (form) {
-  case 1: hipLaunchKernelGGL(k_ftle_bwd<1>, dim3(blocks), dim3(tb), 0, s, d); break;
-  case 2: hipLaunchKernelGGL(k_ftle_bwd<2>, dim3(blocks), dim3(tb), 0, s, d); break;
-  case 4: hipLaunchKernelGGL(k_ftle_bwd<4>, dim3(blocks), dim3(tb), 0, s, d); break;
-  case 6: hipLaunchKernelGGL(k_ftle_bwd<6>, dim3(blocks), dim3(tb), 0, s, d); break;
-  case 7: hipLaunchKernelGGL(k_ftle_bwd<7>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 1:
+    if (e0) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ftle_bwd<1, true>), dim3(blocks), dim3(tb), 0, s, d);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ftle_bwd<1, false>), dim3(blocks), dim3(tb), 0, s, d);
+    break;
+  case 2:
+    if (e0) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ftle_bwd<2, true>), dim3(blocks), dim3(tb), 0, s, d);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ftle_bwd<2, false>), dim3(blocks), dim3(tb), 0, s, d);
+    break;
+  case 4:
+    if (e0) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ftle_bwd<4, true>), dim3(blocks), dim3(tb), 0, s, d);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ftle_bwd<4, false>), dim3(blocks), dim3(tb), 0, s, d);
+    break;
+  case 6:
+    if (e0) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ftle_bwd<6, true>), dim3(blocks), dim3(tb), 0, s, d);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ftle_bwd<6, false>), dim3(blocks), dim3(tb), 0, s, d);
+    break;
+  case 7:
+    if (e0) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ftle_bwd<7, true>), dim3(blocks), dim3(tb), 0, s, d);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ftle_bwd<7, false>), dim3(blocks), dim3(tb), 0, s, d);
+    break;
   default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
