@@ -160,13 +160,19 @@ typedef struct {
  * propagation and the batched persistent launch run a block above 256 (or
  * automatic) as 256.  orbits_per_lane in {1, 2}; unroll in {1, 2};
  * renorm_every in {1, 2, 4, 8, 16}.  persistent_wgs: workgroups of the batched
- * persistent launch (0 = auto). */
+ * persistent launch (0 = auto).  lanes_per_orbit in {0, 1, 2}: tangent-free
+ * launches that end before n_steps (aw_map_ensemble_steps) or bin time windows
+ * (aw_window_density), without AW_F_WINDOW, can run one orbit on two lanes (u
+ * and p_u on one, v and p_v on the other, in the rotated frame); 0 does so
+ * when one lane per orbit would leave SIMDs without a wave (fewer than
+ * 64 x 4 x CUs orbits).  Results are bitwise the same either way. */
 typedef struct {
   int32_t block;
   int32_t orbits_per_lane;
   int32_t unroll;
   int32_t renorm_every;
   int32_t persistent_wgs;
+  int32_t lanes_per_orbit;
 } aw_tuning;
 
 /* Number of orbits of an ensemble (nx*ny for GRID2), or -1 if invalid. */

@@ -129,10 +129,11 @@ class Tuning:
     unroll: int = 1
     renorm_every: int = 8
     persistent_wgs: int = 0
+    lanes_per_orbit: int = 0
 
     def to_c(self) -> _abi.AwTuning:
         return _abi.AwTuning(self.block, self.orbits_per_lane, self.unroll, self.renorm_every,
-                             self.persistent_wgs)
+                             self.persistent_wgs, self.lanes_per_orbit)
 
 
 @dataclass

@@ -65,6 +65,7 @@ class AwTuning(ctypes.Structure):
         ("unroll", ctypes.c_int32),
         ("renorm_every", ctypes.c_int32),
         ("persistent_wgs", ctypes.c_int32),
+        ("lanes_per_orbit", ctypes.c_int32),
     ]
 
 

@@ -273,6 +273,7 @@ aw_status check_tuning(const aw_tuning *t, Tuning &out) {
   out.unroll = t->unroll ? t->unroll : 1;
   out.renorm = t->renorm_every ? t->renorm_every : 8;
   out.pwgs = t->persistent_wgs;
+  out.lpo = t->lanes_per_orbit;
   if (out.block != 0 && out.block != 64 && out.block != 128 && out.block != 256 && out.block != 512)
     return fail(AW_EINVAL, "tuning.block must be 0 (automatic), 64, 128, 256 or 512 (got %d)", out.block);
   if (out.opl != 1 && out.opl != 2) return fail(AW_EINVAL, "tuning.orbits_per_lane must be 1 or 2");
@@ -280,6 +281,7 @@ aw_status check_tuning(const aw_tuning *t, Tuning &out) {
   if (out.renorm < 1 || out.renorm > 16 || (out.renorm & (out.renorm - 1)))
     return fail(AW_EINVAL, "tuning.renorm_every must be 1, 2, 4, 8 or 16");
   if (out.pwgs < 0) return fail(AW_EINVAL, "tuning.persistent_wgs must be >= 0");
+  if (out.lpo != 0 && out.lpo != 1 && out.lpo != 2) return fail(AW_EINVAL, "tuning.lanes_per_orbit must be 0, 1 or 2");
   return AW_OK;
 }
 

@@ -435,6 +435,157 @@ __global__ __launch_bounds__((FILT || WINV) ? 256 : 512) void k_fwd(FwdDesc d) {
   run_orbits<FORM, TAN, OPL, UNR, FILT, WINV>(d, first, s_tab);
 }
 
+// ---------------------------------------------------------------------------
+// Two lanes per orbit, for tangent-free ensembles too small to give every
+// SIMD a wave at one lane per orbit (Fig. 4's 3.2e4 orbits make 500 waves for
+// 1024 SIMDs).  In the rotated frame the force does not couple u and v, so
+// lane 2m of a pair holds u and p_u and lane 2m + 1 holds v and p_v, and both
+// hold z and p_z.  A kick takes one table sine and cosine of the lane's own
+// coordinate and the z factors, swaps the cosine with the partner lane
+// (cs = cos u + cos v is the same sum in both lanes: IEEE addition commutes),
+// and advances the lane's own momentum and p_z; a drift advances the lane's
+// coordinate and z.  Every value is formed and rounded as in run_orbits, so
+// the states, carries and window bins are bitwise those of one lane per
+// orbit.  Intermediate and time-window launches only: the final epilogue and
+// the window test run one lane per orbit.
+// ---------------------------------------------------------------------------
+// Lanes 2m and 2m + 1 exchange v (DPP quad_perm [1, 0, 3, 2] on both halves).
+// Every lane of the wave takes part: lanes past the ensemble's end repeat a
+// valid orbit.
+__device__ __forceinline__ double swap_pair(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0xB1, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+struct HalfOrbit {
+  double w, pw;    // own rotated coordinate (u or v) and its momentum
+  double z, pz;
+  double p0w, p0z;
+  double jsum;     // meaningful in the pair's even lane
+};
+
+__device__ __forceinline__ void pair_kick(HalfOrbit &h, double a2, const double2 *__restrict__ tab) {
+  const SinCosT W = sincos_tab(h.w, tab);
+  const ZTerms Z = zterms_tab(h.z, tab);
+  const double e1 = a2 * Z.cz2;
+  const double e2 = a2 * Z.czsz;
+  const double cs = W.c + swap_pair(W.c);
+  h.pw = __builtin_fma(e1, W.s, h.pw);
+  h.pz = __builtin_fma(e2, cs, h.pz);
+}
+
+__device__ __forceinline__ void pair_drift(HalfOrbit &h, double t) {
+  h.w = __builtin_fma(t, h.pw, h.w);
+  h.z = __builtin_fma(t, h.pz, h.z);
+}
+
+template <int FORM>
+__device__ __forceinline__ void pair_step(HalfOrbit &h, const StepWeights &d, const double2 *__restrict__ tab) {
+  using F = FormPattern<FORM>;
+  constexpr int NK = F::NK;
+  if constexpr (F::LEAD) {
+#pragma unroll
+    for (int i = 0; i < NK; ++i) {
+      pair_drift(h, d.drift[F::drift_idx[i]]);
+      pair_kick(h, d.ka2[F::kick_idx[i]], tab);
+    }
+    pair_drift(h, d.drift[F::drift_idx[NK]]);
+  } else {
+    pair_kick(h, d.ka2[0], tab);
+    pair_drift(h, d.drift[0]);
+  }
+}
+
+template <int FORM, bool WINV>
+__global__ __launch_bounds__(256) void k_fwd_pair(FwdDesc d) {
+  __shared__ double2 s_tab[AW_TAB_N];
+  load_sincos_table(s_tab);
+  const int64_t m0 = (int64_t)blockIdx.x * (blockDim.x >> 1) + (threadIdx.x >> 1);
+  const bool act = m0 < d.N;
+  const int64_t m = act ? m0 : d.N - 1;   // past the end: repeat a valid orbit, never stored
+  const bool odd = (threadIdx.x & 1u) != 0;
+  const int64_t N = d.N;
+  HalfOrbit h;
+  if (d.k_begin == 0) {
+#pragma clang fp contract(off)
+    double s[6];
+    gen_ic(d, m, s);
+    h.w = odd ? s[0] - s[1] : s[0] + s[1];
+    h.pw = odd ? s[3] - s[4] : s[3] + s[4];
+    h.z = s[2];
+    h.pz = s[5];
+    h.p0w = h.pw;
+    h.p0z = s[5];
+    h.jsum = 0.0;
+  } else {
+    const double *c = d.carry;
+    const int64_t r = odd ? 1 : 0;
+    h.w = c[(0 + r) * N + m];
+    h.pw = c[(3 + r) * N + m];
+    h.z = c[2 * N + m];
+    h.pz = c[5 * N + m];
+    h.p0w = c[(15 + r) * N + m];
+    h.p0z = c[17 * N + m];
+    h.jsum = c[18 * N + m];
+  }
+  const double ws = h.w, zs = h.z;
+  StepWeights sw;
+#pragma unroll
+  for (int q = 0; q < MAX_UNIQUE; ++q) {
+    sw.drift[q] = d.drift[q];
+    sw.ka2[q] = d.ka2[q];
+  }
+#pragma nounroll
+  for (int64_t k = d.k_begin; k < d.k_end; ++k) {
+    pair_step<FORM>(h, sw, s_tab);
+    // J as run_orbits accumulates it, in the even lane: (p_u - p0_u)^2, then
+    // (p_v - p0_v)^2, then twice (p_z - p0_z)^2.
+    const double e = h.pw - h.p0w;
+    const double ep = swap_pair(e);
+    const double ez = h.pz - h.p0z;
+    const double ez2 = ez + ez;
+    h.jsum = __builtin_fma(e, e, h.jsum);
+    h.jsum = __builtin_fma(ep, ep, h.jsum);
+    h.jsum = __builtin_fma(ez, ez2, h.jsum);
+  }
+  const double dw = h.w - ws;
+  const double dwp = swap_pair(dw);   // the partner's displacement
+  if (!act) return;
+  double *c = d.carry;
+  if (odd) {
+    c[1 * N + m] = h.w;
+    c[4 * N + m] = h.pw;
+    c[16 * N + m] = h.p0w;
+    return;
+  }
+  if (WINV) {
+#pragma clang fp contract(off)
+    double phi, mu;
+    const double du = dw, dv = dwp;
+    vdir_key(0.5 * (du + dv) / d.wdt, 0.5 * (du - dv) / d.wdt, (h.z - zs) / d.wdt, phi, mu);
+    d.bins[m] = bin_of(phi, mu, d.klo0, d.khi0, d.klo1, d.khi1, d.W, d.H, true);
+  }
+  c[0 * N + m] = h.w;
+  c[2 * N + m] = h.z;
+  c[3 * N + m] = h.pw;
+  c[5 * N + m] = h.pz;
+  c[15 * N + m] = h.p0w;
+  c[17 * N + m] = h.p0z;
+  c[18 * N + m] = h.jsum;
+  c[20 * N + m] = (double)d.k_end;
+  if (d.k_begin == 0) {
+    // what a first launch of run_orbits writes for a tangent-free orbit
+    double s0[6];
+    gen_ic(d, m, s0);
+#pragma unroll
+    for (int r = 6; r < 12; ++r) c[r * N + m] = 0.0;
+    c[12 * N + m] = s0[0]; c[13 * N + m] = s0[1]; c[14 * N + m] = s0[2];
+    c[19 * N + m] = 0.0;
+  }
+  c[21 * N + m] = 0.0;   // no window test here
+}
+
 // Persistent batched propagation: each workgroup takes (ensemble, tile)
 // items from a device counter until the list, sorted longest-first, is empty.
 // Two orbits per lane take about 266 VGPRs in the rotated frame; held to 256
@@ -494,8 +645,29 @@ int block_for(const Tuning &t, int64_t n) {
   return b;
 }
 
+// Two lanes per orbit: tangent-free intermediate or time-window launches
+// without the window test, when asked for (lanes_per_orbit 2) or, by
+// default, when one lane per orbit would leave SIMDs without a wave.
+static bool use_pair(const FwdDesc &d, const Tuning &t, bool tan) {
+  if (tan || d.filter || !(d.window_v || d.k_end < d.T) || d.N <= 0) return false;
+  if (t.lpo) return t.lpo == 2;
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+    ncu = 256;
+  return d.N < (int64_t)ncu * 4 * 64;
+}
+
 template <int FORM, bool TAN>
 static hipError_t fwd_dispatch_opl(const FwdDesc &d, const Tuning &t, hipStream_t s) {
+  if (use_pair(d, t, TAN)) {
+    // 128 orbits (four waves) per block: with the 64 KB table two blocks share
+    // a CU, so a block must bring a wave for each of the CU's four SIMDs.
+    const dim3 grid((unsigned)((d.N + 127) / 128));
+    if (d.window_v) hipLaunchKernelGGL((k_fwd_pair<FORM, true>), grid, dim3(256), 0, s, d);
+    else hipLaunchKernelGGL((k_fwd_pair<FORM, false>), grid, dim3(256), 0, s, d);
+    return hipGetLastError();
+  }
   const int lanes = block_for(t, (d.N + t.opl - 1) / t.opl);
   const int64_t per_block = (int64_t)lanes * t.opl;
   const int64_t blocks = (d.N + per_block - 1) / per_block;

@@ -15,6 +15,7 @@ struct Tuning {
   int unroll = 1;
   int renorm = 8;
   int pwgs = 0;
+  int lpo = 0;    // lanes per orbit of tangent-free intermediate launches: 0 auto, 1 or 2
 };
 
 // Lanes per block for a launch over n orbits (or lanes).  A block set in the

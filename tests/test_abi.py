@@ -108,7 +108,8 @@ def test_host_validation_rejects_bad_descriptors(kw, status):
 def test_bad_tuning_is_rejected():
     lib = _abi.load()
     e = _ens()
-    for t in [(100, 1, 1, 8, 0), (256, 3, 1, 8, 0), (256, 1, 3, 8, 0), (256, 1, 1, 3, 0), (256, 1, 1, 32, 0)]:
+    for t in [(100, 1, 1, 8, 0), (256, 3, 1, 8, 0), (256, 1, 3, 8, 0), (256, 1, 1, 3, 0), (256, 1, 1, 32, 0),
+              (256, 1, 1, 8, 0, 3), (256, 1, 1, 8, 0, -1)]:
         tun = _abi.AwTuning(*t)
         st = lib.aw_map_ensemble(ctypes.byref(e), 1, None, _abi.ptr_array([None]), None, None,
                                  ctypes.byref(tun), None)
