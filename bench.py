@@ -9,7 +9,12 @@ propagation kernel, beside the CPU oracle timed on this host.
 Default workload (c2): eps = 1e-3, a 1024 x 1024 slice of (px, py) in
 [0, 2 pi)^2 with x = y = z = pz = 0, T = 1e5 steps of h = 0.01 * 2 pi, tangent
 start seed 0; one bench step = initial conditions + propagation + per-orbit
-indicators + the chi image, the class map and the chaotic count.
+indicators + the chi image, the class map and the chaotic count.  The default
+line also carries sub-records timed after the steps: one 1e5-step chunk of
+the 1e7-orbit ensemble (c5_chunk), the c4 gradients against their forward
+passes (c4_gradients), and the c3 batch at a tenth of its horizons against
+its separate launches (c3_batch_t0.1); then the oracle on all host threads
+and on one.
 
 Other workloads (measurement records, not the default line):
   c1  the 64 x 64, T = 1e3 slice at eps = 1e-2 (latency-bound);
@@ -287,6 +292,35 @@ def run_c5_chunk(aw, wl, torch, chunk: int = 100_000):
                         f"S6 + tangent, state carried in HBM", "value": N * chunk / elapsed, "unit": "map-steps/s",
             "ms": elapsed * 1e3, "n_orbits": N, "n_steps": chunk,
             "roofline": roofline(aw, e, kern_ms / max(launches, 1), "c5", steps_per_launch=chunk)}
+
+
+def sub_record(fn):
+    """A sub-record of the default line; a failure is recorded, not raised."""
+    try:
+        return fn()
+    except Exception as exc:  # noqa: BLE001 -- the main line must still print
+        log(f"sub-record failed: {exc!r}")
+        return {"error": repr(exc)}
+
+
+def c4_summary(args, aw, wl, torch):
+    """The gradients of the 512x512, T = 1e4 slice against their forward passes."""
+    sub = argparse.Namespace(**{**vars(args), "no_one_segment": True})
+    r, _ = run_adjoint(sub, aw, wl, torch)
+    keys = ("forward_s", "forward_tangent_s", "gradient_s", "gradient_over_forward", "reversible_gradient_s",
+            "reversible_gradient_over_forward", "ftle_gradient_s", "ftle_gradient_over_forward_tangent",
+            "reversible_ftle_gradient_s", "reversible_ftle_gradient_over_forward_tangent")
+    return {"workload": r["config"]["workload"], **{k: r[k] for k in keys}}
+
+
+def c3_summary(args, aw, wl, torch):
+    """The 64-ensemble batch at a tenth of its horizons: one graph launch
+    against the separate launches."""
+    sub = argparse.Namespace(**{**vars(args), "t_scale": 0.1})
+    r, _ = run_batched(sub, aw, wl, torch)
+    keys = ("batched_s", "separate_s", "separate_own_tuning_s", "batched_over_separate_throughput",
+            "batched_over_separate_same_shape", "batched_equals_separate_bitwise")
+    return {"workload": r["config"]["workload"], "value": r["value"], "unit": r["unit"], **{k: r[k] for k in keys}}
 
 
 def run_batched(args, aw, wl, torch):
@@ -766,6 +800,8 @@ def main():
                     help="leave out the oracle on one host thread (cpu_baseline_1core)")
     ap.add_argument("--no-c5-chunk", action="store_true",
                     help="c2: leave out the sub-record of one 1e5-step chunk of the 1e7-orbit ensemble")
+    ap.add_argument("--no-sub-records", action="store_true",
+                    help="c2: leave out the sub-records of the c4 gradients and of the c3 batch at horizons x0.1")
     ap.add_argument("--block", type=int, default=0, help="lanes per block; 0 = the library's automatic choice")
     ap.add_argument("--opl", type=int, default=1)
     ap.add_argument("--unroll", type=int, default=1)
@@ -805,6 +841,9 @@ def main():
     rec, ens = runner[args.workload](args, aw, wl, torch)
     if args.workload == "c2" and not args.no_c5_chunk:
         rec["c5_chunk"] = run_c5_chunk(aw, wl, torch)
+    if args.workload == "c2" and not args.no_sub_records:
+        rec["c4_gradients"] = sub_record(lambda: c4_summary(args, aw, wl, torch))
+        rec["c3_batch_t0.1"] = sub_record(lambda: c3_summary(args, aw, wl, torch))
     rec.setdefault("cpu_baseline", None)
     if ens is not None and not args.no_cpu_baseline and args.workload in ("c1", "c2", "c5"):
         threads = host_threads()

@@ -16,6 +16,7 @@ import hashlib
 import json
 import math
 import os
+import sys
 from typing import Dict, List, Optional, Sequence, Tuple
 
 import torch
@@ -101,7 +102,7 @@ def autotune(ens_list: Sequence[Ensemble], probe_steps: int = 200, cache: Option
         ms = probe_time(probes, t)
         results.append((ms, (b, o, u)))
         if verbose:
-            print(f"autotune {key}: block={b} opl={o} unroll={u}: {ms:.3f} ms", flush=True)
+            print(f"autotune {key}: block={b} opl={o} unroll={u}: {ms:.3f} ms", file=sys.stderr, flush=True)
     results.sort()
     b, o, u = results[0][1]
     best = Tuning(block=b, orbits_per_lane=o, unroll=u)
