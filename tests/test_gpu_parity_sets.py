@@ -8,9 +8,8 @@ from its definition).
   every point of the stride-4 256 x 256 sub-grid -- the class on >= 99.5% of
   them with every disagreement inside chi in [1.5, 2.5], and on regular
   orbits (oracle chi < 1.5) L, chi, dP2 and J to 1e-6 (dP2 on the scale of
-  J, its mean over the run); then every point of
-  the whole slice that the GPU classes chaotic is run by the oracle here,
-  and each must be chaotic there too or lie inside the band.
+  J, its mean over the run); then the class of every point of the whole
+  slice against the oracle's, every disagreement inside the band.
 * c5 (1e7 orbits uniform on [0, 2 pi)^6, eps = 5e-3, T = 1e6): orbits
   0..4095 -- identical to those of the full ensemble, since every draw is
   keyed on the orbit index -- run in the 1e5-step chunks with state carry
@@ -82,12 +81,12 @@ def _regular_rows(got, ref, ic, w0, eps, T, what, rows=(L_, CHI_, DP2_, J_)):
     return worst, len({b[0] for b in beyond})
 
 
-def test_c2_every_subgrid_point_and_every_chaotic_point(aw):
+def test_c2_every_subgrid_point(aw):
     from paper_1107_4107_amd import workloads as wl
     g = _golden("c2_slice_1024_T1e5_stride4.npz")
     e = wl.c2()
     assert (g["eps"], g["n"], g["T"]) == (e.eps, e.nx, e.n_steps)
-    print_case("c2 stride-4 sub-grid and chaotic points")
+    print_case("c2 stride-4 sub-grid")
     img, cnt, cls = aw.indicator_image(e, wl.chi_image(e.nx), want_counts=True, want_class=True)
     chi = np_(img).ravel()
     c = np_(cls)
@@ -103,16 +102,27 @@ def test_c2_every_subgrid_point_and_every_chaotic_point(aw):
                                  "c2 sub-grid")
     print(f"sub-grid: {idx.size} points, class agreement {frac:.5f}, {reg.size} regular, worst error within the "
           f"bar {worst:.2e}, {n_ill} beyond it within their one-ulp spread", flush=True)
-    # every point the GPU classes chaotic, on the whole slice
-    chaotic = np.flatnonzero(c)
-    assert int(np_(cnt).view(np.uint32)[0]) == chaotic.size
-    ic = oracle.ic_grid2((3, 4), (0, 0), (TWO_PI, TWO_PI), e.nx, e.ny, list(e.base), idx=chaotic)
-    chi_o = oracle.ensemble("s6", e.eps, H, e.n_steps, ic, oracle.w0(0, idx=chaotic))[CHI_]
-    dis = chi_o <= 2.0
-    out_band = dis & ~((chi_o >= 1.5) & (chi_o <= 2.5))
-    assert not out_band.any(), f"GPU-chaotic points regular for the oracle outside the band: {chi_o[out_band][:8]}"
-    print(f"{chaotic.size} GPU-chaotic points of {chi.size}: {int(dis.sum())} regular for the oracle, all in the "
-          f"band", flush=True)
+    assert int(np_(cnt).view(np.uint32)[0]) == int(c.sum())
+
+
+def test_c2_class_of_every_point(aw):
+    from paper_1107_4107_amd import workloads as wl
+    full = _golden("c2_slice_1024_T1e5_classes.npz")
+    e = wl.c2()
+    assert (full["eps"], full["n"], full["T"]) == (e.eps, e.nx, e.n_steps)
+    print_case("c2 class of every point")
+    img, _, cls = aw.indicator_image(e, wl.chi_image(e.nx), want_counts=True, want_class=True)
+    chi = np_(img).ravel()
+    c = np_(cls)
+    N = chi.size
+    cls_o = np.unpackbits(full["class_bits"], bitorder="little")[:N].astype(bool)
+    dis = np.flatnonzero((chi > 2.0) != cls_o)
+    band = dict(zip(full["band_idx"].tolist(), full["band_chi"].tolist()))
+    out_band = [int(m) for m in dis if not (m in band and 1.5 <= band[m] <= 2.5)]
+    assert not out_band, f"class disagreements outside the band: {out_band[:8]}"
+    assert dis.size <= 0.005 * N
+    print(f"whole slice: {N} points, {int(cls_o.sum())} chaotic for the oracle, {int(c.sum())} for the GPU, "
+          f"{dis.size} disagreements, all inside the band", flush=True)
 
 
 def test_c5_first_4096_orbits_at_the_full_horizon(aw):
