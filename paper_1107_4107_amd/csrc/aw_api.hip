@@ -929,9 +929,10 @@ aw_status aw_window_density(const aw_ensemble *ens, const double *ic_dev, double
   return AW_OK;
 }
 
-// Validation and enqueue of one histogram over caller keys, with its scratch
-// in the area at `base` (`avail` bytes).  hist2d_layout gives the area the
-// call needs; hist2d_run enqueues nothing unless it fits.
+// One histogram over caller keys: hist2d_check validates the arguments and
+// plans the tiles; hist2d_run enqueues the binning and the reduction with
+// their scratch laid out (layout_of) in the area at `base`, which the caller
+// has sized.
 static aw_status hist2d_check(int64_t N, const double *a_dev, const double *b_dev, double lo0, double hi0, double lo1,
                               double hi1, int32_t W, int32_t H, uint32_t *counts_dev, HistPlan &p) {
   if (N < 0 || N > (int64_t(1) << 31) - 1) return fail(AW_EINVAL, "N out of range");
