@@ -331,3 +331,26 @@ def test_image_workspace_query():
     assert ws([_ens(M=4)], p0)[0] == _abi.AW_EUNSUPPORTED
     assert ws([_ens(ic_kind="box", n_orbits=10)], ImageSpec(kind="hist_p0", W=0, H=8))[0] == _abi.AW_EINVAL
     assert lib.aw_image_workspace(None, 1, None, ctypes.byref(nb)) == _abi.AW_EINVAL
+
+
+def test_graph_create_refuses_bad_requests_on_the_host():
+    """aw_graph_create validates everything before it allocates or captures:
+    a bad descriptor, a missing spec, explicit initial conditions or a bad
+    tuning return an error with no graph handed out."""
+    lib = _abi.load()
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation first
+    imgs = _abi.ptr_array([fake])
+    spec = _abi.AwImageSpec(0, _abi.OUT_CHI, 8, 8, (3, 4), (0.0, 0.0), (1.0, 1.0))
+    cases = [
+        ((_abi.AwEnsemble * 1)(_ens(M=4)), ctypes.byref(spec), None, _abi.AW_EUNSUPPORTED),
+        ((_abi.AwEnsemble * 1)(_ens()), None, None, _abi.AW_EINVAL),
+        ((_abi.AwEnsemble * 1)(_ens(ic_kind="explicit", n_orbits=64)), ctypes.byref(spec), None, _abi.AW_EINVAL),
+        ((_abi.AwEnsemble * 1)(_ens()), ctypes.byref(spec), ctypes.byref(_abi.AwTuning(100, 1, 1, 8, 0, 0)),
+         _abi.AW_EINVAL),
+    ]
+    for ens, sp, tun, status in cases:
+        out = ctypes.c_void_p(0x1234)
+        st = lib.aw_graph_create(ens, 1, sp, imgs, None, None, tun, ctypes.byref(out))
+        assert st == status, (st, status)
+        assert out.value is None
+        assert lib.aw_last_error()
