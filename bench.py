@@ -137,11 +137,15 @@ def oracle_native():
     """The oracle built for this host (gcc -O3 -march=native, contraction off:
     bitwise the results of the portable build), loaded for the timing."""
     global _ORACLE_BUILD
+    import atexit
+    import shutil
     import tempfile
 
     import oracle
     if _ORACLE_BUILD is None:
-        path = os.path.join(tempfile.mkdtemp(prefix="aw_oracle_"), "liboracle_native.so")
+        tmp = tempfile.mkdtemp(prefix="aw_oracle_")
+        atexit.register(shutil.rmtree, tmp, True)
+        path = os.path.join(tmp, "liboracle_native.so")
         oracle.build(force=True, variant="native", out=path)
         oracle.use_build(path)
         _ORACLE_BUILD = "gcc " + " ".join(oracle.CFLAGS + oracle.VARIANT_FLAGS["native"])
