@@ -1,7 +1,8 @@
 // aw_fwd.hip -- ensemble propagation kernels (gfx950, FP64).
 //
 // One orbit per lane (or two, interleaved, for instruction-level
-// parallelism); the state, the tangent vector and the accumulators stay in
+// parallelism; or, for small tangent-free ensembles, one orbit on two lanes);
+// the state, the tangent vector and the accumulators stay in
 // VGPRs for the whole run; initial conditions are generated in registers from
 // the ensemble descriptor, so the only HBM traffic is the coalesced
 // structure-of-arrays store of the per-orbit results (and of the resumable
