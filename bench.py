@@ -67,10 +67,17 @@ def log(*a):
 
 
 def kernel_hash() -> str:
+    """Hash of the propagation kernel's sources with comments and whitespace
+    taken out, so that a counter record stays keyed across edits that cannot
+    change the code."""
+    import re
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
