@@ -76,19 +76,27 @@ __device__ __forceinline__ void rev_drift(Orbit &o, Adjoint &a, double t) {
 // F = (e1 sin u, e1 sin v, e2 cs) and its Jacobian
 //   [[e1 cos u, 0, -2 e2 sin u], [0, e1 cos v, -2 e2 sin v],
 //    [-e2 sin u, -e2 sin v, cs (2 e1 - a2)]],
-// whose transpose acts on Pbar; dF/deps = F / eps.  Sines and cosines from
-// the same table as the forward kick, so the undone kick matches it.
+// whose transpose acts on Pbar; dF/deps = F / eps.  For eps != 0 (EPS0
+// false) a.eb collects eps epsbar = F . Pbar and the kernel divides by eps
+// once at the end; for eps = 0 (EPS0 true) F / eps is formed from w2 = 2 t.
+// Sines and cosines from the same table as the forward kick, so the undone
+// kick matches it.
+template <bool EPS0>
 __device__ __forceinline__ void rev_kick(Orbit &o, Adjoint &a, double a2, double w2,
                                          const double2 *__restrict__ tab) {
   const SinCosT U = sincos_tab(o.x, tab), V = sincos_tab(o.y, tab);
   const ZTerms Z = zterms_tab(o.z, tab);
   const double e1 = a2 * Z.cz2, e2 = a2 * Z.czsz;
-  const double f1 = w2 * Z.cz2, f2 = w2 * Z.czsz;
   const double cs = U.c + V.c;
   const double pub = a.pxb, pvb = a.pyb, pzb = a.pzb;
   const double q = __builtin_fma(U.s, pub, V.s * pvb);   // sin u pu_bar + sin v pv_bar
-  a.eb = __builtin_fma(f1, q, a.eb);
-  a.eb = __builtin_fma(f2 * cs, pzb, a.eb);
+  if constexpr (EPS0) {
+    a.eb = __builtin_fma(w2 * Z.cz2, q, a.eb);
+    a.eb = __builtin_fma((w2 * Z.czsz) * cs, pzb, a.eb);
+  } else {
+    a.eb = __builtin_fma(e1, q, a.eb);
+    a.eb = __builtin_fma(e2 * cs, pzb, a.eb);
+  }
   const double e2p = e2 * pzb;
   a.xb = __builtin_fma(e1 * U.c, pub, __builtin_fma(-U.s, e2p, a.xb));
   a.yb = __builtin_fma(e1 * V.c, pvb, __builtin_fma(-V.s, e2p, a.yb));
@@ -100,7 +108,7 @@ __device__ __forceinline__ void rev_kick(Orbit &o, Adjoint &a, double a2, double
   o.pz = __builtin_fma(-e2, cs, o.pz);
 }
 
-template <int FORM>
+template <int FORM, bool EPS0>
 __device__ __forceinline__ void adj_step_rev(Orbit &o, Adjoint &a, const AdjDesc &d, const double2 *__restrict__ tab) {
   using F = FormPattern<FORM>;
   constexpr int NK = F::NK;
@@ -109,12 +117,12 @@ __device__ __forceinline__ void adj_step_rev(Orbit &o, Adjoint &a, const AdjDesc
 #pragma unroll
     for (int i = NK - 1; i >= 0; --i) {
       const int u = F::kick_idx[i];
-      rev_kick(o, a, d.ka2[u], d.kw2[u], tab);
+      rev_kick<EPS0>(o, a, d.ka2[u], d.kw2[u], tab);
       rev_drift(o, a, d.drift[F::drift_idx[i]]);
     }
   } else {
     rev_drift(o, a, d.drift[0]);
-    rev_kick(o, a, d.ka2[0], d.kw2[0], tab);
+    rev_kick<EPS0>(o, a, d.ka2[0], d.kw2[0], tab);
   }
 }
 
@@ -170,7 +178,7 @@ __device__ __forceinline__ void store_grad(const AdjDesc &d, int64_t n, const Ad
   d.geps[n] = a.eb;
 }
 
-template <int FORM>
+template <int FORM, bool EPS0>
 __global__ __launch_bounds__(512) void k_adj_bwd_rev(AdjDesc d) {
   __shared__ double2 s_tab[AW_TAB_N];
   load_sincos_table(s_tab);
@@ -201,13 +209,14 @@ __global__ __launch_bounds__(512) void k_adj_bwd_rev(AdjDesc d) {
       a.pyb = __builtin_fma(ch, ey, a.pyb);
       a.pzb = __builtin_fma(c, ez, a.pzb);
       sx += ex; sy += ey; sz += ez;
-      adj_step_rev<FORM>(o, a, d, s_tab);              // state now at the start of step g
+      adj_step_rev<FORM, EPS0>(o, a, d, s_tab);              // state now at the start of step g
     }
   }
+  if (!EPS0) a.eb /= d.eps;   // the kicks collected eps epsbar
   store_grad(d, n, a, ch, c, sx, sy, sz);
 }
 
-template <int FORM>
+template <int FORM, bool EPS0>
 __global__ __launch_bounds__(512) void k_adj_bwd(AdjDesc d) {
   __shared__ double2 s_tab[AW_TAB_N];
   load_sincos_table(s_tab);
@@ -245,9 +254,10 @@ __global__ __launch_bounds__(512) void k_adj_bwd(AdjDesc d) {
       a.pyb = __builtin_fma(ch, ey, a.pyb);
       a.pzb = __builtin_fma(c, ez, a.pzb);
       sx += ex; sy += ey; sz += ez;
-      adj_step_rev<FORM>(o, a, d, s_tab);
+      adj_step_rev<FORM, EPS0>(o, a, d, s_tab);
     }
   }
+  if (!EPS0) a.eb /= d.eps;   // the kicks collected eps epsbar
   store_grad(d, n, a, ch, c, sx, sy, sz);
 }
 
@@ -268,14 +278,30 @@ hipError_t launch_adj_forward(const AdjDesc &d, int form, const Tuning &t, hipSt
 
 hipError_t launch_adj_backward_reversible(const AdjDesc &d, int form, const Tuning &t, hipStream_t s) {
   if (d.N <= 0) return hipSuccess;
+  const bool e0 = d.eps == 0.0;
   const int tb = block_for(t, d.N);
   const unsigned blocks = (unsigned)((d.N + tb - 1) / tb);
   switch (form) {
-  case 1: hipLaunchKernelGGL(k_adj_bwd_rev<1>, dim3(blocks), dim3(tb), 0, s, d); break;
-  case 2: hipLaunchKernelGGL(k_adj_bwd_rev<2>, dim3(blocks), dim3(tb), 0, s, d); break;
-  case 4: hipLaunchKernelGGL(k_adj_bwd_rev<4>, dim3(blocks), dim3(tb), 0, s, d); break;
-  case 6: hipLaunchKernelGGL(k_adj_bwd_rev<6>, dim3(blocks), dim3(tb), 0, s, d); break;
-  case 7: hipLaunchKernelGGL(k_adj_bwd_rev<7>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 1:
+    if (e0) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adj_bwd_rev<1, true>), dim3(blocks), dim3(tb), 0, s, d);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adj_bwd_rev<1, false>), dim3(blocks), dim3(tb), 0, s, d);
+    break;
+  case 2:
+    if (e0) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adj_bwd_rev<2, true>), dim3(blocks), dim3(tb), 0, s, d);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adj_bwd_rev<2, false>), dim3(blocks), dim3(tb), 0, s, d);
+    break;
+  case 4:
+    if (e0) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adj_bwd_rev<4, true>), dim3(blocks), dim3(tb), 0, s, d);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adj_bwd_rev<4, false>), dim3(blocks), dim3(tb), 0, s, d);
+    break;
+  case 6:
+    if (e0) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adj_bwd_rev<6, true>), dim3(blocks), dim3(tb), 0, s, d);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adj_bwd_rev<6, false>), dim3(blocks), dim3(tb), 0, s, d);
+    break;
+  case 7:
+    if (e0) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adj_bwd_rev<7, true>), dim3(blocks), dim3(tb), 0, s, d);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adj_bwd_rev<7, false>), dim3(blocks), dim3(tb), 0, s, d);
+    break;
   default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -283,14 +309,30 @@ hipError_t launch_adj_backward_reversible(const AdjDesc &d, int form, const Tuni
 
 hipError_t launch_adj_backward(const AdjDesc &d, int form, const Tuning &t, hipStream_t s) {
   if (d.N <= 0) return hipSuccess;
+  const bool e0 = d.eps == 0.0;
   const int tb = block_for(t, d.N);
   const unsigned blocks = (unsigned)((d.N + tb - 1) / tb);
   switch (form) {
-  case 1: hipLaunchKernelGGL(k_adj_bwd<1>, dim3(blocks), dim3(tb), 0, s, d); break;
-  case 2: hipLaunchKernelGGL(k_adj_bwd<2>, dim3(blocks), dim3(tb), 0, s, d); break;
-  case 4: hipLaunchKernelGGL(k_adj_bwd<4>, dim3(blocks), dim3(tb), 0, s, d); break;
-  case 6: hipLaunchKernelGGL(k_adj_bwd<6>, dim3(blocks), dim3(tb), 0, s, d); break;
-  case 7: hipLaunchKernelGGL(k_adj_bwd<7>, dim3(blocks), dim3(tb), 0, s, d); break;
+  case 1:
+    if (e0) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adj_bwd<1, true>), dim3(blocks), dim3(tb), 0, s, d);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adj_bwd<1, false>), dim3(blocks), dim3(tb), 0, s, d);
+    break;
+  case 2:
+    if (e0) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adj_bwd<2, true>), dim3(blocks), dim3(tb), 0, s, d);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adj_bwd<2, false>), dim3(blocks), dim3(tb), 0, s, d);
+    break;
+  case 4:
+    if (e0) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adj_bwd<4, true>), dim3(blocks), dim3(tb), 0, s, d);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adj_bwd<4, false>), dim3(blocks), dim3(tb), 0, s, d);
+    break;
+  case 6:
+    if (e0) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adj_bwd<6, true>), dim3(blocks), dim3(tb), 0, s, d);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adj_bwd<6, false>), dim3(blocks), dim3(tb), 0, s, d);
+    break;
+  case 7:
+    if (e0) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adj_bwd<7, true>), dim3(blocks), dim3(tb), 0, s, d);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adj_bwd<7, false>), dim3(blocks), dim3(tb), 0, s, d);
+    break;
   default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -124,15 +124,19 @@ __device__ __forceinline__ void rev_kick2(Orbit &o, Adjoint2 &a, double a2, doub
   const ZTerms Z = zterms_tab(o.z, tab);
   const double e1 = a2 * Z.cz2, e2 = a2 * Z.czsz, g = __builtin_fma(2.0, e1, -a2);
   const double cs = U.c + V.c;
+  // F, the kick's increment of P.
+  const double fu = e1 * U.s, fv = e1 * V.s, fz = e2 * cs;
   const double du = o.dx, dv = o.dy, dz = o.dz;
   const double pub = a.pxb, pvb = a.pyb, pzb = a.pzb;
   const double dpub = a.dpxb, dpvb = a.dpyb, dpzb = a.dpzb;
-  // M.
-  const double muu = e1 * U.c, mvv = e1 * V.c, muz = -2.0 * e2 * U.s, mvz = -2.0 * e2 * V.s;
+  // M; its (u, z) and (v, z) entries are 2 mzu and 2 mzv, and every product
+  // with them is formed as mzu (2 dz) and the like, exact rescalings by 2.
+  const double muu = e1 * U.c, mvv = e1 * V.c;
   const double mzu = -e2 * U.s, mzv = -e2 * V.s, mzz = cs * g;
+  const double dz2 = dz + dz;
   // M dX: the tangent kick of the forward step.
-  const double mdu = __builtin_fma(muu, du, muz * dz);
-  const double mdv = __builtin_fma(mvv, dv, mvz * dz);
+  const double mdu = __builtin_fma(muu, du, mzu * dz2);
+  const double mdv = __builtin_fma(mvv, dv, mzv * dz2);
   const double mdz = __builtin_fma(mzu, du, __builtin_fma(mzv, dv, mzz * dz));
 
   if constexpr (EPS0) {
@@ -148,10 +152,11 @@ __device__ __forceinline__ void rev_kick2(Orbit &o, Adjoint2 &a, double a2, doub
     eb = __builtin_fma(__builtin_fma(wzu, du, __builtin_fma(wzv, dv, wzz * dz)), dpzb, eb);
     a.eb = eb;
   } else {
-    // eps epsbar.
+    // eps epsbar: F . Pbar + (M dX) . dPbar.
     double eb = a.eb;
-    eb = __builtin_fma(e1, __builtin_fma(U.s, pub, V.s * pvb), eb);
-    eb = __builtin_fma(e2 * cs, pzb, eb);
+    eb = __builtin_fma(fu, pub, eb);
+    eb = __builtin_fma(fv, pvb, eb);
+    eb = __builtin_fma(fz, pzb, eb);
     eb = __builtin_fma(mdu, dpub, eb);
     eb = __builtin_fma(mdv, dpvb, eb);
     eb = __builtin_fma(mdz, dpzb, eb);
@@ -160,18 +165,19 @@ __device__ __forceinline__ void rev_kick2(Orbit &o, Adjoint2 &a, double a2, doub
 
   // Xbar += M^T Pbar + S.
   const double e2cu = e2 * U.c, e2cv = e2 * V.c, gsu = g * U.s, gsv = g * V.s;
-  const double Au = __builtin_fma(e1 * U.s, du, 2.0 * e2cu * dz);
-  const double Av = __builtin_fma(e1 * V.s, dv, 2.0 * e2cv * dz);
+  const double Au = __builtin_fma(fu, du, e2cu * dz2);
+  const double Av = __builtin_fma(fv, dv, e2cv * dz2);
   const double Bu = __builtin_fma(e2cu, du, gsu * dz);
   const double Bv = __builtin_fma(e2cv, dv, gsv * dz);
-  const double Cz = __builtin_fma(gsu, du, __builtin_fma(gsv, dv, 4.0 * e2 * cs * dz));
+  const double Cz = __builtin_fma(gsu, du, __builtin_fma(gsv, dv, fz * (dz2 + dz2)));
   double xb = a.xb, yb = a.yb, zb = a.zb;
   xb = __builtin_fma(muu, pub, __builtin_fma(mzu, pzb, xb));
   yb = __builtin_fma(mvv, pvb, __builtin_fma(mzv, pzb, yb));
-  zb = __builtin_fma(muz, pub, __builtin_fma(mvz, pvb, __builtin_fma(mzz, pzb, zb)));
   xb = __builtin_fma(-dpub, Au, __builtin_fma(-dpzb, Bu, xb));
   yb = __builtin_fma(-dpvb, Av, __builtin_fma(-dpzb, Bv, yb));
-  zb = __builtin_fma(-2.0 * dpub, Bu, __builtin_fma(-2.0 * dpvb, Bv, __builtin_fma(-dpzb, Cz, zb)));
+  // The z row: the terms with a factor 2 summed first, then doubled.
+  const double zh = __builtin_fma(mzu, pub, __builtin_fma(mzv, pvb, __builtin_fma(-dpub, Bu, -(dpvb * Bv))));
+  zb = __builtin_fma(2.0, zh, __builtin_fma(mzz, pzb, __builtin_fma(-dpzb, Cz, zb)));
   a.xb = xb;
   a.yb = yb;
   a.zb = zb;
@@ -179,7 +185,7 @@ __device__ __forceinline__ void rev_kick2(Orbit &o, Adjoint2 &a, double a2, doub
   // dXbar += M^T dPbar.
   a.dxb = __builtin_fma(muu, dpub, __builtin_fma(mzu, dpzb, a.dxb));
   a.dyb = __builtin_fma(mvv, dpvb, __builtin_fma(mzv, dpzb, a.dyb));
-  a.dzb = __builtin_fma(muz, dpub, __builtin_fma(mvz, dpvb, __builtin_fma(mzz, dpzb, a.dzb)));
+  a.dzb = __builtin_fma(2.0, __builtin_fma(mzu, dpub, mzv * dpvb), __builtin_fma(mzz, dpzb, a.dzb));
 
   // Undo the kick: dP -= M dX, P -= F.
   o.dpx -= mdu;
