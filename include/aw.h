@@ -301,10 +301,13 @@ aw_status aw_histogram2d(int64_t N, const double *a_dev, const double *b_dev, co
  * runtime may place the array in device memory then); later calls change
  * nothing in the device's memory use.  Scratch a
  * call needs, each part rounded up to 256 bytes: 4 N (bins) + 2 N (sorted
- * local bins), with values (v_dev != NULL) + 8 N + 8 N, plus 4 T G + 4 G +
- * 4 (2 T + 1) of tile tables, where T = ceil(W/32) ceil(H/32) and
- * G = ceil(N/8192) (N = 0 counts as 1); about 2.9e6 items with values or
- * 1.1e7 without.  A larger request returns AW_EWORKSPACE and enqueues nothing.
+ * local bins), with values (v_dev != NULL) + 8 N (sorted values); tile tables
+ * of 4 T G + 4 G + 4 (2 T + 1) + 8 (T + 1) + 4 (T + B) bytes; and partial
+ * tiles of 8192 B bytes, with values + 16384 B; where T = ceil(W/32)
+ * ceil(H/32), G = ceil(N/8192) and B = min(ceil(N/16384), max(ceil(T/2),
+ * 256)) (N = 0 counts as 1).  For a 512 x 512 image that allows about
+ * 4.3e6 items with values or 1.06e7 without.  A larger request returns
+ * AW_EWORKSPACE and enqueues nothing.
  * Every call on a GPU shares that GPU's array, and the array keeps the last
  * call's contents (each call writes every part it reads before reading it):
  * calls on one stream are ordered and safe, but calls that overlap on one

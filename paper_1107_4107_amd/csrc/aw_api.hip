@@ -49,6 +49,8 @@ struct Layout {
   // byte offsets into the area
   size_t bins = 0, vals = 0;                               // per orbit, every ensemble (histograms)
   size_t block_counts = 0, block_dropped = 0, tile_start = 0;
+  size_t chunk_first = 0, part_first = 0, chunk_tile = 0;  // accumulation chunks
+  size_t part_counts = 0, part_sums = 0;                   // partial tiles
   size_t sorted_local = 0, sorted_val = 0;                 // the largest single reduction
   size_t descs = 0, items = 0, head = 0;                   // tables of a batched launch
   size_t total = 0;
@@ -56,17 +58,21 @@ struct Layout {
 
 // hist: histogram images over n_all orbits in all, of which one reduction
 // sorts at most n_max items into n_tiles tiles; vals: the items carry values;
-// n_descs, n_items: tables of a batched launch (0 for none).
-constexpr Layout layout_of(bool hist, bool vals, int64_t n_all, int64_t n_max, int64_t n_tiles, size_t n_descs,
-                           size_t n_items) {
+// vals_here: the items' values are kept in the area (written by the
+// propagation), not read from the caller; n_descs, n_items: tables of a
+// batched launch (0 for none).
+constexpr Layout layout_of(bool hist, bool vals, bool vals_here, int64_t n_all, int64_t n_max, int64_t n_tiles,
+                           size_t n_descs, size_t n_items) {
   Layout l{};
   size_t o = 0;
   if (hist) {
     const size_t na = (size_t)(n_all > 0 ? n_all : 1), nm = (size_t)(n_max > 0 ? n_max : 1);
     const size_t G = (nm + HIST_ITEMS_PER_BLOCK - 1) / HIST_ITEMS_PER_BLOCK;
+    // partial tiles: fewer than 2 ceil(N / chunk) <= 2 acc_bound(n_max, n_tiles) of them
+    const size_t parts = 2 * (size_t)acc_bound((int64_t)nm, n_tiles);
     l.bins = o;
     o += align_up(sizeof(uint32_t) * na);
-    if (vals) {
+    if (vals && vals_here) {
       l.vals = o;
       o += align_up(sizeof(double) * na);
     }
@@ -76,6 +82,18 @@ constexpr Layout layout_of(bool hist, bool vals, int64_t n_all, int64_t n_max, i
     o += align_up(sizeof(uint32_t) * G);
     l.tile_start = o;
     o += align_up(sizeof(uint32_t) * (2 * (size_t)n_tiles + 1));
+    l.chunk_first = o;
+    o += align_up(sizeof(uint32_t) * ((size_t)n_tiles + 1));
+    l.part_first = o;
+    o += align_up(sizeof(uint32_t) * ((size_t)n_tiles + 1));
+    l.chunk_tile = o;
+    o += align_up(sizeof(uint32_t) * ((size_t)n_tiles + parts / 2));
+    l.part_counts = o;
+    o += align_up(sizeof(uint32_t) * parts * TILE_BINS);
+    if (vals) {
+      l.part_sums = o;
+      o += align_up(sizeof(double) * parts * TILE_BINS);
+    }
     l.sorted_local = o;
     o += align_up(sizeof(uint16_t) * nm);
     if (vals) {
@@ -101,6 +119,11 @@ HistScratch hist_scratch_at(char *base, const Layout &l, bool vals, int64_t n_ti
   w.block_dropped = (uint32_t *)(base + l.block_dropped);
   w.tile_start = (uint32_t *)(base + l.tile_start);
   w.tile_total = w.tile_start + n_tiles + 1;
+  w.chunk_first = (uint32_t *)(base + l.chunk_first);
+  w.part_first = (uint32_t *)(base + l.part_first);
+  w.chunk_tile = (uint32_t *)(base + l.chunk_tile);
+  w.part_counts = (uint32_t *)(base + l.part_counts);
+  w.part_sums = vals ? (double *)(base + l.part_sums) : nullptr;
   w.sorted_local = (uint16_t *)(base + l.sorted_local);
   w.sorted_val = vals ? (double *)(base + l.sorted_val) : nullptr;
   return w;
@@ -618,7 +641,7 @@ aw_status prepare_image(const aw_ensemble *ens, int32_t n_ens, const aw_image_sp
   if (c.hist) c.n_tiles = hist_plan(n_max, spec->W, spec->H).n_tiles;
   if (c.batched) c.items = make_items(c.descs, t).items;
   const int64_t n_all = c.batched ? c.off[n_ens] : n_max;
-  c.lay = layout_of(c.hist, c.vals, n_all, n_max, c.n_tiles, c.batched ? c.descs.size() : 0,
+  c.lay = layout_of(c.hist, c.vals, true, n_all, n_max, c.n_tiles, c.batched ? c.descs.size() : 0,
                     c.batched ? c.items.size() : 0);
   return AW_OK;
 }
@@ -788,7 +811,7 @@ aw_status aw_image_workspace(const aw_ensemble *ens, int32_t n_ens, const aw_ima
     }
     std::vector<FwdDesc> descs(n_ens);
     for (int e = 0; e < n_ens; ++e) descs[e] = make_desc(ens[e], nullptr, Tuning{});
-    *bytes = layout_of(false, false, 0, 0, 0, descs.size(), make_items(descs, Tuning{}).items.size()).total;
+    *bytes = layout_of(false, false, false, 0, 0, 0, descs.size(), make_items(descs, Tuning{}).items.size()).total;
     return AW_OK;
   }
   std::vector<double> dummy(n_ens, 0.0);
@@ -840,7 +863,7 @@ aw_status aw_map_ensemble(const aw_ensemble *ens, int32_t n_ens, const double *c
   if (n_ens == 1) return launch_one(descs[0], t, form, tan, s);
   BatchTables b = make_items(descs, t);
   if (b.items.empty()) return AW_OK;
-  const Layout l = layout_of(false, false, 0, 0, 0, descs.size(), b.items.size());
+  const Layout l = layout_of(false, false, false, 0, 0, 0, descs.size(), b.items.size());
   std::lock_guard<std::mutex> lk(g_mu);
   StreamScratch &sc = stream_scratch(s);
   if ((st = reserve_area(sc, l.total)) != AW_OK) return st;
@@ -910,7 +933,7 @@ aw_status aw_window_density(const aw_ensemble *ens, const double *ic_dev, double
   d.carry = carry_dev;
   hipStream_t s = (hipStream_t)stream;
   const HistPlan p = hist_plan(d.N, spec->W, spec->H);
-  const Layout l = layout_of(true, false, d.N, d.N, p.n_tiles, 0, 0);
+  const Layout l = layout_of(true, false, false, d.N, d.N, p.n_tiles, 0, 0);
   std::lock_guard<std::mutex> lk(g_mu);
   StreamScratch &sc = stream_scratch(s);
   if ((st = reserve_area(sc, l.total)) != AW_OK) return st;
@@ -950,15 +973,12 @@ static aw_status hist2d_run(char *base, const Layout &l, const HistPlan &p, int6
                             const double *b_dev, const double *v_dev, double lo0, double hi0, double lo1, double hi1,
                             int32_t W, int32_t H, int32_t closed_upper, uint32_t *counts_dev, double *sums_dev,
                             uint64_t *dropped_dev, hipStream_t s) {
-  const bool with_v = v_dev != nullptr;
-  const HistScratch w = hist_scratch_at(base, l, with_v, p.n_tiles);
+  const HistScratch w = hist_scratch_at(base, l, v_dev != nullptr, p.n_tiles);
   uint32_t *bins = (uint32_t *)(base + l.bins);
-  double *vals = with_v ? (double *)(base + l.vals) : nullptr;
   hipError_t e;
-  if ((e = launch_hist_bins(N, a_dev, b_dev, v_dev, lo0, hi0, lo1, hi1, W, H, closed_upper, bins, vals, s)) !=
-      hipSuccess)
+  if ((e = launch_hist_bins(N, a_dev, b_dev, lo0, hi0, lo1, hi1, W, H, closed_upper, bins, s)) != hipSuccess)
     return hip_fail(e, "histogram bins");
-  if ((e = launch_hist_reduce(N, bins, vals, p, w, 0, 1.0, counts_dev, sums_dev, dropped_dev, s)) != hipSuccess)
+  if ((e = launch_hist_reduce(N, bins, v_dev, p, w, 0, 1.0, counts_dev, sums_dev, dropped_dev, s)) != hipSuccess)
     return hip_fail(e, "histogram reduction");
   return AW_OK;
 }
@@ -970,7 +990,7 @@ aw_status aw_histogram2d(int64_t N, const double *a_dev, const double *b_dev, co
   aw_status st = hist2d_check(N, a_dev, b_dev, lo0, hi0, lo1, hi1, W, H, counts_dev, p);
   if (st != AW_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  const Layout l = layout_of(true, v_dev != nullptr, N, N, p.n_tiles, 0, 0);
+  const Layout l = layout_of(true, v_dev != nullptr, false, N, N, p.n_tiles, 0, 0);
   std::lock_guard<std::mutex> lk(g_mu);
   StreamScratch &sc = stream_scratch(s);
   if ((st = reserve_area(sc, l.total)) != AW_OK) return st;
@@ -985,7 +1005,7 @@ aw_status aw_histogram2d_noalloc(int64_t N, const double *a_dev, const double *b
   HistPlan p;
   aw_status st = hist2d_check(N, a_dev, b_dev, lo0, hi0, lo1, hi1, W, H, counts_dev, p);
   if (st != AW_OK) return st;
-  const Layout l = layout_of(true, v_dev != nullptr, N, N, p.n_tiles, 0, 0);
+  const Layout l = layout_of(true, v_dev != nullptr, false, N, N, p.n_tiles, 0, 0);
   if (l.total > (size_t)AW_NOALLOC_SCRATCH_BYTES)
     return fail(AW_EWORKSPACE, "aw_histogram2d_noalloc: %lld items into %d x %d bins need %zu bytes of scratch, "
                                "more than its fixed %zu", (long long)N, W, H, l.total,

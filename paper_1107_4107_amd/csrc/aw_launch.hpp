@@ -48,21 +48,25 @@ void step_op_counts(int form, bool tan, int64_t *fma, int64_t *mul, int64_t *add
 struct HistPlan {
   int W = 0, H = 0, tiles_x = 0, n_tiles = 0;
   int32_t G = 0;
-  size_t bytes_block_counts = 0, bytes_block_dropped = 0, bytes_tile_start = 0;
-  size_t bytes_sorted_local = 0, bytes_sorted_val = 0;
+  int64_t chunk = 0;       // items per accumulation chunk
+  int64_t max_chunks = 0;  // accumulation workgroups launched: n_tiles + ceil(N / chunk)
 };
 struct HistScratch {
   uint32_t *block_counts = nullptr;
   uint32_t *block_dropped = nullptr;
-  uint32_t *tile_start = nullptr;  // n_tiles + 1 entries
-  uint32_t *tile_total = nullptr;  // n_tiles entries (in the same buffer, after tile_start)
+  uint32_t *tile_start = nullptr;   // n_tiles + 1 entries
+  uint32_t *tile_total = nullptr;   // n_tiles entries (in the same buffer, after tile_start)
+  uint32_t *chunk_first = nullptr;  // n_tiles + 1: first chunk of each tile; [n_tiles] = chunks in all
+  uint32_t *part_first = nullptr;   // n_tiles + 1: first partial-tile slot of each tile of several chunks
+  uint32_t *chunk_tile = nullptr;   // the tile of each chunk
+  uint32_t *part_counts = nullptr;  // [slots][TILE_BINS] partial counts
+  double *part_sums = nullptr;      // [slots][TILE_BINS] partial sums (with values only)
   uint16_t *sorted_local = nullptr;
   double *sorted_val = nullptr;
 };
 HistPlan hist_plan(int64_t N, int W, int H);
-hipError_t launch_hist_bins(int64_t N, const double *a, const double *b, const double *v, double lo0,
-                            double hi0, double lo1, double hi1, int W, int H, int closed, uint32_t *bins,
-                            double *vals, hipStream_t s);
+hipError_t launch_hist_bins(int64_t N, const double *a, const double *b, double lo0, double hi0, double lo1,
+                            double hi1, int W, int H, int closed, uint32_t *bins, hipStream_t s);
 hipError_t launch_vdir_keys(int64_t N, const double *V, double *phi, double *mu, hipStream_t s);
 // accumulate != 0: counts are added to counts_out instead of written.
 hipError_t launch_hist_reduce(int64_t N, const uint32_t *bins, const double *vals, const HistPlan &p,

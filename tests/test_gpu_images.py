@@ -60,6 +60,60 @@ def test_histogram2d_matches_oracle(aw, N, W, H_):
     assert not bad.any(), f"sums: {bad.sum()} bins beyond 1e-12 of their sum of |v|; worst {err[bad].max()}"
 
 
+def _crowded_keys(rng, N, W, H_, tiles):
+    """Keys with 90% of the items spread over the given 32 x 32-bin tiles
+    (equal shares) and the rest uniform over the image and a little beyond."""
+    a = rng.uniform(-0.3, 6.6, N)
+    b = rng.uniform(-0.2, 6.5, N)
+    crowd = np.nonzero(rng.random(N) < 0.9)[0]
+    which = rng.integers(0, len(tiles), crowd.size)
+    wa, wb = TWO_PI / W, TWO_PI / H_
+    for k, (tx, ty) in enumerate(tiles):
+        m = crowd[which == k]
+        a[m] = (tx * 32 + rng.uniform(0, min(32, W - tx * 32), m.size)) * wa
+        b[m] = (ty * 32 + rng.uniform(0, min(32, H_ - ty * 32), m.size)) * wb
+    return a, b
+
+
+@pytest.mark.parametrize("N,W,H_,tiles", [(2_000_003, 512, 512, [(5, 3)]),
+                                          (40_000, 64, 64, [(0, 0), (1, 1)]),
+                                          (16_384, 32, 32, [(0, 0)]), (16_385, 32, 32, [(0, 0)]),
+                                          (1_000_000, 1024, 512, [(0, 0), (31, 15), (7, 9), (8, 9), (20, 2)])])
+def test_histogram2d_crowded_tiles_match_oracle(aw, N, W, H_, tiles):
+    """Items crowding into a few tiles: the accumulation splits each tile's
+    range into chunks of at least 16384 items, one workgroup each, and adds
+    the partial tiles of a tile in chunk order.  One tile of 1.8e6 items
+    (about 110 chunks), two of about 2e4 (two chunks each), one tile of
+    exactly one chunk and of one chunk plus an item, five crowded tiles of
+    a large image.  Counts bitwise, sums within 1e-12 of their sum of |v|."""
+    print_case("hist2d crowded", N, W, H_, len(tiles))
+    rng = np.random.default_rng(N + 7 * W)
+    a, b = _crowded_keys(rng, N, W, H_, tiles)
+    if N == 16_384 or N == 16_385:   # every item in the single tile
+        a = rng.uniform(0.0, TWO_PI, N)
+        b = rng.uniform(0.0, TWO_PI, N)
+        a[a >= TWO_PI] = 0.0
+        b[b >= TWO_PI] = 0.0
+    v = rng.normal(size=N)
+    c, s, d = aw.histogram2d(tensor(a), tensor(b), tensor(v), (0, 0), (TWO_PI, TWO_PI), W, H_)
+    co, so, do = oracle.hist2d(a, b, v, (0, 0), (TWO_PI, TWO_PI), W, H_)
+    per_tile = np.add.reduceat(np.add.reduceat(co.astype(np.int64), np.arange(0, H_, 32), axis=0),
+                               np.arange(0, W, 32), axis=1)
+    print(f"largest tile {per_tile.max()} items", flush=True)
+    if N > 16_384:
+        assert per_tile.max() > 16_384                # the case has a tile of several chunks
+    np.testing.assert_array_equal(np_(c).view(np.uint32), co)
+    assert int(np_(d)[0]) == do
+    _, sabs, _ = oracle.hist2d(a, b, np.abs(v), (0, 0), (TWO_PI, TWO_PI), W, H_)
+    err = np.abs(np_(s) - so)
+    bad = ~(err <= 1e-12 * np.maximum(sabs, 1e-300))
+    assert not bad.any(), f"sums: {bad.sum()} bins beyond 1e-12 of their sum of |v|; worst {err[bad].max()}"
+    c2, s2, d2 = aw.histogram2d(tensor(a), tensor(b), None, (0, 0), (TWO_PI, TWO_PI), W, H_)
+    assert s2 is None
+    np.testing.assert_array_equal(np_(c2).view(np.uint32), co)
+    assert int(np_(d2)[0]) == do
+
+
 def test_histogram2d_without_values_and_closed_edges(aw):
     print_case("hist2d closed")
     a = np.array([-np.pi, np.pi, 0.0, np.pi, 3.0])
@@ -115,6 +169,31 @@ def test_momentum_drift_image(aw):
     ic = oracle.ic_box(e.box_lo, e.box_hi, e.seed_ic, N)
     out = oracle.ensemble("s6", e.eps, H, T, ic, oracle.w0(e.seed_tangent, N), nthreads=0)
     mean_o, cnt_o, drop_o = oracle.hist_p0(ic, out[6], (3, 4), (0, 0), (TWO_PI, TWO_PI), 512, 512)
+    np.testing.assert_array_equal(np_(cnt).view(np.uint32), cnt_o)
+    assert drop_o == 0
+    assert_close(np_(img), mean_o, 1e-9, floor=1e-12, what="mean dP2")
+
+
+def test_momentum_drift_image_crowded(aw):
+    """HIST_P0 with the initial momenta in a narrow box, so that a few tiles
+    hold every item and the mean image goes through the chunk merge: counts
+    bitwise, per-bin means of |P_T - P_0|^2 to 1e-9 at T = 50."""
+    import dataclasses
+    print_case("hist p0 crowded")
+    from paper_1107_4107_amd import workloads
+    N, T = 200_003, 50
+    e = _box(aw, N, T)
+    lo, hi = list(e.box_lo), list(e.box_hi)
+    lo[3], hi[3], lo[4], hi[4] = 1.0, 1.2, 2.0, 2.2
+    e = dataclasses.replace(e, box_lo=lo, box_hi=hi)
+    spec = workloads.c5_p0_image()
+    img, cnt, _ = aw.indicator_image(e, spec)
+    ic = oracle.ic_box(e.box_lo, e.box_hi, e.seed_ic, N)
+    out = oracle.ensemble("s6", e.eps, H, T, ic, oracle.w0(e.seed_tangent, N), nthreads=0)
+    mean_o, cnt_o, drop_o = oracle.hist_p0(ic, out[6], (3, 4), (0, 0), (TWO_PI, TWO_PI), 512, 512)
+    per_tile = np.add.reduceat(np.add.reduceat(cnt_o.astype(np.int64), np.arange(0, 512, 32), axis=0),
+                               np.arange(0, 512, 32), axis=1)
+    assert per_tile.max() > 2 * 16_384
     np.testing.assert_array_equal(np_(cnt).view(np.uint32), cnt_o)
     assert drop_o == 0
     assert_close(np_(img), mean_o, 1e-9, floor=1e-12, what="mean dP2")

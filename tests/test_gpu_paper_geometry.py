@@ -191,3 +191,38 @@ def test_window_density_accumulates_over_windows(aw):
     print(f"window counts: {c1.sum()} binned, |diff| sum {diff.sum()}, edge items {amb}", flush=True)
     assert c1.sum() > 0.5 * 4 * N
     assert diff.sum() <= 2 * amb + 4
+
+
+def test_window_density_merges_crowded_tiles(aw):
+    """The window density of 2e5 cloud orbits on a 64 x 64 zoom (four tiles):
+    a window puts more items into a tile than one accumulation chunk holds, so
+    its counts go through the chunk merge, and they are added to a buffer that
+    already holds counts.  Against the oracle's window velocities binned the
+    same way, with the edge-item allowance of the test above."""
+    import torch
+    print_case("window density, crowded tiles")
+    e = _cloud(aw, 200_000, 200)
+    w = math.pi / 4
+    lo, hi = (w - 0.6, -0.6), (w + 0.6, 0.6)
+    spec = aw.ImageSpec(kind="hist_vdir", W=64, H=64, lo=lo, hi=hi)
+    N = e.n_orbits
+    carry = torch.empty((aw.NCARRY, N), dtype=torch.float64, device="cuda")
+    base = np.random.default_rng(5).integers(0, 1000, (64, 64)).astype(np.int32)
+    cnt = torch.as_tensor(base).cuda()
+    aw.window_density(e, carry, 0, 2, 100, spec, cnt)
+    c1 = np_(cnt).astype(np.int64) - base
+    V = oracle.window_velocities("s6", 1.0, H, _oracle_cloud(e), 2, 100)
+    co = np.zeros((64, 64), dtype=np.int64)
+    amb, crowded = 0, 0
+    for k in range(2):
+        phi, mu = oracle.vdir_keys(V[k])
+        ck, _, _ = oracle.hist2d(phi, mu, np.zeros(N), lo, hi, 64, 64, closed_upper=True)
+        co += ck
+        crowded = max(crowded, int(ck.reshape(2, 32, 2, 32).sum(axis=(1, 3)).max()))
+        fi = (phi - lo[0]) / 1.2 * 64
+        fj = (mu - lo[1]) / 1.2 * 64
+        amb += int(np.sum((np.abs(fi - np.round(fi)) < 1e-4) | (np.abs(fj - np.round(fj)) < 1e-4)))
+    diff = np.abs(c1 - co)
+    print(f"largest tile of a window {crowded} items; |diff| sum {diff.sum()}, edge items {amb}", flush=True)
+    assert crowded > 16_384
+    assert diff.sum() <= 2 * amb + 4
