@@ -77,13 +77,18 @@ __device__ __forceinline__ void tile_of(uint32_t bin, const TileGeom &g, int &ti
   local = (j % TILE_H) * TILE_W + (i % TILE_W);
 }
 
+// Both per-block kernels hold one LDS word per tile, sized at launch to the
+// image (n_tiles + 1 words), so that a small image leaves room for more
+// blocks per CU.
+extern __shared__ uint32_t tile_words[];
+
 // 1. Per-block tile counts; dropped items per block.
 __global__ __launch_bounds__(HIST_BLOCK) void k_tile_count(int64_t N, const uint32_t *__restrict__ bins,
                                                            TileGeom g, int32_t G,
                                                            uint32_t *__restrict__ block_counts,
                                                            uint32_t *__restrict__ block_dropped) {
-  __shared__ uint32_t cnt[MAX_TILES];
-  __shared__ uint32_t drop;
+  uint32_t *cnt = tile_words;
+  uint32_t &drop = tile_words[g.n_tiles];
   for (int t = threadIdx.x; t < g.n_tiles; t += blockDim.x) cnt[t] = 0u;
   if (threadIdx.x == 0) drop = 0u;
   __syncthreads();
@@ -235,7 +240,7 @@ __global__ __launch_bounds__(HIST_BLOCK) void k_tile_scatter(int64_t N, const ui
                                                              const uint32_t *__restrict__ tile_start,
                                                              uint16_t *__restrict__ sorted_local,
                                                              double *__restrict__ sorted_val) {
-  __shared__ uint32_t cur[MAX_TILES];
+  uint32_t *cur = tile_words;
   for (int t = threadIdx.x; t < g.n_tiles; t += blockDim.x)
     cur[t] = tile_start[t] + offsets[(int64_t)t * G + blockIdx.x];
   __syncthreads();
@@ -489,8 +494,9 @@ hipError_t launch_hist_reduce(int64_t N, const uint32_t *bins, const double *val
                               const HistScratch &w, int mode, double norm, uint32_t *counts_out,
                               double *f_out, uint64_t *dropped_out, hipStream_t s, int accumulate) {
   TileGeom g{p.W, p.H, p.tiles_x, p.n_tiles};
+  const unsigned tile_lds = (unsigned)(sizeof(uint32_t) * ((size_t)p.n_tiles + 1));  // <= 32 KB + 4 B
   if (N > 0) {
-    hipLaunchKernelGGL(k_tile_count, dim3((unsigned)p.G), dim3(HIST_BLOCK), 0, s, N, bins, g, p.G,
+    hipLaunchKernelGGL(k_tile_count, dim3((unsigned)p.G), dim3(HIST_BLOCK), tile_lds, s, N, bins, g, p.G,
                        w.block_counts, w.block_dropped);
   } else {
     hipError_t e = launch_zero_u32(w.block_counts, p.n_tiles * p.G, s);
@@ -506,7 +512,7 @@ hipError_t launch_hist_reduce(int64_t N, const uint32_t *bins, const double *val
     hipLaunchKernelGGL(k_tile_scatter_staged, dim3((unsigned)p.G), dim3(STAGE_BLOCK), 0, s, N, bins, vals, g, p.G,
                        w.block_counts, w.tile_start, w.sorted_local, vals ? w.sorted_val : nullptr);
   else if (N > 0)
-    hipLaunchKernelGGL(k_tile_scatter, dim3((unsigned)p.G), dim3(HIST_BLOCK), 0, s, N, bins, vals, g, p.G,
+    hipLaunchKernelGGL(k_tile_scatter, dim3((unsigned)p.G), dim3(HIST_BLOCK), tile_lds, s, N, bins, vals, g, p.G,
                        w.block_counts, w.tile_start, w.sorted_local, vals ? w.sorted_val : nullptr);
   double *psums = vals ? w.part_sums : nullptr;
   hipLaunchKernelGGL(k_tile_accum, dim3((unsigned)p.max_chunks), dim3(ACC_BLOCK), 0, s, w.tile_start,
