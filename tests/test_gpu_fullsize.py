@@ -74,3 +74,52 @@ def test_eps_sweep_batch_full_size():
     assert len(ill) <= max(1, n_reg // 1000), ill
     frac = class_agreement(np.concatenate(chi_g), np.concatenate(chi_o))
     print(f"class agreement {frac:.5f} over {sum(c.size for c in chi_g)} sampled orbits, {n_reg} regular", flush=True)
+
+
+def test_largest_ensemble_indexing():
+    """3e8 orbits of the uniform box ensemble (the c5 distribution), two S6
+    steps with the tangent map: the structure-of-arrays outputs hold their
+    rows at offsets r N beyond 2^31 elements, so every 64-bit index of the
+    propagation, the initial-condition draw and the histogram is exercised.
+    The first, the last and 62 spread orbits against the oracle (at two
+    steps the outputs are fixed to rounding: 1e-9 relative); the histogram
+    of all 3e8 initial momenta bitwise against the oracle's, its value sums
+    against the per-orbit values."""
+    need_gpu()
+    import torch
+    import paper_1107_4107_amd as aw
+    from paper_1107_4107_amd import workloads
+    from gpu_util import assert_close
+    N, T = 300_000_000, 2
+    print_case("largest ensemble", N, T)
+    e = workloads.c5(n_orbits=N, T=T)
+    r = aw.map_ensemble(e, want_class=True)
+    idx = np.unique(np.concatenate([[0, N - 1], np.random.default_rng(11).choice(N, 62, replace=False)]))
+    ti = torch.as_tensor(idx, device="cuda")
+    out = r.orbit_out.index_select(1, ti).cpu().numpy()
+    cls = r.cls.index_select(0, ti).cpu().numpy()
+    ic = oracle.ic_box(e.box_lo, e.box_hi, e.seed_ic, idx=idx)
+    out_o = oracle.ensemble("s6", e.eps, H, T, ic, oracle.w0(e.seed_tangent, idx=idx))
+    # |L| and dP2 are small after two steps: the bar is 1e-9 of max(1e-3, |value|)
+    for k, name in enumerate(("L", "lambda", "chi", "Vx", "Vy", "Vz", "dP2", "J")):
+        assert_close(out[k], out_o[k], 1e-9, floor=1e-3, what=name)
+    assert np.all(np.abs(out[8] - out_o[8]) <= 1e-12), "dE"
+    far = np.abs(out_o[2] - 2.0) > 1e-6
+    np.testing.assert_array_equal(cls.astype(bool)[far], out_o[2][far] > 2.0)
+    # the histogram of every orbit's initial momenta, valued by its dP2
+    g_ic, _ = aw.generate_ic(e)
+    dp2 = r.orbit_out[6].contiguous()
+    del r
+    c, s, d = aw.histogram2d(g_ic[3].contiguous(), g_ic[4].contiguous(), dp2, (0, 0), (2 * np.pi, 2 * np.pi),
+                             512, 512)
+    total = float(dp2.sum())
+    del g_ic, dp2
+    c = np_(c).view(np.uint32)
+    assert int(np_(d)[0]) == 0 and int(c.astype(np.int64).sum()) == N
+    assert abs(float(np_(s).sum()) - total) <= 1e-9 * total
+    ic_all = oracle.ic_box(e.box_lo, e.box_hi, e.seed_ic, N)
+    co, _, do = oracle.hist2d(ic_all[3], ic_all[4], np.zeros(N), (0, 0), (2 * np.pi, 2 * np.pi), 512, 512)
+    del ic_all
+    assert do == 0
+    np.testing.assert_array_equal(c, co)
+    print(f"{N} orbits: sampled outputs, classes and the 512 x 512 histogram agree", flush=True)
