@@ -354,3 +354,58 @@ def test_graph_create_refuses_bad_requests_on_the_host():
         assert st == status, (st, status)
         assert out.value is None
         assert lib.aw_last_error()
+
+
+def test_accumulation_chunks_fit_the_scratch(tmp_path):
+    """The histogram accumulation's chunk size and the scratch bound it is
+    sized by (aw_hist.hpp), compiled for the host: the chunk is a multiple
+    of 4096 of at least 16384 items; ceil(N / chunk) never exceeds
+    acc_bound(N, T), which never decreases with N (scratch sized for the
+    largest ensemble of a call serves the smaller ones); and for tile
+    populations from uniform to a single crowded tile, the chunks (one at
+    least per tile) and the partial tiles of tiles of several chunks fit
+    T + ceil(N / chunk) and 2 ceil(N / chunk)."""
+    src = tmp_path / "chunks.cpp"
+    src.write_text(r"""
+#include <cstdio>
+#include <cstdint>
+#include <vector>
+#include "aw_hist.hpp"
+using namespace aw;
+static int64_t nch(int64_t c, int64_t ch) { return c == 0 ? 1 : (c + ch - 1) / ch; }
+int main() {
+  const int64_t Ts[] = {1, 2, 6, 8, 64, 192, 256, 1024, 4096, 8192};
+  uint64_t s = 12345;
+  auto rnd = [&]() { s = s * 6364136223846793005ull + 1442695040888963407ull; return s >> 11; };
+  for (int64_t T : Ts) {
+    int64_t prev = -1;
+    for (int64_t N = 0; N < (int64_t(1) << 31); N = N < 100000 ? N + 997 : N + N / 7 + 1) {
+      const int64_t ch = acc_chunk(N, T), b = acc_bound(N > 0 ? N : 1, T), k = (N + ch - 1) / ch;
+      if (ch < ACC_CHUNK_MIN || ch % ACC_ROUND) { printf("chunk %lld T %lld N %lld\n", (long long)ch, (long long)T, (long long)N); return 1; }
+      if (k > b) { printf("bound T %lld N %lld: %lld > %lld\n", (long long)T, (long long)N, (long long)k, (long long)b); return 1; }
+      if (b < prev) { printf("bound decreases at T %lld N %lld\n", (long long)T, (long long)N); return 1; }
+      prev = b;
+      if (T > 1024 && N > 50000000) continue;
+      for (int shape = 0; shape < 3; ++shape) {   // uniform, one crowded tile, random shares
+        std::vector<int64_t> c(T, 0);
+        if (shape == 0) for (int64_t t = 0; t < T; ++t) c[t] = N / T + (t < N % T ? 1 : 0);
+        else if (shape == 1) c[rnd() % T] = N;
+        else { int64_t left = N; for (int64_t t = 0; t + 1 < T && left > 0; ++t) { int64_t x = (int64_t)(rnd() % (uint64_t)(left + 1)); c[t] = x; left -= x; } c[T - 1] += left; }
+        int64_t chunks = 0, parts = 0;
+        for (int64_t t = 0; t < T; ++t) { const int64_t q = nch(c[t], ch); chunks += q; if (q > 1) parts += q; }
+        if (chunks > T + k || parts > 2 * k || parts > 2 * b) { printf("fit T %lld N %lld shape %d\n", (long long)T, (long long)N, shape); return 1; }
+        if (shape == 0 && N > 0 && 2 * ((N + T - 1) / T) <= (N + 255) / 256 && parts != 0) { printf("uniform split T %lld N %lld\n", (long long)T, (long long)N); return 1; }
+      }
+    }
+  }
+  printf("ok\n");
+  return 0;
+}
+""")
+    exe = tmp_path / "chunks"
+    hipcc = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
+    csrc = os.path.join(ROOT, "paper_1107_4107_amd", "csrc")
+    subprocess.run([hipcc, "-std=c++17", "-O1", "--offload-arch=gfx950", "-I", csrc, str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0 and out.stdout.strip() == "ok", out.stdout
