@@ -2,7 +2,8 @@
 cannot allocate device memory -- called through the C ABI and compared with
 aw_histogram2d on the same inputs: two calls in a row, the second with fewer
 items (so it runs over what the first left in the fixed scratch), with and
-without values.  Counts and the dropped count bit for bit; per-bin sums, whose
+without values, and with items crowding into one tile (whose range the
+accumulation splits into chunks with partial tiles in the fixed scratch).  Counts and the dropped count bit for bit; per-bin sums, whose
 float order follows LDS atomics, within 1e-12 relative (values are >= 0).
 After the first call on the device (which looks up the fixed array), the
 device's free memory is the same before and after the calls, and a request
@@ -20,12 +21,17 @@ W, H = 512, 384
 LO, HI = (0.0, -1.0), (2 * np.pi, 1.0)
 
 
-def _inputs(torch, N, seed):
+def _inputs(torch, N, seed, crowded=False):
     g = torch.Generator(device="cpu").manual_seed(seed)
     # keys spill past both ends of the ranges so that some items are dropped
     a = (torch.rand(N, generator=g, dtype=torch.float64) * 1.1 - 0.05) * (2 * np.pi)
     b = torch.rand(N, generator=g, dtype=torch.float64) * 2.2 - 1.1
     v = torch.rand(N, generator=g, dtype=torch.float64) ** 2
+    if crowded:   # 90% of the items in the 32 x 32 bins of one tile: its range splits into chunks
+        m = torch.rand(N, generator=g) < 0.9
+        k = int(m.sum())
+        a[m] = (64 + 32 * torch.rand(k, generator=g, dtype=torch.float64)) * (2 * np.pi / W)
+        b[m] = -1.0 + (96 + 32 * torch.rand(k, generator=g, dtype=torch.float64)) * (2.0 / H)
     return a.cuda(), b.cuda(), v.cuda()
 
 
@@ -44,15 +50,15 @@ def _call(torch, fn, a, b, v, out=None, closed_upper=0):
     return st, counts, sums, dropped
 
 
-@pytest.mark.parametrize("with_values", [True, False])
-def test_noalloc_histogram_matches_the_allocating_entry_point(with_values):
+@pytest.mark.parametrize("with_values,crowded", [(True, False), (False, False), (True, True)])
+def test_noalloc_histogram_matches_the_allocating_entry_point(with_values, crowded):
     need_gpu()
     import torch
     from paper_1107_4107_amd import _abi
     lib = _abi.load()
-    print_case("noalloc histogram", "values" if with_values else "counts only")
+    print_case("noalloc histogram", "values" if with_values else "counts only", "crowded" if crowded else "")
     sizes = [2_000_003, 300_001]
-    data = [_inputs(torch, N, 17 + k) for k, N in enumerate(sizes)]
+    data = [_inputs(torch, N, 17 + k, crowded) for k, N in enumerate(sizes)]
     # reference calls first: they also load every histogram kernel
     refs = []
     for a, b, v in data:
