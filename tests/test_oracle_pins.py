@@ -17,7 +17,12 @@ makes at least one of them fail:
   points of eq. 2, in closed form;
 * forward-mode derivatives of J against central finite differences;
 * histogram counts against numpy's histogram2d, and the equal-area property
-  of the direction binning.
+  of the direction binning;
+* twenty steps of S6, S4 and the standard map redone at 50 digits from the
+  definitions, the force by mpmath differentiation of the printed eq. 2 and
+  the tangent by 50-digit central differences (state and L);
+* reversibility and symplecticity on random initial states, eps, h and forms
+  drawn by hypothesis.
 """
 import json
 import os
@@ -666,3 +671,100 @@ def test_window_velocities_at_eps0(orc):
     V = orc.window_velocities("s6", 0.0, H_PAPER, ic, 4, 25)
     for w in range(4):
         np.testing.assert_allclose(V[w], ic[3:], rtol=1e-12, atol=1e-12)
+
+
+# ---------------------------------------------------------------- 50-digit re-run
+def _hp_mp(x, y, z):
+    """Eq. 2 as printed, in mpmath."""
+    return mpmath.cos(x) * mpmath.cos(y) * (1 + mpmath.cos(2 * z))
+
+
+def _stages_mp(form, h):
+    """The stage list of a form from its definition (section "Computational
+    method" and the triple jump of the appendix): S2(t) = D(t/2) K(t) D(t/2);
+    S4(t) = S2(g1 t) S2(g0 t) S2(g1 t) with g1 = 1/(2 - 2^(1/3)), g0 = 1 - 2 g1;
+    S6(t) = S4(d1 t) S4(d0 t) S4(d1 t) with d1 = 1/(2 - 2^(1/5)), d0 = 1 - 2 d1;
+    the standard map K(h) then D(h).  Adjacent drifts are not merged."""
+    if form == "stdmap":
+        return [("K", h), ("D", h)]
+    s2 = lambda t: [("D", t / 2), ("K", t), ("D", t / 2)]  # noqa: E731
+    g1 = 1 / (2 - mpmath.cbrt(2))
+    s4 = lambda t: s2(g1 * t) + s2((1 - 2 * g1) * t) + s2(g1 * t)  # noqa: E731
+    if form == "s4":
+        return s4(h)
+    d1 = 1 / (2 - mpmath.root(2, 5))
+    return s4(d1 * h) + s4((1 - 2 * d1) * h) + s4(d1 * h)
+
+
+def _map_mp(form, eps, h, T, s):
+    """T steps at 50 digits; the force is mpmath's numerical derivative of the
+    printed eq. 2 (no hand-derived gradient)."""
+    X, P = [mpmath.mpf(v) for v in s[:3]], [mpmath.mpf(v) for v in s[3:]]
+    eps = mpmath.mpf(eps)
+    stages = _stages_mp(form, mpmath.mpf(h))
+    for _ in range(T):
+        for kind, t in stages:
+            if kind == "D":
+                X = [X[i] + t * P[i] for i in range(3)]
+            else:
+                x, y, z = X
+                g = (mpmath.diff(lambda a: _hp_mp(a, y, z), x), mpmath.diff(lambda a: _hp_mp(x, a, z), y),
+                     mpmath.diff(lambda a: _hp_mp(x, y, a), z))
+                P = [P[i] - t * eps * g[i] for i in range(3)]
+    return X + P
+
+
+@pytest.mark.parametrize("form,eps", [("s6", 1.0), ("s6", 0.05), ("s4", 0.3), ("stdmap", 0.5)])
+def test_map_and_ftle_against_a_50_digit_rerun(orc, form, eps):
+    """Twenty steps of two random orbits redone at 50 digits from the
+    definitions alone: the oracle's binary64 state within 1e-13, and its
+    L = ln(|w_T| / |w_0|) within 1e-13 of the 50-digit value, whose tangent is
+    the central difference of the 50-digit map (step 1e-20, error ~1e-40), so
+    that neither the oracle's stage weights nor its Hessian are reused."""
+    mpmath.mp.dps = 50
+    try:
+        rng = np.random.default_rng(7 + int(eps * 100))
+        T = 20
+        for _ in range(2):
+            s0 = np.concatenate([rng.uniform(0, 2 * np.pi, 3), rng.uniform(-2, 2, 3)])
+            w0 = rng.normal(size=6)
+            w0 /= np.linalg.norm(w0)
+            ref = _map_mp(form, eps, H_PAPER, T, s0)
+            got = orc.map_state(form, eps, H_PAPER, T, s0)
+            for i in range(6):
+                assert abs(got[i] - float(ref[i])) <= 1e-13 * max(1.0, abs(float(ref[i]))), (form, i)
+            d = mpmath.mpf("1e-20")
+            sp = _map_mp(form, eps, H_PAPER, T, [mpmath.mpf(s0[i]) + d * mpmath.mpf(w0[i]) for i in range(6)])
+            sm = _map_mp(form, eps, H_PAPER, T, [mpmath.mpf(s0[i]) - d * mpmath.mpf(w0[i]) for i in range(6)])
+            wT = [(sp[i] - sm[i]) / (2 * d) for i in range(6)]
+            L_ref = mpmath.log(mpmath.sqrt(mpmath.fsum(v * v for v in wT)) /
+                               mpmath.sqrt(mpmath.fsum(mpmath.mpf(v) ** 2 for v in w0)))
+            out = orc.ensemble(form, eps, H_PAPER, T, s0.reshape(6, 1), w0.reshape(6, 1))
+            assert abs(out[0, 0] - float(L_ref)) <= 1e-13, (form, out[0, 0], float(L_ref))
+    finally:
+        mpmath.mp.dps = 15
+
+
+# ---------------------------------------------------------------- random-input properties
+def test_reversibility_and_symplecticity_on_random_inputs(orc):
+    """Hypothesis draws the initial state, eps, h and the form: every
+    symmetric composition satisfies S(-h) S(h) = id, and the 6x6 Jacobian of
+    ten steps of every form is symplectic (M^T Omega M = Omega)."""
+    from hypothesis import given, settings, strategies as st
+    Om = np.block([[np.zeros((3, 3)), np.eye(3)], [-np.eye(3), np.zeros((3, 3))]])
+
+    @settings(max_examples=60, deadline=None, derandomize=True)
+    @given(x=st.lists(st.floats(0.0, 2 * np.pi), min_size=3, max_size=3),
+           p=st.lists(st.floats(-3.0, 3.0), min_size=3, max_size=3),
+           eps=st.floats(0.0, 1.0), h=st.floats(0.005, 0.1),
+           form=st.sampled_from(["stdmap", "s2", "s4", "s6", "y6"]))
+    def check(x, p, eps, h, form):
+        s0 = np.array(x + p)
+        T = 10
+        if form != "stdmap":
+            back = orc.map_state(form, eps, -h, T, orc.map_state(form, eps, h, T, s0))
+            assert np.max(np.abs(back - s0)) <= 1e-12 * max(1.0, np.max(np.abs(s0)))
+        _, M = orc.jacobian(form, eps, h, T, s0)
+        assert np.max(np.abs(M.T @ Om @ M - Om)) <= 1e-10 * max(1.0, np.max(np.abs(M)) ** 2)
+
+    check()
