@@ -33,7 +33,9 @@ Other workloads (measurement records, not the default line):
   peak    the achievable FP64 rate of independent FMA chains and the shader
       clock the SIMDs sustain under that load (the probe library);
   forms   the integrators side by side on one slice (eps = 1e-2, 512 x 512,
-      pz0 = 1, T = 1e4): map-steps/s and the energy error |dE| at h and 2h.
+      pz0 = 1, T = 1e4): map-steps/s and the energy error |dE| at h and 2h;
+  energy  the energy error of S6 at the paper's h on the configurations' eps
+      and at the paper's energies E = 400 and E = 15.
 
 Prints ONE JSON line.  Single GPU only.
 """
@@ -761,6 +763,42 @@ def run_forms(args, aw, wl, torch):
     return rec, None
 
 
+def run_energy(args, aw, wl, torch):
+    """The energy error |dE| = |H(X_T, P_T) - H(X_0, P_0)| of S6 at the
+    paper's h on each configuration's eps and on the paper's two energies
+    (E = 400 on the whole sphere, Fig. 2; E = 15, Figs. 3-4): median, 99th
+    percentile and maximum over the ensemble, and the share under the
+    paper's 1e-8 (section "Computational method").  The paper's integrator
+    is not the one built here, so this is reported, not a gate."""
+    import numpy as np
+    cases = [("c2 eps=1e-3, 512^2 slice", wl.slice_ensemble(1e-3, 512, 10_000)),
+             ("c4 eps=1e-2, 512^2 slice", wl.slice_ensemble(1e-2, 512, 10_000)),
+             ("c5 eps=5e-3, 1e6 box orbits", wl.c5(n_orbits=1_000_000, T=10_000)),
+             ("Fig. 2: E=400, eps=1, whole sphere, 1e6 orbits", wl.fig2(n_orbits=1_000_000)),
+             ("Figs. 3-4: E=15, eps=1, whole sphere, 1e6 orbits", wl.sphere_ensemble(15.0, 1_000_000, wl.DT50)),
+             ("Fig. 4 cloud: E=15, eps=1, 3.2e4 orbits at W", wl.fig4_cloud(n_orbits=32_000, T=wl.DT50))]
+    rows = []
+    t_all, steps_all = 0.0, 0
+    for name, e in cases:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = aw.map_ensemble(e, want_class=False)
+        torch.cuda.synchronize()
+        t_all += time.perf_counter() - t0
+        steps_all += e.size * e.n_steps
+        dE = np.abs(r.orbit_out[aw.OUT_DE].cpu().numpy())
+        dE = dE[np.isfinite(dE)]
+        rows.append({"case": name, "n_orbits": int(e.size), "n_steps": int(e.n_steps), "eps": e.eps,
+                     "dE_median": float(np.median(dE)), "dE_p99": float(np.quantile(dE, 0.99)),
+                     "dE_max": float(dE.max()), "share_below_1e-8": float(np.mean(dE < 1e-8))})
+        log(f"{name}: |dE| median {rows[-1]['dE_median']:.3e}, p99 {rows[-1]['dE_p99']:.3e}, "
+            f"max {rows[-1]['dE_max']:.3e}, {100 * rows[-1]['share_below_1e-8']:.2f}% under 1e-8")
+    rec = base_record(steps_all / t_all, 1, 1, t_all * 1e3)
+    rec["config"] = {"workload": "energy error of S6 at h = 0.01 T on the configurations' eps and at E = 15, 400"}
+    rec["energy"] = rows
+    return rec, None
+
+
 def run_sweep(args, aw, wl, torch):
     """Chaotic fraction (chi > 2) against eps on the literal slice and on the
     pz0 = 1 companion (256 x 256, T = 3e4, 16 eps values), each slice as one
@@ -801,7 +839,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "fig2", "fig3", "fig4", "sweep",
-                                                             "nsweep", "peak", "forms"])
+                                                             "nsweep", "peak", "forms", "energy"])
     ap.add_argument("--windows", type=int, default=200, help="fig4: number of 50 T windows")
     ap.add_argument("--t-scale", type=float, default=1.0, help="c3/c5: scale the horizons")
     ap.add_argument("--n-orbits", type=int, default=10_000_000, help="c5: ensemble size")
@@ -848,7 +886,8 @@ def main():
         del src, dst
     runner = {"c1": run_slice, "c2": run_slice, "c3": run_batched, "c4": run_adjoint, "c5": run_large,
               "fig2": run_sphere, "fig3": run_sphere, "fig4": run_diffusion, "sweep": run_sweep,
-              "nsweep": run_nsweep, "peak": run_peak, "forms": run_forms}
+              "nsweep": run_nsweep, "peak": run_peak, "forms": run_forms,
+              "energy": run_energy}
     rec, ens = runner[args.workload](args, aw, wl, torch)
     if args.workload == "c2" and not args.no_c5_chunk:
         rec["c5_chunk"] = run_c5_chunk(aw, wl, torch)
