@@ -766,17 +766,22 @@ def run_forms(args, aw, wl, torch):
 def run_energy(args, aw, wl, torch):
     """The energy error |dE| = |H(X_T, P_T) - H(X_0, P_0)| of S6 at the
     paper's h on each configuration's eps and on the paper's two energies
-    (E = 400 on the whole sphere, Fig. 2; E = 15, Figs. 3-4): median, 99th
-    percentile and maximum over the ensemble, and the share under the
-    paper's 1e-8 (section "Computational method").  The paper's integrator
-    is not the one built here, so this is reported, not a gate."""
+    (E = 400 on the whole sphere, Fig. 2; E = 15, Figs. 3-4), and at E = 15
+    also S6 at h/2 and Y6 at h: median, 99th percentile and maximum over the
+    ensemble, and the share under the paper's 1e-8 (section "Computational
+    method").  The paper's integrator is not the one built here, so this is
+    reported, not a gate."""
     import numpy as np
     cases = [("c2 eps=1e-3, 512^2 slice", wl.slice_ensemble(1e-3, 512, 10_000)),
              ("c4 eps=1e-2, 512^2 slice", wl.slice_ensemble(1e-2, 512, 10_000)),
              ("c5 eps=5e-3, 1e6 box orbits", wl.c5(n_orbits=1_000_000, T=10_000)),
              ("Fig. 2: E=400, eps=1, whole sphere, 1e6 orbits", wl.fig2(n_orbits=1_000_000)),
              ("Figs. 3-4: E=15, eps=1, whole sphere, 1e6 orbits", wl.sphere_ensemble(15.0, 1_000_000, wl.DT50)),
-             ("Fig. 4 cloud: E=15, eps=1, 3.2e4 orbits at W", wl.fig4_cloud(n_orbits=32_000, T=wl.DT50))]
+             ("Fig. 4 cloud: E=15, eps=1, 3.2e4 orbits at W", wl.fig4_cloud(n_orbits=32_000, T=wl.DT50)),
+             ("Figs. 3-4 at h/2 (same time span)",
+              dataclasses.replace(wl.sphere_ensemble(15.0, 1_000_000, 2 * wl.DT50), h=aw.H_PAPER / 2)),
+             ("Figs. 3-4 with Y6 at h", dataclasses.replace(wl.sphere_ensemble(15.0, 1_000_000, wl.DT50),
+                                                            map_form="y6"))]
     rows = []
     t_all, steps_all = 0.0, 0
     for name, e in cases:
@@ -794,7 +799,8 @@ def run_energy(args, aw, wl, torch):
         log(f"{name}: |dE| median {rows[-1]['dE_median']:.3e}, p99 {rows[-1]['dE_p99']:.3e}, "
             f"max {rows[-1]['dE_max']:.3e}, {100 * rows[-1]['share_below_1e-8']:.2f}% under 1e-8")
     rec = base_record(steps_all / t_all, 1, 1, t_all * 1e3)
-    rec["config"] = {"workload": "energy error of S6 at h = 0.01 T on the configurations' eps and at E = 15, 400"}
+    rec["config"] = {"workload": "energy error of S6 at h = 0.01 T on the configurations' eps and at E = 15, 400; "
+                                 "at E = 15 also S6 at h/2 and Y6"}
     rec["energy"] = rows
     return rec, None
 
