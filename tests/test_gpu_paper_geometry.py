@@ -98,7 +98,12 @@ def test_fig2_web_structure(aw):
     the uniform initial density stays uniform almost everywhere (regular
     motion keeps V near P(0)), and the primary resonances m = (1, -1, 0) and
     (1, 1, 0), i.e. Vx = Vy (phi = pi/4, -3 pi/4) and Vx = -Vy (phi = -pi/4,
-    3 pi/4), show as bright lines with a dark zone beside them."""
+    3 pi/4), show as bright lines with a dark zone beside them.  So do the
+    other primary resonances of eq. 2's Fourier form, m = (1, +-1, +-2): on
+    the sphere m . V = 0 is the circle mu = -s2 c / sqrt(4 + c^2) with
+    c = cos phi + s1 sin phi, and the bins it crosses hold at least twice the
+    median count (away from the (1, +-1, 0) lines and from mu = 0, where the
+    circles meet)."""
     print_case("fig 2 structure")
     from paper_1107_4107_amd import workloads as wl
     N = 2_000_000
@@ -123,6 +128,18 @@ def test_fig2_web_structure(aw):
               f"side min / median = {prof[ring].min() / med:.3f}", flush=True)
         assert prof[near].max() > 1.3 * med
         assert prof[ring].min() < 0.9 * med
+    cmed = np.median(c)
+    far_from_lines = np.min([np.abs((phi - c0 + math.pi) % (2 * math.pi) - math.pi)
+                             for c0 in (math.pi / 4, -3 * math.pi / 4, -math.pi / 4, 3 * math.pi / 4)], axis=0) > 0.15
+    for s1 in (1, -1):
+        for s2 in (1, -1):
+            cc = np.cos(phi) + s1 * np.sin(phi)
+            mu_r = -s2 * cc / np.sqrt(4 + cc * cc)
+            cols = far_from_lines & (np.abs(mu_r) > 0.1)
+            on = (np.abs(mu_c[:, None] - mu_r[None, :]) < 1.5 / 256) & cols[None, :]
+            ratio = c[on].mean() / cmed
+            print(f"resonance m=(1,{s1:+d},{2 * s2:+d}): mean count on the circle / median = {ratio:.3f}", flush=True)
+            assert ratio > 2.0
 
 
 def _cloud(aw, n, T):
