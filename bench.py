@@ -573,8 +573,9 @@ def run_sphere(args, aw, wl, torch):
     """The paper's Fig. 2 experiment (section "Main results"): eps = 1,
     E = 400, N = 1e8 orbits with the direction of P uniform on the momentum
     sphere and X uniform on the torus, propagated for Delta t = 50 T (5000
-    steps), reduced to the density F of the direction of V (1024 x 512).  The
-    paper propagates the state only, so the tangent is off here (the metric of
+    steps; --t-scale 2 gives the paper's other window, 100 T), reduced to the
+    density F of the direction of V (1024 x 512).  The paper propagates the
+    state only, so the tangent is off here (the metric of
     this record is map-steps/s without the tangent).  fig3: E = 15, a zoom
     window with the stay-in-area selection."""
     if args.workload == "fig2":
@@ -583,6 +584,7 @@ def run_sphere(args, aw, wl, torch):
     else:
         e = wl.fig3_zoom(n_orbits=args.n_orbits if args.n_orbits != 10_000_000 else 20_000_000)
         spec = wl.sphere_image(512, 512, e.window)
+    e = dataclasses.replace(e, n_steps=max(1, int(round(e.n_steps * args.t_scale))))   # 2: Delta t = 100 T
     N, T = e.size, e.n_steps
     small = dataclasses.replace(e, n_steps=10, n_orbits=min(N, 1_000_000))
     aw.indicator_image(small, spec)
@@ -847,7 +849,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "fig2", "fig3", "fig4", "sweep",
                                                              "nsweep", "peak", "forms", "energy"])
     ap.add_argument("--windows", type=int, default=200, help="fig4: number of 50 T windows")
-    ap.add_argument("--t-scale", type=float, default=1.0, help="c3/c5: scale the horizons")
+    ap.add_argument("--t-scale", type=float, default=1.0,
+                    help="c3/c5/fig2/fig3: scale the horizons (fig2, fig3: 2 gives Delta t = 100 T)")
     ap.add_argument("--n-orbits", type=int, default=10_000_000, help="c5: ensemble size")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
